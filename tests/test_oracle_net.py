@@ -1,0 +1,98 @@
+"""Pins for oracle.net: digital nets (Definition and Eq. (defy)) and t-values."""
+import itertools
+
+import numpy as np
+import pytest
+
+from oracle import net
+from paper_0808_0487_amd import inputs
+
+
+def radical_inverse_digits_reversed(p, m, n):
+    """van der Corput: the base-p digit string of n, written in reverse after
+    the radix point, read as an m-digit integer (textbook construction via
+    numpy's base representation, independent of any matrix product)."""
+    s = np.base_repr(n, base=p).rjust(m, "0")
+    return int(s[::-1], p)
+
+
+@pytest.mark.parametrize("p,m", [(2, 6), (3, 4), (5, 3)])
+def test_identity_generator_is_van_der_corput(p, m):
+    C = inputs.identity_generators(p, m, 1)
+    X = net.net_int(p, m, C)
+    ref = [radical_inverse_digits_reversed(p, m, n) for n in range(p ** m)]
+    assert X[0].tolist() == ref
+
+
+@pytest.mark.parametrize("p,m", [(2, 5), (3, 3), (5, 2)])
+def test_anti_identity_gives_hammersley_and_t0(p, m):
+    """C_1 = I, C_2 = anti-identity: x_2 = n / p^m, the Hammersley set, a
+    (0, m, 2)-net (textbook)."""
+    C = np.stack([np.eye(m, dtype=np.uint8), np.eye(m, dtype=np.uint8)[::-1]])
+    X = net.net_int(p, m, C)
+    assert X[1].tolist() == list(range(p ** m))
+    assert net.t_value(p, m, C) == 0
+    assert net.t_value_geometric(p, m, X) == 0
+
+
+@pytest.mark.parametrize("p,m,s,seed", [(2, 8, 3, 1), (3, 5, 3, 2), (5, 3, 4, 3)])
+def test_nonsingular_coordinates_are_permutations(p, m, s, seed):
+    C = inputs.upper_triangular_generators(p, m, s, seed)
+    X = net.net_int(p, m, C)
+    for j in range(s):
+        assert sorted(X[j].tolist()) == list(range(p ** m))
+
+
+@pytest.mark.parametrize("p,m,s,seed", [(2, 7, 2, 4), (3, 4, 3, 5)])
+def test_net_is_a_group_under_digitwise_subtraction(p, m, s, seed):
+    """x_n (-) x_v = x_{n (-) v}: the map n -> X is Z_p-linear (Section 3.3)."""
+    C = inputs.upper_triangular_generators(p, m, s, seed)
+    X = net.net_int(p, m, C)
+    g = np.random.default_rng(seed)
+    nd = lambda v: np.array([(v // p ** i) % p for i in range(m)])
+    todigit = lambda d: int(sum(int(d[i]) * p ** i for i in range(m)))
+    for _ in range(50):
+        a, b = (int(t) for t in g.integers(0, p ** m, 2))
+        diff = todigit((nd(a) - nd(b)) % p)
+        for j in range(s):
+            xa = nd(int(X[j, a]))
+            xb = nd(int(X[j, b]))
+            assert todigit((xa - xb) % p) == int(X[j, diff])
+
+
+def test_output_digit_matvec_small_bruteforce():
+    """y = C n over Z_p against a scalar triple loop."""
+    p, m = 3, 4
+    C = inputs.random_generators(p, m, 2, 11).astype(np.int64)
+    y = net.output_digits(p, m, C, np.arange(p ** m))
+    for n in range(p ** m):
+        nd = [(n // p ** i) % p for i in range(m)]
+        for j in range(2):
+            for r in range(m):
+                acc = 0
+                for c in range(m):
+                    acc += int(C[j, r, c]) * nd[c]
+                assert y[j, n, r] == acc % p
+
+
+@pytest.mark.parametrize("p,m,s", [(2, 3, 2), (2, 4, 3), (3, 2, 2), (3, 3, 2), (5, 2, 2)])
+def test_rank_t_value_equals_geometric_t_value(p, m, s):
+    """The rank condition after the Definition gives the same t as exhaustive
+    counting of points in elementary intervals, for seeded random (also
+    singular) generators."""
+    for seed in range(6):
+        C = inputs.random_generators(p, m, s, 100 + seed)
+        X = net.net_int(p, m, C)
+        assert net.t_value(p, m, C) == net.t_value_geometric(p, m, X)
+
+
+def test_every_one_dimensional_binary_net_t_value():
+    """s = 1, p = 2, m = 2: all 16 matrices; t = 0 exactly for non-singular
+    ones, and t equals m - rank of the leading-row system otherwise."""
+    for Cm in net.all_generators(2, 2):
+        C = Cm[None]
+        X = net.net_int(2, 2, C)
+        t = net.t_value(2, 2, C)
+        assert t == net.t_value_geometric(2, 2, X)
+        if net.rank_mod_p(Cm, 2) == 2:
+            assert t == 0
