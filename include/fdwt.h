@@ -1,0 +1,194 @@
+/*
+ * fdwt.h -- C ABI of libfdwt: fast discrete Walsh transforms on digital nets
+ * over Z_p, native on AMD MI355X (gfx950).
+ *
+ * Method: K.-I. Liu, J. Dick, F. J. Hickernell, "A Multivariate Fast Discrete
+ * Walsh Transform with an Application to Function Interpolation".
+ *
+ * Conventions used by every call
+ *   - p in {2, 3, 5}; m >= 1; N = p^m <= 2^26 points; 1 <= s <= 64.
+ *   - Point index n = n_0 + n_1 p + ... + n_{m-1} p^{m-1} (digit vector
+ *     n_vec least significant first).  Coefficient index h = h_0 + h_1 p + ...
+ *     where h_vec = C . k is the label of the coset of wavenumber k
+ *     (Section 2.1); the transform leaves coefficient k at position h, as in
+ *     Algorithm 1 (no digit reversal).
+ *   - Buffers named *_dev are device pointers (hipMalloc'd or torch CUDA
+ *     tensors on the current device), owned by the caller; *_host pointers
+ *     are host memory owned by the caller.  Coordinate-major layouts are
+ *     [s][N] (all N values of coordinate 1, then coordinate 2, ...).
+ *   - stream is a hipStream_t (NULL = the null stream).  Calls enqueue work
+ *     on it and return without waiting, except fdwt_eff_dim, which returns
+ *     its scalars to the host and therefore synchronises the stream.
+ *   - Calls made with one net handle must be ordered on one stream (or
+ *     synchronised by the caller): the handle owns a workspace they share.
+ *   - Errors: every int-returning call returns FDWT_OK (0) or a negative
+ *     code; fdwt_last_error() gives a message for the calling thread.  No
+ *     exception crosses the ABI.  Invalid arguments are rejected before any
+ *     work is enqueued.
+ */
+#ifndef FDWT_H
+#define FDWT_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define FDWT_OK            0
+#define FDWT_EINVAL       -1   /* bad argument (p, m, s, sizes, types, NULL)  */
+#define FDWT_ENOMEM       -2   /* device or host allocation failed            */
+#define FDWT_EDEVICE      -3   /* a HIP runtime call failed                   */
+#define FDWT_EBUDGET      -4   /* request exceeds a configured memory budget  */
+#define FDWT_EUNSUPPORTED -5   /* valid math, not supported here (e.g. p = 7) */
+
+/* Element types of transform inputs and outputs. */
+#define FDWT_F32  1   /* float                                               */
+#define FDWT_I32  2   /* int32, arithmetic modulo 2^32 (p = 2 only)          */
+#define FDWT_CF32 3   /* complex float, interleaved (re, im)                 */
+
+typedef struct fdwt_net fdwt_net;
+
+/* ------------------------------------------------------------------ nets */
+
+/* Build the digital (t,m,s)-net P(C) of Section 1 (Definition of a digital
+ * net, Eq. (defy)): x_{j,n} = sum_r y_{j,n,r} p^-r with y_vec = C_j n_vec over
+ * Z_p.  C_host is uint8 [s][m][m]: C_host[(j*m + r)*m + c] is the entry of
+ * C_{j+1} in row r+1 (output digit y_{r+1}, weight p^-(r+1)) and column c
+ * (input digit n_c).  Entries must be < p; singular matrices are allowed.
+ * The handle copies what it needs from C_host (caller keeps ownership) and
+ * owns device tables and a workspace; free it with fdwt_net_free.  The
+ * current HIP device at this call is the device of every later call.
+ * Errors: FDWT_EINVAL (p not prime, m < 1, p^m > 2^26, s outside 1..64,
+ * entry >= p, NULL), FDWT_EUNSUPPORTED (prime p other than 2, 3, 5),
+ * FDWT_ENOMEM, FDWT_EDEVICE. */
+int fdwt_net_generate(int p, int m, int s, const uint8_t* C_host, fdwt_net** out);
+
+/* p, m, s and N = p^m of a net (any pointer may be NULL). */
+int fdwt_net_info(const fdwt_net* net, int* p, int* m, int* s, int64_t* n_points);
+
+/* Integer coordinates X_{j,n} = sum_r y_{j,n,r} p^{m-r} (so x = X p^-m) into
+ * X_dev uint32 [s][N].  Bit-exact. */
+int fdwt_net_digits(const fdwt_net* net, uint32_t* X_dev, void* stream);
+
+/* Points x_{j,n} = X_{j,n} p^-m as float into x_dev [s][N] (exact for p = 2
+ * and m <= 24, otherwise within 1.5 ulp). */
+int fdwt_net_points(const fdwt_net* net, float* x_dev, void* stream);
+
+void fdwt_net_free(fdwt_net* net);
+
+/* ------------------------------------------------------------ sampling */
+
+#define FDWT_FAMILY_PRODUCT  1   /* f = prod_j (1 + a_j (x_j - 1/2))              */
+#define FDWT_FAMILY_EXP      2   /* f = exp(-sum_j a_j x_j^2)                     */
+#define FDWT_FAMILY_WANGFANG 3   /* f = prod_j (|4 x_j - 2| + a_j)/(1 + a_j),
+                                    the test function of Section 5.2              */
+
+/* Sample a test function at the net: f_dev[n] = f(x_n), float [N], computed
+ * on the device from the net (the points are not materialised).  a_host is
+ * double [s] (read during the call).  Values are evaluated in float. */
+int fdwt_sample(const fdwt_net* net, int family, const double* a_host, float* f_dev, void* stream);
+
+/* ----------------------------------------------------------- transforms */
+
+/* Forward discrete Walsh transform, Algorithm 1 (Section 2.2), i.e. the
+ * coefficients of Eq. (eq_dwalshcoeff):
+ *     out[h] = p^-m sum_n in[n] omega_p^(-n_vec . h_vec).
+ * Allowed (in_type -> out_type):
+ *     p = 2:  F32 -> F32 (normalised as above);
+ *             I32 -> I32 (NOT normalised: out = p^m times the coefficient,
+ *                         exact modulo 2^32);
+ *     p odd:  F32 -> CF32, CF32 -> CF32 (normalised).
+ * in_dev and out_dev may be the same buffer when both types have the same
+ * size.  Sizes: N elements each. */
+int fdwt_dwt_forward(const fdwt_net* net, int in_type, const void* in_dev,
+                     int out_type, void* out_dev, void* stream);
+
+/* Inverse transform, Algorithm 2 (Section 3.3), the Lemma's sum:
+ *     out[n] = sum_h in[h] omega_p^(+n_vec . h_vec)   (no normalisation).
+ * Allowed: p = 2: F32 -> F32, I32 -> I32 (mod 2^32); p odd: CF32 -> CF32, and
+ * CF32 -> F32, which returns the real part (exact result when the input is
+ * the transform of real data).  In place allowed for equal sizes. */
+int fdwt_dwt_inverse(const fdwt_net* net, int in_type, const void* in_dev,
+                     int out_type, void* out_dev, void* stream);
+
+/* ------------------------------------------------------- spline kernel */
+
+/* Weighted Walsh kernel of Section 4: K(x,y) = prod_j [1 + gamma_j K'(x_j (-) y_j, 0)]
+ * with K'(z,0) = 1 - p^(i(1-alpha)) (p^alpha - 1)/(p - 1), i the index of the
+ * first non-zero base-p digit of z (K'(0,0) = 1).  alpha > 1, gamma_j > 0,
+ * s must equal the net's s; gamma is host memory read during the call. */
+typedef struct {
+  double alpha;
+  const double* gamma;
+  int s;
+} fdwt_kernel;
+
+/* Query depth D: queries are D-digit base-p integers Q, q = Q p^-D, with
+ * D = 32 (p = 2), 20 (p = 3), 13 (p = 5). */
+int fdwt_query_depth(int p);
+
+/* Spline coefficients (Section 3.2, Eq. (splinecoef), then Algorithm 2):
+ *     c~(h) = ft(h) / (p^m K~(h)),  c = inverse DWT of c~,
+ * where ft is the forward transform of the data (dwt_forward output: F32 for
+ * p = 2, CF32 for p odd) and K~ the DWT of the kernel data (K(x_n, 0))_n,
+ * computed on the device in double-float (about 48-bit) precision.  c_dev is
+ * float [N]: the c_n with Sf = sum_n c_n K(., x_n) interpolating the data. */
+int fdwt_spline_coef(const fdwt_net* net, const fdwt_kernel* kern, int ft_type,
+                     const void* ft_dev, float* c_dev, void* stream);
+
+/* Evaluate Sf(q) = sum_n c_n K(q, x_n) (Section 3.2) at nq queries.  q_dev
+ * is uint32 [s][nq] of D-digit integers (see fdwt_query_depth); sf_dev is
+ * float [nq].  Partial sums over point blocks are combined in a fixed order
+ * (deterministic). */
+int fdwt_spline_eval(const fdwt_net* net, const fdwt_kernel* kern, const float* c_dev,
+                     int64_t nq, const uint32_t* q_dev, float* sf_dev, void* stream);
+
+/* Whole interpolation: forward DWT of f_dev (float [N] at the net points),
+ * spline coefficients (into c_dev if non-NULL, float [N]) and, when nq > 0,
+ * Sf at the queries into sf_dev. */
+int fdwt_walsh_interp(const fdwt_net* net, const fdwt_kernel* kern, const float* f_dev,
+                      float* c_dev, int64_t nq, const uint32_t* q_dev, float* sf_dev,
+                      void* stream);
+
+/* ------------------------------------------------- effective dimension */
+
+/* ANOVA variances of the spline and effective dimensions (Section 4):
+ *   var_trc[d] = sigma^2_trc(Sf; d) = p^2m sum_h |c~(h)|^2 (R_d - 1)~(h),
+ *                R_d = prod_{j<=d} (1 + gamma_j^2 R'(x_j, 0)),
+ *   var_sup[d] = sigma^2_sup(Sf; d) = sum_{j<=d} p^2m sum_h |c~(h)|^2 Q~_j(h),
+ *                Q_j = j-th elementary symmetric polynomial of the
+ *                gamma_l^2 R'(x_l, 0),
+ * for d = 0..s (index 0 holds 0), var_total = var_trc[s] = sigma^2(Sf)
+ * (Eq. (varSf), with the h = 0 bin included), var_total_h0 = the h = 0
+ * bin's share of it, var_qmc = sum_{h != 0} |ft(h)|^2 (the sample variance
+ * of the data), d_trc / d_sup = smallest d with var_*[d] >= 0.99 var_total.
+ * The kernel spectra are computed in double-float; the grouped sums over h
+ * are accumulated in float64 in a fixed order.  var_trc and var_sup are
+ * caller-owned host arrays of s+1 doubles. */
+typedef struct {
+  double* var_trc;
+  double* var_sup;
+  double var_total;
+  double var_total_h0;
+  double var_qmc;
+  int d_trc;
+  int d_sup;
+} fdwt_effdim;
+
+/* ft_dev: the forward transform of the data (F32 for p = 2, CF32 for p odd).
+ * Synchronises stream before returning. */
+int fdwt_eff_dim(const fdwt_net* net, const fdwt_kernel* kern, int ft_type,
+                 const void* ft_dev, fdwt_effdim* out, void* stream);
+
+/* ------------------------------------------------------------ errors */
+
+/* Message of the last failed call on this thread ("" if none).  The pointer
+ * stays valid until the next fdwt_* call on the thread. */
+const char* fdwt_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* FDWT_H */

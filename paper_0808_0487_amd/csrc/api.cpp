@@ -1,0 +1,406 @@
+// C ABI of libfdwt: argument validation, net handles, workspace ownership and
+// dispatch to the HIP kernels.  Every entry point returns a status code and
+// never lets an exception escape.
+#include <cmath>
+#include <cstring>
+#include <exception>
+#include <new>
+
+#include "fdwt_internal.h"
+
+namespace fdwt {
+
+static thread_local std::string g_err;
+
+void set_error(int code, const std::string& msg) {
+  (void)code;
+  g_err = msg;
+}
+int fail(int code, const std::string& msg) {
+  set_error(code, msg);
+  return code;
+}
+
+int64_t ipow(int64_t b, int e) {
+  int64_t r = 1;
+  for (int i = 0; i < e; ++i) r *= b;
+  return r;
+}
+
+int query_depth(int p) { return p == 2 ? 32 : (p == 3 ? 20 : (p == 5 ? 13 : 0)); }
+
+// K'(z,0) and R'(z,0) of Section 4 for z whose first non-zero base-p digit is
+// digit i (i = 0: z = 0).
+double kprime(int p, double alpha, int i) {
+  if (i == 0) return 1.0;
+  return 1.0 - std::pow((double)p, i * (1.0 - alpha)) * (std::pow((double)p, alpha) - 1.0) / (p - 1.0);
+}
+double rprime(int p, double alpha, int i) {
+  const double pa = std::pow((double)p, alpha), p2a = std::pow((double)p, 2.0 * alpha);
+  const double A = (pa - p) * (pa - p) / ((p - 1.0) * (p2a - p));
+  if (i == 0) return A;
+  return A * (1.0 - std::pow((double)p, i * (1.0 - 2.0 * alpha)) * (p2a - 1.0) / (p - 1.0));
+}
+
+int ensure_ws(Net& net, size_t bytes, hipStream_t st) {
+  if (net.ws_bytes >= bytes) return FDWT_OK;
+  if (net.ws) {
+    FDWT_HIP(hipStreamSynchronize(st));
+    FDWT_HIP(hipFree(net.ws));
+    net.ws = nullptr;
+    net.ws_bytes = 0;
+  }
+  void* p = nullptr;
+  if (hipMalloc(&p, bytes) != hipSuccess) {
+    (void)hipGetLastError();
+    return fail(FDWT_ENOMEM, "workspace allocation of " + std::to_string(bytes) + " bytes failed");
+  }
+  net.ws = p;
+  net.ws_bytes = bytes;
+  return FDWT_OK;
+}
+
+int pin_acquire(Net& net) {
+  if (net.pin_done) FDWT_HIP(hipEventSynchronize(net.pin_done));
+  return FDWT_OK;
+}
+int pin_release(Net& net, hipStream_t st) {
+  if (!net.pin_done) FDWT_HIP(hipEventCreateWithFlags(&net.pin_done, hipEventDisableTiming));
+  FDWT_HIP(hipEventRecord(net.pin_done, st));
+  return FDWT_OK;
+}
+int ensure_pin(Net& net, size_t bytes) {
+  int rc = pin_acquire(net);
+  if (rc) return rc;
+  if (net.pin_bytes >= bytes) return FDWT_OK;
+  if (net.pin) FDWT_HIP(hipHostFree(net.pin));
+  net.pin = nullptr;
+  net.pin_bytes = 0;
+  void* p = nullptr;
+  if (hipHostMalloc(&p, bytes, hipHostMallocDefault) != hipSuccess) {
+    (void)hipGetLastError();
+    return fail(FDWT_ENOMEM, "pinned staging allocation failed");
+  }
+  net.pin = p;
+  net.pin_bytes = bytes;
+  return FDWT_OK;
+}
+
+// Makes the net's device current for the duration of a call.
+struct DeviceGuard {
+  int prev = -1;
+  bool ok = true;
+  explicit DeviceGuard(int dev) {
+    if (hipGetDevice(&prev) != hipSuccess) prev = -1;
+    if (prev != dev && hipSetDevice(dev) != hipSuccess) ok = false;
+  }
+  ~DeviceGuard() {
+    if (prev >= 0) (void)hipSetDevice(prev);
+  }
+};
+
+static bool is_prime(int p) {
+  if (p < 2) return false;
+  for (int d = 2; d * d <= p; ++d)
+    if (p % d == 0) return false;
+  return true;
+}
+
+static int check_net(const fdwt_net* h) {
+  if (!h) return fail(FDWT_EINVAL, "net handle is NULL");
+  return FDWT_OK;
+}
+
+static int check_kernel(const Net& net, const fdwt_kernel* k) {
+  if (!k || !k->gamma) return fail(FDWT_EINVAL, "kernel or its gamma is NULL");
+  if (k->s != net.s) return fail(FDWT_EINVAL, "kernel s differs from the net's s");
+  if (!(k->alpha > 1.0) || !std::isfinite(k->alpha)) return fail(FDWT_EINVAL, "alpha must be > 1");
+  for (int j = 0; j < k->s; ++j)
+    if (!(k->gamma[j] > 0.0) || !std::isfinite(k->gamma[j]))
+      return fail(FDWT_EINVAL, "gamma_j must be positive and finite");
+  return FDWT_OK;
+}
+
+static Kind to_kind(int t) {
+  switch (t) {
+    case FDWT_F32: return K_F32;
+    case FDWT_I32: return K_U32;
+    case FDWT_CF32: return K_CF32;
+  }
+  return (Kind)-1;
+}
+
+int fwt_run_tmp(int p, int m, bool inverse, Kind in_kind, const void* in, Kind work_kind,
+                Kind out_kind, void* out, void* tmp, int batch, float scale, hipStream_t st);
+
+static int transform(Net& net, bool inverse, int in_type, const void* in, int out_type, void* out,
+                     hipStream_t st) {
+  if (!in || !out) return fail(FDWT_EINVAL, "NULL data pointer");
+  Kind ik = to_kind(in_type), ok = to_kind(out_type), wk;
+  if ((int)ik < 0 || (int)ok < 0) return fail(FDWT_EINVAL, "unknown element type");
+  if (net.p == 2) {
+    if (!((ik == K_F32 && ok == K_F32) || (ik == K_U32 && ok == K_U32)))
+      return fail(FDWT_EINVAL, "p = 2 transforms are F32 -> F32 or I32 -> I32");
+    wk = ik;
+  } else {
+    const bool okf = inverse ? (ik == K_CF32 && (ok == K_CF32 || ok == K_F32))
+                             : ((ik == K_F32 || ik == K_CF32) && ok == K_CF32);
+    if (!okf)
+      return fail(FDWT_EINVAL, inverse ? "odd-p inverse takes CF32 to CF32 or F32"
+                                       : "odd-p forward takes F32 or CF32 to CF32");
+    wk = K_CF32;
+  }
+  if (in == out && kind_bytes(ik) != kind_bytes(ok))
+    return fail(FDWT_EINVAL, "in-place transform needs equal input and output element sizes");
+  void* tmp = nullptr;
+  if (kind_bytes(ok) < kind_bytes(wk)) {
+    int rc = ensure_ws(net, (size_t)net.N * kind_bytes(wk), st);
+    if (rc) return rc;
+    tmp = net.ws;
+  }
+  const float scale =
+      (!inverse && wk != K_U32) ? (float)(1.0 / (double)net.N) : 1.0f;  // Eq. (eq_dwalshcoeff)
+  return fwt_run_tmp(net.p, net.m, inverse, ik, in, wk, ok, out, tmp, 1, scale, st);
+}
+
+}  // namespace fdwt
+
+using namespace fdwt;
+
+#define FDWT_GUARD_BEGIN try {
+#define FDWT_GUARD_END                                                        \
+  }                                                                           \
+  catch (const std::bad_alloc&) {                                             \
+    return fail(FDWT_ENOMEM, "host allocation failed");                       \
+  }                                                                           \
+  catch (const std::exception& e) {                                           \
+    return fail(FDWT_EDEVICE, std::string("internal error: ") + e.what());    \
+  }                                                                           \
+  catch (...) {                                                               \
+    return fail(FDWT_EDEVICE, "internal error");                              \
+  }
+
+extern "C" {
+
+const char* fdwt_last_error(void) { return g_err.c_str(); }
+
+int fdwt_query_depth(int p) { return query_depth(p); }
+
+int fdwt_net_generate(int p, int m, int s, const uint8_t* C_host, fdwt_net** out) {
+  FDWT_GUARD_BEGIN
+  g_err.clear();
+  if (!out || !C_host) return fail(FDWT_EINVAL, "NULL argument");
+  *out = nullptr;
+  if (!is_prime(p)) return fail(FDWT_EINVAL, "p must be prime");
+  if (p != 2 && p != 3 && p != 5) return fail(FDWT_EUNSUPPORTED, "only p = 2, 3, 5 are supported");
+  if (m < 1) return fail(FDWT_EINVAL, "m must be >= 1");
+  if (s < 1 || s > kMaxS) return fail(FDWT_EINVAL, "s must be in 1..64");
+  if (ipow(p, m) > (int64_t(1) << kMaxLog2N)) return fail(FDWT_EINVAL, "p^m must be <= 2^26");
+  for (int64_t i = 0; i < (int64_t)s * m * m; ++i)
+    if (C_host[i] >= p) return fail(FDWT_EINVAL, "generator entry >= p");
+  auto* h = new fdwt_net();
+  Net& net = h->n;
+  net.p = p;
+  net.m = m;
+  net.s = s;
+  net.N = ipow(p, m);
+  if (hipGetDevice(&net.device) != hipSuccess) {
+    delete h;
+    return fail(FDWT_EDEVICE, "no HIP device");
+  }
+  auto C = [&](int j, int r, int c) { return (int)C_host[((int64_t)j * m + r) * m + c]; };
+  if (p == 2) {
+    // Column c of C_j as an m-bit integer (row r -> bit m-1-r); per byte b of n,
+    // the XOR of the columns selected by each byte value.
+    net.nbytes = (m + 7) / 8;
+    std::vector<uint32_t> tab((size_t)s * net.nbytes * 256, 0);
+    for (int j = 0; j < s; ++j) {
+      uint32_t col[32] = {0};
+      for (int c = 0; c < m; ++c)
+        for (int r = 0; r < m; ++r)
+          if (C(j, r, c) & 1) col[c] |= 1u << (m - 1 - r);
+      for (int b = 0; b < net.nbytes; ++b)
+        for (int v = 0; v < 256; ++v) {
+          uint32_t x = 0;
+          for (int t = 0; t < 8; ++t)
+            if ((v >> t) & 1 && 8 * b + t < m) x ^= col[8 * b + t];
+          tab[((size_t)j * net.nbytes + b) * 256 + v] = x;
+        }
+    }
+    if (hipMalloc(&net.d_xtab, tab.size() * 4) != hipSuccess) {
+      delete h;
+      return fail(FDWT_ENOMEM, "table allocation failed");
+    }
+    if (hipMemcpy(net.d_xtab, tab.data(), tab.size() * 4, hipMemcpyHostToDevice) != hipSuccess) {
+      hipFree(net.d_xtab);
+      delete h;
+      return fail(FDWT_EDEVICE, "table upload failed");
+    }
+  } else {
+    // Packed digits of v * (column c of C_j) mod p, digit y_{r+1} at bits 4(m-1-r).
+    std::vector<uint64_t> tab((size_t)s * m * p, 0);
+    for (int j = 0; j < s; ++j)
+      for (int c = 0; c < m; ++c)
+        for (int v = 0; v < p; ++v) {
+          uint64_t x = 0;
+          for (int r = 0; r < m; ++r) x |= (uint64_t)((v * C(j, r, c)) % p) << (4 * (m - 1 - r));
+          tab[((size_t)j * m + c) * p + v] = x;
+        }
+    if (hipMalloc(&net.d_ptab, tab.size() * 8) != hipSuccess) {
+      delete h;
+      return fail(FDWT_ENOMEM, "table allocation failed");
+    }
+    if (hipMemcpy(net.d_ptab, tab.data(), tab.size() * 8, hipMemcpyHostToDevice) != hipSuccess) {
+      hipFree(net.d_ptab);
+      delete h;
+      return fail(FDWT_EDEVICE, "table upload failed");
+    }
+  }
+  *out = h;
+  return FDWT_OK;
+  FDWT_GUARD_END
+}
+
+int fdwt_net_info(const fdwt_net* h, int* p, int* m, int* s, int64_t* n_points) {
+  if (int rc = check_net(h)) return rc;
+  if (p) *p = h->n.p;
+  if (m) *m = h->n.m;
+  if (s) *s = h->n.s;
+  if (n_points) *n_points = h->n.N;
+  return FDWT_OK;
+}
+
+void fdwt_net_free(fdwt_net* h) {
+  if (!h) return;
+  Net& n = h->n;
+  DeviceGuard g(n.device);
+  if (n.ws || n.pin_done) (void)hipDeviceSynchronize();
+  if (n.d_xtab) (void)hipFree(n.d_xtab);
+  if (n.d_ptab) (void)hipFree(n.d_ptab);
+  if (n.ws) (void)hipFree(n.ws);
+  if (n.pin) (void)hipHostFree(n.pin);
+  if (n.pin_done) (void)hipEventDestroy(n.pin_done);
+  delete h;
+}
+
+int fdwt_net_digits(const fdwt_net* h, uint32_t* X_dev, void* stream) {
+  FDWT_GUARD_BEGIN
+  if (int rc = check_net(h)) return rc;
+  if (!X_dev) return fail(FDWT_EINVAL, "NULL output");
+  DeviceGuard g(h->n.device);
+  return launch_net_digits(h->n, X_dev, (hipStream_t)stream);
+  FDWT_GUARD_END
+}
+
+int fdwt_net_points(const fdwt_net* h, float* x_dev, void* stream) {
+  FDWT_GUARD_BEGIN
+  if (int rc = check_net(h)) return rc;
+  if (!x_dev) return fail(FDWT_EINVAL, "NULL output");
+  DeviceGuard g(h->n.device);
+  return launch_net_points(h->n, x_dev, (hipStream_t)stream);
+  FDWT_GUARD_END
+}
+
+int fdwt_sample(const fdwt_net* h, int family, const double* a_host, float* f_dev, void* stream) {
+  FDWT_GUARD_BEGIN
+  if (int rc = check_net(h)) return rc;
+  if (!a_host || !f_dev) return fail(FDWT_EINVAL, "NULL argument");
+  if (family != FDWT_FAMILY_PRODUCT && family != FDWT_FAMILY_EXP && family != FDWT_FAMILY_WANGFANG)
+    return fail(FDWT_EINVAL, "unknown family");
+  for (int j = 0; j < h->n.s; ++j)
+    if (!std::isfinite(a_host[j]) || (family == FDWT_FAMILY_WANGFANG && a_host[j] <= -1.0))
+      return fail(FDWT_EINVAL, "family parameter out of range");
+  DeviceGuard g(h->n.device);
+  return launch_sample(h->n, family, a_host, f_dev, (hipStream_t)stream);
+  FDWT_GUARD_END
+}
+
+int fdwt_dwt_forward(const fdwt_net* h, int in_type, const void* in_dev, int out_type, void* out_dev,
+                     void* stream) {
+  FDWT_GUARD_BEGIN
+  if (int rc = check_net(h)) return rc;
+  DeviceGuard g(h->n.device);
+  return transform(const_cast<Net&>(h->n), false, in_type, in_dev, out_type, out_dev,
+                   (hipStream_t)stream);
+  FDWT_GUARD_END
+}
+
+int fdwt_dwt_inverse(const fdwt_net* h, int in_type, const void* in_dev, int out_type, void* out_dev,
+                     void* stream) {
+  FDWT_GUARD_BEGIN
+  if (int rc = check_net(h)) return rc;
+  DeviceGuard g(h->n.device);
+  return transform(const_cast<Net&>(h->n), true, in_type, in_dev, out_type, out_dev,
+                   (hipStream_t)stream);
+  FDWT_GUARD_END
+}
+
+int fdwt_spline_coef(const fdwt_net* h, const fdwt_kernel* kern, int ft_type, const void* ft_dev,
+                     float* c_dev, void* stream) {
+  FDWT_GUARD_BEGIN
+  if (int rc = check_net(h)) return rc;
+  if (int rc = check_kernel(h->n, kern)) return rc;
+  if (!ft_dev || !c_dev) return fail(FDWT_EINVAL, "NULL data pointer");
+  if (ft_type != (h->n.p == 2 ? FDWT_F32 : FDWT_CF32))
+    return fail(FDWT_EINVAL, "coefficients must be F32 (p = 2) or CF32 (p odd)");
+  DeviceGuard g(h->n.device);
+  return run_spline_coef(const_cast<Net&>(h->n), kern, ft_type, ft_dev, c_dev, (hipStream_t)stream);
+  FDWT_GUARD_END
+}
+
+int fdwt_spline_eval(const fdwt_net* h, const fdwt_kernel* kern, const float* c_dev, int64_t nq,
+                     const uint32_t* q_dev, float* sf_dev, void* stream) {
+  FDWT_GUARD_BEGIN
+  if (int rc = check_net(h)) return rc;
+  if (int rc = check_kernel(h->n, kern)) return rc;
+  if (nq < 0 || nq > (int64_t(1) << 28)) return fail(FDWT_EINVAL, "nq must be in 0..2^28");
+  if (nq == 0) return FDWT_OK;
+  if (!c_dev || !q_dev || !sf_dev) return fail(FDWT_EINVAL, "NULL data pointer");
+  DeviceGuard g(h->n.device);
+  return run_spline_eval(const_cast<Net&>(h->n), kern, c_dev, nq, q_dev, sf_dev, (hipStream_t)stream);
+  FDWT_GUARD_END
+}
+
+int fdwt_walsh_interp(const fdwt_net* h, const fdwt_kernel* kern, const float* f_dev, float* c_dev,
+                      int64_t nq, const uint32_t* q_dev, float* sf_dev, void* stream) {
+  FDWT_GUARD_BEGIN
+  if (int rc = check_net(h)) return rc;
+  if (int rc = check_kernel(h->n, kern)) return rc;
+  if (!f_dev) return fail(FDWT_EINVAL, "NULL data pointer");
+  if (nq < 0 || nq > (int64_t(1) << 28)) return fail(FDWT_EINVAL, "nq must be in 0..2^28");
+  if (nq > 0 && (!q_dev || !sf_dev)) return fail(FDWT_EINVAL, "NULL query or output pointer");
+  Net& net = const_cast<Net&>(h->n);
+  DeviceGuard g(net.device);
+  hipStream_t st = (hipStream_t)stream;
+  // ft and c live in the caller's c buffer when given, else in a scratch
+  // allocation owned by this call.
+  const size_t ftb = (size_t)net.N * (net.p == 2 ? 4 : 8);
+  void* ft = nullptr;
+  float* c = c_dev;
+  if (hipMallocAsync(&ft, ftb + (c_dev ? 0 : (size_t)net.N * 4), st) != hipSuccess) {
+    (void)hipGetLastError();
+    return fail(FDWT_ENOMEM, "interpolation scratch allocation failed");
+  }
+  if (!c) c = (float*)((char*)ft + ftb);
+  int rc = transform(net, false, FDWT_F32, f_dev, net.p == 2 ? FDWT_F32 : FDWT_CF32, ft, st);
+  if (!rc) rc = run_spline_coef(net, kern, net.p == 2 ? FDWT_F32 : FDWT_CF32, ft, c, st);
+  if (!rc && nq > 0) rc = run_spline_eval(net, kern, c, nq, q_dev, sf_dev, st);
+  (void)hipFreeAsync(ft, st);
+  return rc;
+  FDWT_GUARD_END
+}
+
+int fdwt_eff_dim(const fdwt_net* h, const fdwt_kernel* kern, int ft_type, const void* ft_dev,
+                 fdwt_effdim* out, void* stream) {
+  FDWT_GUARD_BEGIN
+  if (int rc = check_net(h)) return rc;
+  if (int rc = check_kernel(h->n, kern)) return rc;
+  if (!ft_dev || !out || !out->var_trc || !out->var_sup) return fail(FDWT_EINVAL, "NULL argument");
+  if (ft_type != (h->n.p == 2 ? FDWT_F32 : FDWT_CF32))
+    return fail(FDWT_EINVAL, "coefficients must be F32 (p = 2) or CF32 (p odd)");
+  DeviceGuard g(h->n.device);
+  return run_eff_dim(const_cast<Net&>(h->n), kern, ft_type, ft_dev, out, (hipStream_t)stream);
+  FDWT_GUARD_END
+}
+
+}  // extern "C"

@@ -1,0 +1,162 @@
+// Device arithmetic for the transform element types: float, uint32 (mod 2^32),
+// complex float (float2), double-float (df) and complex double-float (cdf),
+// plus the radix-p DFT codelets the butterfly stages apply.
+#pragma once
+
+#include "fdwt_internal.h"
+
+namespace fdwt {
+
+// ---------------------------------------------------------- double-float
+// Error-free transformations (Knuth's TwoSum, Dekker's FastTwoSum, and the
+// FMA-based exact product).  Contraction is switched off so the compiler
+// keeps every rounding step as written.
+__device__ __forceinline__ df two_sum(float a, float b) {
+#pragma clang fp contract(off)
+  float s = a + b;
+  float bb = s - a;
+  float e = (a - (s - bb)) + (b - bb);
+  return {s, e};
+}
+__device__ __forceinline__ df fast_two_sum(float a, float b) {
+#pragma clang fp contract(off)
+  float s = a + b;
+  float e = b - (s - a);
+  return {s, e};
+}
+__device__ __forceinline__ df add(df a, df b) {
+#pragma clang fp contract(off)
+  df s = two_sum(a.hi, b.hi);
+  df t = two_sum(a.lo, b.lo);
+  s.lo += t.hi;
+  s = fast_two_sum(s.hi, s.lo);
+  s.lo += t.lo;
+  return fast_two_sum(s.hi, s.lo);
+}
+__device__ __forceinline__ df neg(df a) { return {-a.hi, -a.lo}; }
+__device__ __forceinline__ df sub(df a, df b) { return add(a, neg(b)); }
+__device__ __forceinline__ df mul(df a, df b) {
+#pragma clang fp contract(off)
+  float p = a.hi * b.hi;
+  float e = __builtin_fmaf(a.hi, b.hi, -p);
+  e = __builtin_fmaf(a.hi, b.lo, e);
+  e = __builtin_fmaf(a.lo, b.hi, e);
+  return fast_two_sum(p, e);
+}
+__device__ __forceinline__ df scale(df a, df c) { return mul(a, c); }
+__device__ __forceinline__ df half(df a) { return {0.5f * a.hi, 0.5f * a.lo}; }
+__device__ __forceinline__ df df_from(float v) { return {v, 0.0f}; }
+__device__ __forceinline__ double to_double(df a) { return (double)a.hi + (double)a.lo; }
+
+// ----------------------------------------------------------- plain types
+__device__ __forceinline__ float add(float a, float b) { return a + b; }
+__device__ __forceinline__ float sub(float a, float b) { return a - b; }
+__device__ __forceinline__ uint32_t add(uint32_t a, uint32_t b) { return a + b; }
+__device__ __forceinline__ uint32_t sub(uint32_t a, uint32_t b) { return a - b; }
+
+__device__ __forceinline__ float2 add(float2 a, float2 b) { return make_float2(a.x + b.x, a.y + b.y); }
+__device__ __forceinline__ float2 sub(float2 a, float2 b) { return make_float2(a.x - b.x, a.y - b.y); }
+__device__ __forceinline__ float2 scale(float2 a, float c) { return make_float2(a.x * c, a.y * c); }
+__device__ __forceinline__ float2 half(float2 a) { return make_float2(0.5f * a.x, 0.5f * a.y); }
+// a + i*sg*b for sg = +1 or -1 (multiplication by +-i folded in).
+__device__ __forceinline__ float2 add_i(float2 a, float2 b, int sg) {
+  return sg > 0 ? make_float2(a.x - b.y, a.y + b.x) : make_float2(a.x + b.y, a.y - b.x);
+}
+
+__device__ __forceinline__ cdf add(cdf a, cdf b) { return {add(a.re, b.re), add(a.im, b.im)}; }
+__device__ __forceinline__ cdf sub(cdf a, cdf b) { return {sub(a.re, b.re), sub(a.im, b.im)}; }
+__device__ __forceinline__ cdf scale(cdf a, df c) { return {mul(a.re, c), mul(a.im, c)}; }
+__device__ __forceinline__ cdf half(cdf a) { return {half(a.re), half(a.im)}; }
+__device__ __forceinline__ cdf add_i(cdf a, cdf b, int sg) {
+  return sg > 0 ? cdf{sub(a.re, b.im), add(a.im, b.re)} : cdf{add(a.re, b.im), sub(a.im, b.re)};
+}
+
+// ---------------------------------------------------- codelet constants
+// Real constants of the p-point DFT, as float and as double-float
+// (hi = nearest float, lo = nearest float to the remainder).
+struct DfConst {
+  float hi, lo;
+};
+constexpr DfConst mkdf(double v) {
+  return DfConst{(float)v, (float)(v - (double)(float)v)};
+}
+constexpr double kSin60 = 0.86602540378443864676;   // sin(2 pi / 3)
+constexpr double kCos72 = 0.30901699437494742410;   // cos(2 pi / 5)
+constexpr double kSin72 = 0.95105651629515357212;   // sin(2 pi / 5)
+constexpr double kCos144 = -0.80901699437494742410; // cos(4 pi / 5)
+constexpr double kSin144 = 0.58778525229247312917;  // sin(4 pi / 5)
+
+template <class C>
+struct RealOf;
+template <>
+struct RealOf<float2> {
+  using T = float;
+  static __device__ __forceinline__ float k(double v, DfConst) { return (float)v; }
+};
+template <>
+struct RealOf<cdf> {
+  using T = df;
+  static __device__ __forceinline__ df k(double, DfConst c) { return df{c.hi, c.lo}; }
+};
+#define FDWT_K(C, v) RealOf<C>::k(v, mkdf(v))
+
+// p-point DFT of x[0], x[st], ..., x[(p-1) st] in place:
+//   y_h = sum_n x_n w^(n h),  w = exp(-2 pi i / p) (forward) or exp(+2 pi i / p)
+// (inverse).  For p = 2 any ring element type works.
+template <int P, bool INV>
+struct Dft;
+
+template <bool INV>
+struct Dft<2, INV> {
+  template <class T>
+  static __device__ __forceinline__ void run(T* x, int st) {
+    T a = x[0], b = x[st];
+    x[0] = add(a, b);
+    x[st] = sub(a, b);
+  }
+};
+
+template <bool INV>
+struct Dft<3, INV> {
+  // y0 = x0 + t, y1,2 = (x0 - t/2) -+ i sin60 (x1 - x2) (forward signs).
+  template <class C>
+  static __device__ __forceinline__ void run(C* x, int st) {
+    C x0 = x[0], x1 = x[st], x2 = x[2 * st];
+    C t = add(x1, x2);
+    C d = sub(x1, x2);
+    C a = sub(x0, half(t));
+    C b = scale(d, FDWT_K(C, kSin60));
+    const int sg = INV ? 1 : -1;
+    x[0] = add(x0, t);
+    x[st] = add_i(a, b, sg);
+    x[2 * st] = add_i(a, b, -sg);
+  }
+};
+
+template <bool INV>
+struct Dft<5, INV> {
+  // With t1 = x1 + x4, t2 = x2 + x3, d1 = x1 - x4, d2 = x2 - x3:
+  //   a1 = x0 + c72 t1 + c144 t2, a2 = x0 + c144 t1 + c72 t2,
+  //   b1 = s72 d1 + s144 d2,       b2 = s144 d1 - s72 d2,
+  //   y1 = a1 -+ i b1, y4 = a1 +- i b1, y2 = a2 -+ i b2, y3 = a2 +- i b2.
+  template <class C>
+  static __device__ __forceinline__ void run(C* x, int st) {
+    C x0 = x[0], x1 = x[st], x2 = x[2 * st], x3 = x[3 * st], x4 = x[4 * st];
+    C t1 = add(x1, x4), t2 = add(x2, x3);
+    C d1 = sub(x1, x4), d2 = sub(x2, x3);
+    const auto c1 = FDWT_K(C, kCos72), c2 = FDWT_K(C, kCos144);
+    const auto s1 = FDWT_K(C, kSin72), s2 = FDWT_K(C, kSin144);
+    C a1 = add(x0, add(scale(t1, c1), scale(t2, c2)));
+    C a2 = add(x0, add(scale(t1, c2), scale(t2, c1)));
+    C b1 = add(scale(d1, s1), scale(d2, s2));
+    C b2 = sub(scale(d1, s2), scale(d2, s1));
+    const int sg = INV ? 1 : -1;
+    x[0] = add(x0, add(t1, t2));
+    x[st] = add_i(a1, b1, sg);
+    x[4 * st] = add_i(a1, b1, -sg);
+    x[2 * st] = add_i(a2, b2, sg);
+    x[3 * st] = add_i(a2, b2, -sg);
+  }
+};
+
+}  // namespace fdwt

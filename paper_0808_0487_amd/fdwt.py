@@ -1,0 +1,233 @@
+"""Thin ctypes binding of libfdwt (include/fdwt.h).
+
+Argument marshalling only: every computation runs in the library's HIP
+kernels.  Device buffers are torch CUDA tensors (ROCm); the HIP stream is
+torch's current stream unless one is passed.  Raises RuntimeError when the
+library is not built or a call fails -- there is no fallback path.
+"""
+import ctypes
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libfdwt.so")
+
+OK, EINVAL, ENOMEM, EDEVICE, EBUDGET, EUNSUPPORTED = 0, -1, -2, -3, -4, -5
+F32, I32, CF32 = 1, 2, 3
+FAMILY = {"product": 1, "exp": 2, "wangfang": 3}
+
+# Every function the header declares, with (restype, argtypes).
+_vp, _i, _i64, _d = ctypes.c_void_p, ctypes.c_int, ctypes.c_int64, ctypes.c_double
+
+
+class KernelC(ctypes.Structure):
+    _fields_ = [("alpha", ctypes.c_double), ("gamma", ctypes.POINTER(ctypes.c_double)), ("s", ctypes.c_int)]
+
+
+class EffDimC(ctypes.Structure):
+    _fields_ = [("var_trc", ctypes.POINTER(ctypes.c_double)), ("var_sup", ctypes.POINTER(ctypes.c_double)),
+                ("var_total", ctypes.c_double), ("var_total_h0", ctypes.c_double),
+                ("var_qmc", ctypes.c_double), ("d_trc", ctypes.c_int), ("d_sup", ctypes.c_int)]
+
+
+SIGNATURES = {
+    "fdwt_net_generate": (_i, [_i, _i, _i, _vp, ctypes.POINTER(_vp)]),
+    "fdwt_net_info": (_i, [_vp, ctypes.POINTER(_i), ctypes.POINTER(_i), ctypes.POINTER(_i), ctypes.POINTER(_i64)]),
+    "fdwt_net_digits": (_i, [_vp, _vp, _vp]),
+    "fdwt_net_points": (_i, [_vp, _vp, _vp]),
+    "fdwt_net_free": (None, [_vp]),
+    "fdwt_sample": (_i, [_vp, _i, _vp, _vp, _vp]),
+    "fdwt_dwt_forward": (_i, [_vp, _i, _vp, _i, _vp, _vp]),
+    "fdwt_dwt_inverse": (_i, [_vp, _i, _vp, _i, _vp, _vp]),
+    "fdwt_query_depth": (_i, [_i]),
+    "fdwt_spline_coef": (_i, [_vp, ctypes.POINTER(KernelC), _i, _vp, _vp, _vp]),
+    "fdwt_spline_eval": (_i, [_vp, ctypes.POINTER(KernelC), _vp, _i64, _vp, _vp, _vp]),
+    "fdwt_walsh_interp": (_i, [_vp, ctypes.POINTER(KernelC), _vp, _vp, _i64, _vp, _vp, _vp]),
+    "fdwt_eff_dim": (_i, [_vp, ctypes.POINTER(KernelC), _i, _vp, ctypes.POINTER(EffDimC), _vp]),
+    "fdwt_last_error": (ctypes.c_char_p, []),
+}
+
+_LIB = None
+
+
+def lib():
+    """Load libfdwt.so (once).  Raises if it is not built."""
+    global _LIB
+    if _LIB is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError("libfdwt.so is not built (%s); run __graft_entry__.build()" % LIB_PATH)
+        L = ctypes.CDLL(LIB_PATH)
+        for name, (res, args) in SIGNATURES.items():
+            fn = getattr(L, name)
+            fn.restype = res
+            fn.argtypes = args
+        _LIB = L
+    return _LIB
+
+
+class FdwtError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__("fdwt error %d: %s" % (code, msg))
+        self.code = code
+
+
+def _check(rc):
+    if rc != OK:
+        raise FdwtError(rc, lib().fdwt_last_error().decode())
+
+
+def _stream(stream):
+    import torch
+    if stream is None:
+        return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+    return ctypes.c_void_p(stream.cuda_stream if hasattr(stream, "cuda_stream") else int(stream))
+
+
+def _ptr(t):
+    if t is None:
+        return None
+    if not t.is_cuda:
+        raise ValueError("expected a device tensor")
+    if not t.is_contiguous():
+        raise ValueError("expected a contiguous tensor")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _type_of(t):
+    import torch
+    return {torch.float32: F32, torch.int32: I32, torch.complex64: CF32}[t.dtype]
+
+
+class Kernel:
+    """Weighted Walsh kernel (alpha, gamma_1..gamma_s) of Section 4."""
+
+    def __init__(self, alpha, gamma):
+        self.alpha = float(alpha)
+        self.gamma = np.ascontiguousarray(gamma, dtype=np.float64)
+        self._c = KernelC(self.alpha, self.gamma.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                          len(self.gamma))
+
+    @property
+    def c(self):
+        return ctypes.byref(self._c)
+
+
+class Net:
+    """A digital net handle (fdwt_net_generate)."""
+
+    def __init__(self, p, m, s, C):
+        C = np.ascontiguousarray(C, dtype=np.uint8)
+        if C.shape != (s, m, m):
+            raise ValueError("C must have shape (s, m, m)")
+        h = ctypes.c_void_p()
+        _check(lib().fdwt_net_generate(p, m, s, C.ctypes.data_as(ctypes.c_void_p), ctypes.byref(h)))
+        self.h = h
+        self.p, self.m, self.s = p, m, s
+        self.N = p ** m
+
+    def close(self):
+        if self.h:
+            lib().fdwt_net_free(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def info(self):
+        p, m, s, n = ctypes.c_int(), ctypes.c_int(), ctypes.c_int(), ctypes.c_int64()
+        _check(lib().fdwt_net_info(self.h, ctypes.byref(p), ctypes.byref(m), ctypes.byref(s), ctypes.byref(n)))
+        return p.value, m.value, s.value, n.value
+
+    # --------------------------------------------------------------- net
+    def digits(self, out=None, stream=None):
+        import torch
+        if out is None:
+            out = torch.empty((self.s, self.N), dtype=torch.int32, device="cuda")
+        _check(lib().fdwt_net_digits(self.h, _ptr(out), _stream(stream)))
+        return out
+
+    def points(self, out=None, stream=None):
+        import torch
+        if out is None:
+            out = torch.empty((self.s, self.N), dtype=torch.float32, device="cuda")
+        _check(lib().fdwt_net_points(self.h, _ptr(out), _stream(stream)))
+        return out
+
+    def sample(self, family, a, out=None, stream=None):
+        import torch
+        a = np.ascontiguousarray(a, dtype=np.float64)
+        if out is None:
+            out = torch.empty(self.N, dtype=torch.float32, device="cuda")
+        _check(lib().fdwt_sample(self.h, FAMILY[family], a.ctypes.data_as(ctypes.c_void_p), _ptr(out),
+                                 _stream(stream)))
+        return out
+
+    # --------------------------------------------------------- transforms
+    def forward(self, x, out=None, stream=None):
+        """dwt_forward: float32 -> float32 (p = 2) or complex64 (p odd);
+        int32 -> int32 (p = 2, unnormalised, mod 2^32)."""
+        import torch
+        if out is None:
+            if x.dtype == torch.int32:
+                dt = torch.int32
+            else:
+                dt = torch.float32 if self.p == 2 else torch.complex64
+            out = torch.empty(self.N, dtype=dt, device=x.device)
+        _check(lib().fdwt_dwt_forward(self.h, _type_of(x), _ptr(x), _type_of(out), _ptr(out), _stream(stream)))
+        return out
+
+    def inverse(self, x, out=None, real=False, stream=None):
+        """dwt_inverse (no normalisation); real=True returns the real part
+        (p odd)."""
+        import torch
+        if out is None:
+            dt = x.dtype
+            if real and x.dtype == torch.complex64:
+                dt = torch.float32
+            out = torch.empty(self.N, dtype=dt, device=x.device)
+        _check(lib().fdwt_dwt_inverse(self.h, _type_of(x), _ptr(x), _type_of(out), _ptr(out), _stream(stream)))
+        return out
+
+    # ------------------------------------------------------------ spline
+    def spline_coef(self, kern, ft, out=None, stream=None):
+        import torch
+        if out is None:
+            out = torch.empty(self.N, dtype=torch.float32, device=ft.device)
+        _check(lib().fdwt_spline_coef(self.h, kern.c, _type_of(ft), _ptr(ft), _ptr(out), _stream(stream)))
+        return out
+
+    def spline_eval(self, kern, c, q, out=None, stream=None):
+        import torch
+        nq = q.shape[1]
+        if out is None:
+            out = torch.empty(nq, dtype=torch.float32, device=c.device)
+        _check(lib().fdwt_spline_eval(self.h, kern.c, _ptr(c), nq, _ptr(q), _ptr(out), _stream(stream)))
+        return out
+
+    def walsh_interp(self, kern, f, q=None, c_out=None, sf_out=None, stream=None):
+        import torch
+        if c_out is None:
+            c_out = torch.empty(self.N, dtype=torch.float32, device=f.device)
+        nq = 0 if q is None else q.shape[1]
+        if nq and sf_out is None:
+            sf_out = torch.empty(nq, dtype=torch.float32, device=f.device)
+        _check(lib().fdwt_walsh_interp(self.h, kern.c, _ptr(f), _ptr(c_out), nq, _ptr(q) if nq else None,
+                                       _ptr(sf_out) if nq else None, _stream(stream)))
+        return c_out, sf_out
+
+    def eff_dim(self, kern, ft, stream=None):
+        trc = np.zeros(self.s + 1)
+        sup = np.zeros(self.s + 1)
+        out = EffDimC(trc.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                      sup.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), 0.0, 0.0, 0.0, 0, 0)
+        _check(lib().fdwt_eff_dim(self.h, kern.c, _type_of(ft), _ptr(ft), ctypes.byref(out), _stream(stream)))
+        return {"var_trc": trc, "var_sup": sup, "var_total": out.var_total, "var_total_h0": out.var_total_h0,
+                "var_qmc": out.var_qmc, "d_trc": out.d_trc, "d_sup": out.d_sup}
+
+
+def query_depth(p):
+    return lib().fdwt_query_depth(p)

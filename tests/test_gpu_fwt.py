@@ -1,0 +1,165 @@
+"""Forward and inverse transforms on the GPU against the oracle's
+definition (Eq. (eq_dwalshcoeff), Lemma of Section 3.3)."""
+import numpy as np
+import pytest
+import torch
+
+from oracle import families, net as onet, walsh
+from paper_0808_0487_amd import fdwt, inputs
+from tests.gpu_common import announce, nrel, sample_indices
+
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-5  # normwise relative, float32 data
+
+
+def to_dev(a, dtype):
+    return torch.from_numpy(np.ascontiguousarray(a)).to(dtype).cuda()
+
+
+def test_small_configuration_against_definition():
+    """p = 2, m = 10, s = 4, product family: forward vs the definition with
+    the K(C)-free coset members, round trip, int32 bit-exact."""
+    p, m, s = 2, 10, 4
+    announce("C1 forward", p, m, s)
+    C = inputs.upper_triangular_generators(p, m, s, 1)
+    a = inputs.family_params("product", s, const=0.5)
+    fo = families.product(onet.net_points(p, m, C), a)
+    net = fdwt.Net(p, m, s, C)
+    ft = net.forward(to_dev(fo, torch.float32)).cpu().numpy()
+    ref = walsh.dwt_direct(p, m, C, fo).real
+    assert nrel(ft, ref) <= TOL
+    back = net.inverse(to_dev(ref, torch.float32)).cpu().numpy()
+    assert nrel(back, fo) <= TOL
+    fi = inputs.uniform_int32(p ** m, -1000, 1000, 3)
+    gi = net.forward(to_dev(fi, torch.int32)).cpu().numpy().astype(np.int64)
+    assert np.array_equal(gi, walsh.dwt_direct(p, m, C, fi))
+    bi = net.inverse(to_dev(gi.astype(np.int32), torch.int32)).cpu().numpy().astype(np.int64)
+    assert np.array_equal(bi, (p ** m) * fi.astype(np.int64))
+
+
+P2_SIZES = [1, 2, 3, 5, 8, 12, 13, 14, 15, 16, 17, 19, 21, 22]
+
+
+@pytest.mark.parametrize("m", P2_SIZES)
+def test_p2_float_sizes_span_tiles_and_passes(m):
+    """Every pass layout (one tile, one pass, two and three passes, ragged
+    digit splits) against the phase form on sampled outputs."""
+    p = 2
+    announce("p2 f32 forward/inverse", m)
+    N = p ** m
+    f = inputs.uniform_float(N, 100 + m, dtype=np.float64)
+    net = fdwt.Net(p, m, 1, inputs.identity_generators(p, m, 1))
+    ft = net.forward(to_dev(f, torch.float32)).cpu().numpy()
+    hs = sample_indices(N, 300, m)
+    ref = walsh.dwt_phase(p, m, f, hs)
+    assert nrel(ft[hs], ref) <= TOL
+    assert abs(np.sum(ft.astype(np.float64) ** 2) - np.sum(f ** 2) / N) <= 1e-5 * np.sum(f ** 2) / N
+    back = net.inverse(to_dev(ft, torch.float32)).cpu().numpy()
+    assert nrel(back, f) <= TOL
+
+
+@pytest.mark.parametrize("m", [1, 4, 13, 14, 18, 23])
+def test_p2_int32_bit_exact(m):
+    p = 2
+    announce("p2 i32", m)
+    N = p ** m
+    f = inputs.uniform_int32(N, -1000, 1000, 200 + m)
+    net = fdwt.Net(p, m, 1, inputs.identity_generators(p, m, 1))
+    g = net.forward(to_dev(f, torch.int32))
+    hs = sample_indices(N, 200, m)
+    ref = walsh.dwt_phase(p, m, f, hs)
+    got = g.cpu().numpy().astype(np.int64)
+    assert np.array_equal(got[hs], ref)
+    back = net.inverse(g).cpu().numpy().astype(np.int64)
+    assert np.array_equal(back, (N * f.astype(np.int64) + 2 ** 31) % 2 ** 32 - 2 ** 31)
+
+
+@pytest.mark.parametrize("p,m", [(3, 1), (3, 2), (3, 7), (3, 8), (3, 9), (3, 12), (3, 15),
+                                 (5, 1), (5, 2), (5, 5), (5, 6), (5, 8), (5, 10)])
+def test_odd_p_complex_sizes(p, m):
+    announce("odd p forward/inverse", p, m)
+    N = p ** m
+    f = inputs.uniform_float(N, 300 + m, dtype=np.float64)
+    net = fdwt.Net(p, m, 1, inputs.identity_generators(p, m, 1))
+    ft = net.forward(to_dev(f, torch.float32)).cpu().numpy()
+    hs = sample_indices(N, 200, m)
+    ref = walsh.dwt_phase(p, m, f, hs)
+    assert nrel(ft[hs], ref) <= TOL
+    back = net.inverse(to_dev(ft, torch.complex64), real=True).cpu().numpy()
+    assert nrel(back, f) <= TOL
+    backc = net.inverse(to_dev(ft, torch.complex64)).cpu().numpy()
+    assert nrel(backc, f) <= TOL
+    # complex input forward
+    z = f + 1j * inputs.uniform_float(N, 400 + m, dtype=np.float64)
+    zt = net.forward(to_dev(z, torch.complex64)).cpu().numpy()
+    assert nrel(zt[hs], walsh.dwt_phase(p, m, z, hs)) <= TOL
+
+
+@pytest.mark.parametrize("p,m,s,seed", [(2, 5, 2, 11), (2, 4, 3, 14), (3, 3, 2, 12), (5, 2, 2, 13)])
+def test_net_data_against_definition_with_representatives(p, m, s, seed):
+    """Data on a small non-trivial net against the definition evaluated with
+    the K(C) representatives themselves."""
+    announce("K(C) definition", p, m, s, seed)
+    C = inputs.upper_triangular_generators(p, m, s, seed)
+    x = onet.net_points(p, m, C)
+    fo = families.exponential(x, inputs.family_params("exp", s, ratio=0.5))
+    net = fdwt.Net(p, m, s, C)
+    ft = net.forward(to_dev(fo, torch.float32)).cpu().numpy()
+    ref = walsh.dwt_direct(p, m, C, fo, reps=walsh.representatives(p, m, C))
+    if p == 2:
+        ref = ref.real
+    assert nrel(ft, ref) <= TOL
+
+
+def test_full_size_p2_float_and_int32():
+    """m = 24 (the plain-at-scale workload): sampled outputs against the
+    phase form, Parseval, round trip; int32 exact on samples and the round
+    trip mod 2^32."""
+    p, m = 2, 24
+    N = p ** m
+    announce("full p2 m=24")
+    net = fdwt.Net(p, m, 20, inputs.upper_triangular_generators(p, m, 20, 2))
+    f = inputs.uniform_float(N, 24, dtype=np.float64)
+    fd = to_dev(f, torch.float32)
+    ft = net.forward(fd)
+    hs = sample_indices(N, 48, 24)
+    got = ft.cpu().numpy()
+    assert nrel(got[hs], walsh.dwt_phase(p, m, f, hs)) <= TOL
+    e_f = float(torch.sum(fd.double() ** 2)) / N
+    assert abs(float(torch.sum(ft.double() ** 2)) - e_f) <= 1e-5 * e_f
+    back = net.inverse(ft)
+    assert float(torch.linalg.norm(back - fd) / torch.linalg.norm(fd)) <= TOL
+    fi = inputs.uniform_int32(N, -1000, 1000, 25)
+    gi = net.forward(to_dev(fi, torch.int32))
+    gin = gi.cpu().numpy().astype(np.int64)
+    assert np.array_equal(gin[hs], walsh.dwt_phase(p, m, fi, hs))
+    bi = net.inverse(gi).cpu().numpy().astype(np.int64)
+    assert np.array_equal(bi, (N * fi.astype(np.int64) + 2 ** 31) % 2 ** 32 - 2 ** 31)
+
+
+def test_full_size_p3():
+    """p = 3, m = 14 (4.78M points): sampled outputs and round trip."""
+    p, m = 3, 14
+    N = p ** m
+    announce("full p3 m=14")
+    net = fdwt.Net(p, m, 10, inputs.upper_triangular_generators(p, m, 10, 3))
+    f = inputs.uniform_float(N, 31, dtype=np.float64)
+    ft = net.forward(to_dev(f, torch.float32))
+    hs = sample_indices(N, 24, 14)
+    assert nrel(ft.cpu().numpy()[hs], walsh.dwt_phase(p, m, f, hs)) <= TOL
+    back = net.inverse(ft, real=True).cpu().numpy()
+    assert nrel(back, f) <= TOL
+
+
+def test_in_place_and_errors():
+    p, m = 2, 15
+    announce("in place / errors")
+    net = fdwt.Net(p, m, 1, inputs.identity_generators(p, m, 1))
+    f = to_dev(inputs.uniform_float(2 ** m, 5), torch.float32)
+    ref = net.forward(f).clone()
+    g = f.clone()
+    net.forward(g, out=g)
+    assert torch.equal(g, ref)
+    with pytest.raises(fdwt.FdwtError):
+        net.forward(f, out=torch.empty(2 ** m, dtype=torch.int32, device="cuda"))

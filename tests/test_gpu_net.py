@@ -1,0 +1,79 @@
+"""Net generation and sampling on the GPU against the oracle (bit-exact
+digits; float points and samples)."""
+import numpy as np
+import pytest
+import torch
+
+from oracle import families, net as onet
+from paper_0808_0487_amd import fdwt, inputs
+from tests.gpu_common import announce, nrel, sample_indices
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.mark.parametrize("p,m,s,seed", [(2, 1, 1, 1), (2, 7, 3, 2), (2, 10, 4, 1), (2, 13, 8, 3),
+                                        (2, 17, 5, 4), (3, 1, 2, 5), (3, 6, 4, 6), (3, 9, 3, 7),
+                                        (5, 1, 1, 8), (5, 4, 3, 9), (5, 7, 2, 10)])
+def test_net_digits_bit_exact(p, m, s, seed):
+    announce("net_digits", p, m, s, seed)
+    C = inputs.upper_triangular_generators(p, m, s, seed)
+    net = fdwt.Net(p, m, s, C)
+    X = net.digits().cpu().numpy().astype(np.int64)
+    assert np.array_equal(X, onet.net_int(p, m, C))
+    x = net.points().cpu().numpy().astype(np.float64)
+    assert np.max(np.abs(x - onet.net_points(p, m, C))) <= 2 ** -24
+
+
+@pytest.mark.parametrize("p,m,s,seed", [(2, 6, 3, 21), (3, 4, 3, 22)])
+def test_singular_generators_bit_exact(p, m, s, seed):
+    announce("net_digits singular", p, m, s, seed)
+    C = inputs.random_generators(p, m, s, seed)
+    net = fdwt.Net(p, m, s, C)
+    assert np.array_equal(net.digits().cpu().numpy().astype(np.int64), onet.net_int(p, m, C))
+
+
+@pytest.mark.parametrize("p,m,s,seed", [(2, 24, 20, 2), (3, 14, 10, 3), (5, 11, 8, 4), (2, 26, 3, 5)])
+def test_net_digits_full_size_sampled(p, m, s, seed):
+    """Full-size nets: sampled points bit-exact; every coordinate a
+    permutation of 0..p^m-1 (non-singular generators)."""
+    announce("net_digits full", p, m, s, seed)
+    C = inputs.upper_triangular_generators(p, m, s, seed)
+    net = fdwt.Net(p, m, s, C)
+    Xd = net.digits()
+    idx = sample_indices(p ** m, 20000, seed)
+    got = Xd[:, torch.from_numpy(idx).cuda()].cpu().numpy().astype(np.int64)
+    assert np.array_equal(got, onet.net_int(p, m, C, idx))
+    ar = torch.arange(p ** m, dtype=torch.int32, device="cuda")
+    for j in range(s):
+        assert torch.equal(torch.sort(Xd[j])[0], ar)
+
+
+@pytest.mark.parametrize("kind,p,m,s,seed", [("product", 2, 10, 4, 1), ("exp", 2, 12, 20, 2),
+                                             ("wangfang", 2, 12, 10, 3), ("product", 3, 8, 10, 4),
+                                             ("exp", 5, 6, 5, 5), ("wangfang", 3, 7, 6, 6)])
+def test_sample_families(kind, p, m, s, seed):
+    announce("sample", kind, p, m, s, seed)
+    C = inputs.upper_triangular_generators(p, m, s, seed)
+    a = {"product": inputs.family_params("product", s, seed=seed),
+         "exp": inputs.family_params("exp", s),
+         "wangfang": inputs.family_params("wangfang", s, a="k")}[kind]
+    net = fdwt.Net(p, m, s, C)
+    f = net.sample(kind, a).cpu().numpy().astype(np.float64)
+    fo = families.evaluate(kind, onet.net_points(p, m, C), a)
+    assert nrel(f, fo) <= 1e-6
+    assert np.max(np.abs(f - fo) / np.maximum(np.abs(fo), 1e-30)) <= 1e-5
+
+
+def test_sample_full_size_exp_family_sampled():
+    """The C2 workload's sampler (p = 2, m = 24, s = 20, w_j = 0.1^j) at
+    sampled points."""
+    p, m, s = 2, 24, 20
+    announce("sample full", p, m, s)
+    C = inputs.upper_triangular_generators(p, m, s, 2)
+    a = inputs.family_params("exp", s, ratio=0.1)
+    net = fdwt.Net(p, m, s, C)
+    f = net.sample("exp", a)
+    idx = sample_indices(p ** m, 50000, 7)
+    got = f[torch.from_numpy(idx).cuda()].cpu().numpy().astype(np.float64)
+    fo = families.exponential(onet.net_points(p, m, C, idx), a)
+    assert np.max(np.abs(got - fo) / np.abs(fo)) <= 1e-6

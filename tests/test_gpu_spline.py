@@ -1,0 +1,141 @@
+"""Spline coefficients, interpolant evaluation and ANOVA variances on the
+GPU against the oracle (dense Gram solve, direct sums, direct double sums)."""
+import numpy as np
+import pytest
+import torch
+
+from oracle import anova, families, kernel, net as onet
+from paper_0808_0487_amd import fdwt, inputs
+from tests.gpu_common import announce, nrel, sample_indices
+
+pytestmark = pytest.mark.gpu
+
+CASES = [(2, 8, 4, 1), (2, 10, 4, 2), (2, 11, 6, 3), (3, 5, 3, 4), (3, 6, 4, 5), (5, 3, 3, 6), (5, 4, 2, 7)]
+
+
+def setup_case(p, m, s, seed, alpha=2.0):
+    C = inputs.upper_triangular_generators(p, m, s, seed)
+    X = onet.net_int(p, m, C)
+    gam = inputs.kernel_weights(s)
+    fo = families.product(X / float(p ** m), inputs.family_params("product", s, scale=1.0, alpha=2.0))
+    net = fdwt.Net(p, m, s, C)
+    kern = fdwt.Kernel(alpha, gam)
+    f = torch.from_numpy(fo).float().cuda()
+    return C, X, gam, fo, net, kern, f
+
+
+@pytest.mark.parametrize("p,m,s,seed", CASES)
+def test_spline_coefficients_solve_the_interpolation_system(p, m, s, seed):
+    """c from the spectral solve satisfies the Gram system of Section 3.2 to
+    1e-5 (normwise residual) and matches the dense solve to the system's
+    conditioning."""
+    announce("spline coef", p, m, s, seed)
+    C, X, gam, fo, net, kern, f = setup_case(p, m, s, seed)
+    ft = net.forward(f)
+    c = net.spline_coef(kern, ft).cpu().numpy().astype(np.float64)
+    G = kernel.gram(p, m, 2.0, gam, X)
+    assert nrel(G @ c, fo) <= 1e-5
+    co = kernel.spline_coef_dense(p, m, 2.0, gam, X, fo)
+    cond = np.linalg.cond(G)
+    assert nrel(c, co) <= max(1e-5, 4e-7 * cond)
+
+
+@pytest.mark.parametrize("p,m,s,seed", CASES)
+def test_interpolant_at_queries(p, m, s, seed):
+    """Sf at random D-digit queries against the oracle's direct sum with the
+    oracle's coefficients, and Sf(x_n) = f(x_n) at net points."""
+    announce("spline eval", p, m, s, seed)
+    C, X, gam, fo, net, kern, f = setup_case(p, m, s, seed)
+    D = inputs.QUERY_DEPTH[p]
+    Q = inputs.queries(p, s, 300, seed)
+    idx = sample_indices(p ** m, 40, seed)
+    Qn = kernel.to_depth(p, m, D, X[:, idx])
+    Qall = np.concatenate([Q.astype(np.int64), Qn], axis=1)
+    qd = torch.from_numpy(Qall.astype(np.uint32).view(np.int32)).cuda()
+    c, sf = net.walsh_interp(kern, f, qd)
+    sf = sf.cpu().numpy().astype(np.float64)
+    co = kernel.spline_coef_dense(p, m, 2.0, gam, X, fo)
+    ref = kernel.spline_eval(p, m, 2.0, gam, X, co, Qall, D)
+    assert nrel(sf, ref) <= 1e-5
+    assert nrel(sf[-len(idx):], fo[idx]) <= 1e-5
+
+
+@pytest.mark.parametrize("p,m,s,seed", CASES)
+def test_effective_dimension_variances(p, m, s, seed):
+    """var_trc, var_sup (Section 4) against the direct double sums with the
+    oracle's dense-solve coefficients; d_trc, d_sup equal; sample variance."""
+    announce("eff_dim", p, m, s, seed)
+    C, X, gam, fo, net, kern, f = setup_case(p, m, s, seed)
+    ft = net.forward(f)
+    res = net.eff_dim(kern, ft)
+    co = kernel.spline_coef_dense(p, m, 2.0, gam, X, fo)
+    trc, sup = anova.variances_direct(p, m, 2.0, gam, X, co)
+    assert np.allclose(res["var_trc"], trc, rtol=1e-5, atol=1e-7 * trc[s])
+    assert np.allclose(res["var_sup"], sup, rtol=1e-5, atol=1e-7 * trc[s])
+    assert res["var_total"] == pytest.approx(trc[s], rel=1e-5)
+    assert res["var_qmc"] == pytest.approx(anova.var_qmc(fo), rel=1e-5)
+    dt, ds = anova.effective_dims(trc, sup)
+    assert (res["d_trc"], res["d_sup"]) == (dt, ds)
+    assert res["var_total"] - res["var_total_h0"] <= res["var_qmc"] * (1 + 1e-6)
+
+
+def test_kernel_section_closed_form():
+    """f = K(., x_v): every variance has the closed form of the kernel
+    section (Section 4 product structure)."""
+    p, m, s = 2, 9, 5
+    announce("kernel section", p, m, s)
+    C = inputs.upper_triangular_generators(p, m, s, 9)
+    X = onet.net_int(p, m, C)
+    gam = inputs.kernel_weights(s, q=-1.0, beta=0.8)
+    fo = kernel.kernel_K(p, 2.0, gam, m, X, X[:, 7:8])
+    net = fdwt.Net(p, m, s, C)
+    kern = fdwt.Kernel(2.0, gam)
+    ft = net.forward(torch.from_numpy(fo).float().cuda())
+    res = net.eff_dim(kern, ft)
+    r0 = gam ** 2 * kernel.rprime_closed(p, 2.0, 0)
+    e = anova.esp(list(r0))
+    for d in range(1, s + 1):
+        assert res["var_trc"][d] == pytest.approx(np.prod(1 + r0[:d]) - 1, rel=1e-5)
+        assert res["var_sup"][d] == pytest.approx(sum(e[1:d + 1]), rel=1e-5)
+
+
+@pytest.mark.parametrize("p,m,s", [(2, 16, 10), (3, 10, 6)])
+def test_effdim_invariants_at_scale(p, m, s):
+    """Chain 0 <= trc <= sup <= total, monotone, the QMC bound, and the
+    product-function analytic ANOVA as a loose sanity check."""
+    announce("eff_dim invariants", p, m, s)
+    C = inputs.upper_triangular_generators(p, m, s, 40 + m)
+    a = inputs.family_params("product", s, alpha=2.0)
+    net = fdwt.Net(p, m, s, C)
+    kern = fdwt.Kernel(2.0, inputs.kernel_weights(s))
+    f = net.sample("product", a)
+    res = net.eff_dim(kern, net.forward(f))
+    trc, sup = res["var_trc"], res["var_sup"]
+    tol = 1e-6 * res["var_total"]
+    assert np.all(np.diff(trc) >= -tol) and np.all(np.diff(sup) >= -tol)
+    assert np.all(trc <= sup + tol)
+    assert res["var_total"] - res["var_total_h0"] <= res["var_qmc"] * (1 + 1e-6)
+    _, _, total = anova.product_anova(anova.product_family_component_variance(a))
+    assert 0.5 * total <= res["var_total"] <= 1.5 * total
+
+
+def test_prime_three_full_size_interpolation():
+    """p = 3, m = 14, s = 10 with 65536 queries: Sf reproduces the data at
+    sampled net points (queries lifted to depth 20), and the queries run."""
+    p, m, s = 3, 14, 10
+    announce("full p3 interp")
+    C = inputs.upper_triangular_generators(p, m, s, 3)
+    idx = sample_indices(p ** m, 256, 1)
+    x_all = onet.net_points(p, m, C)
+    a = 1.0 / np.arange(1, s + 1) ** 2
+    fo = families.product(x_all, a)
+    net = fdwt.Net(p, m, s, C)
+    kern = fdwt.Kernel(2.0, inputs.kernel_weights(s))
+    Q = inputs.queries(p, s, 65536, 3).astype(np.int64)
+    Qn = kernel.to_depth(p, m, 20, onet.net_int(p, m, C, idx))
+    Qall = np.concatenate([Q, Qn], axis=1)
+    qd = torch.from_numpy(Qall.astype(np.uint32).view(np.int32)).cuda()
+    c, sf = net.walsh_interp(kern, torch.from_numpy(fo).float().cuda(), qd)
+    sf = sf.cpu().numpy()
+    assert nrel(sf[-len(idx):], fo[idx]) <= 1e-5
+    assert np.all(np.isfinite(sf))
