@@ -168,11 +168,38 @@ def dwt_direct(p, m, C, f, hs=None, reps=None):
     return out
 
 
+_DIGIT_CACHE = {}
+
+
+def _all_index_digits(p, m):
+    """Digits n_i of every index n < p^m as an int8 array (m, N), computed
+    once per (p, m) and reused across coefficients."""
+    key = (p, m)
+    if key not in _DIGIT_CACHE:
+        _DIGIT_CACHE.clear()
+        N = p ** m
+        nd = np.empty((m, N), dtype=np.int8)
+        q = np.arange(N, dtype=np.int64)
+        for i in range(m):
+            nd[i] = q % p
+            q //= p
+        _DIGIT_CACHE[key] = nd
+    return _DIGIT_CACHE[key]
+
+
 def phase_exponents(p, m, n, h):
     """n_vec . h_vec (mod p) for arrays of indices n and one label h."""
+    hd = int_digits(p, h, m)
+    if isinstance(n, np.ndarray) and n.shape == (p ** m,) and n[0] == 0 and n[-1] == p ** m - 1:
+        nd = _all_index_digits(p, m)
+        e = np.zeros(p ** m, dtype=np.int16)
+        for i in range(m):
+            if hd[i]:
+                e += nd[i].astype(np.int16) * np.int16(hd[i])
+                e %= p
+        return e
     nd = index_digits(p, m, n)
-    hd = np.array(int_digits(p, h, m), dtype=np.int64)
-    return (nd @ hd) % p
+    return (nd @ np.array(hd, dtype=np.int64)) % p
 
 
 def dwt_phase(p, m, f, hs, normalise=True):

@@ -19,6 +19,9 @@ def nrel(a, b):
 
 
 def sample_indices(N, k, seed):
+    """k random indices plus the corners; k is capped so that the oracle's
+    O(N) per-coefficient sums stay within seconds at large N."""
+    k = int(min(k, max(12, 4e8 // max(N, 1))))
     g = np.random.default_rng(seed)
     idx = np.unique(np.concatenate([[0, N - 1, 1, N // 2], g.integers(0, N, k)]))
     return idx[idx < N]

