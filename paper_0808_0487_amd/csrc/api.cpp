@@ -4,7 +4,9 @@
 #include <cmath>
 #include <cstring>
 #include <exception>
+#include <mutex>
 #include <new>
+#include <unordered_set>
 
 #include "fdwt_internal.h"
 
@@ -25,6 +27,17 @@ int64_t ipow(int64_t b, int e) {
   int64_t r = 1;
   for (int i = 0; i < e; ++i) r *= b;
   return r;
+}
+
+int allow_lds(const void* fn, size_t bytes) {
+  static std::mutex mu;
+  static std::unordered_set<const void*> done;
+  if (bytes <= 65536) return FDWT_OK;
+  std::lock_guard<std::mutex> g(mu);
+  if (done.count(fn)) return FDWT_OK;
+  FDWT_HIP(hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes));
+  done.insert(fn);
+  return FDWT_OK;
 }
 
 int query_depth(int p) { return p == 2 ? 32 : (p == 3 ? 20 : (p == 5 ? 13 : 0)); }

@@ -1,16 +1,27 @@
-// Device arithmetic for the transform element types: float, uint32 (mod 2^32),
-// complex float (float2), double-float (df) and complex double-float (cdf),
-// plus the radix-p DFT codelets the butterfly stages apply.
+// Device arithmetic for the transform element types -- float, uint32 (mod
+// 2^32), complex float (float2), double and complex double (double2) -- the
+// radix-p DFT codelets the butterfly stages apply, and a double-float pair
+// (df) used for compensated partial sums.
 #pragma once
 
 #include "fdwt_internal.h"
 
 namespace fdwt {
 
+// Workgroup barrier that orders LDS only.  __syncthreads() fences every
+// address space, which makes each wave wait for all of its outstanding global
+// loads and stores at the barrier; the transform passes only exchange data
+// through LDS, so their barriers wait for LDS traffic alone and global
+// prefetches stay in flight across them.
+__device__ __forceinline__ void lds_barrier() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+  __builtin_amdgcn_s_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+}
+
 // ---------------------------------------------------------- double-float
-// Error-free transformations (Knuth's TwoSum, Dekker's FastTwoSum, and the
-// FMA-based exact product).  Contraction is switched off so the compiler
-// keeps every rounding step as written.
+// Error-free transformations (Knuth's TwoSum, Dekker's FastTwoSum).
+// Contraction is switched off so the compiler keeps every rounding step.
 __device__ __forceinline__ df two_sum(float a, float b) {
 #pragma clang fp contract(off)
   float s = a + b;
@@ -33,19 +44,6 @@ __device__ __forceinline__ df add(df a, df b) {
   s.lo += t.lo;
   return fast_two_sum(s.hi, s.lo);
 }
-__device__ __forceinline__ df neg(df a) { return {-a.hi, -a.lo}; }
-__device__ __forceinline__ df sub(df a, df b) { return add(a, neg(b)); }
-__device__ __forceinline__ df mul(df a, df b) {
-#pragma clang fp contract(off)
-  float p = a.hi * b.hi;
-  float e = __builtin_fmaf(a.hi, b.hi, -p);
-  e = __builtin_fmaf(a.hi, b.lo, e);
-  e = __builtin_fmaf(a.lo, b.hi, e);
-  return fast_two_sum(p, e);
-}
-__device__ __forceinline__ df scale(df a, df c) { return mul(a, c); }
-__device__ __forceinline__ df half(df a) { return {0.5f * a.hi, 0.5f * a.lo}; }
-__device__ __forceinline__ df df_from(float v) { return {v, 0.0f}; }
 __device__ __forceinline__ double to_double(df a) { return (double)a.hi + (double)a.lo; }
 
 // ----------------------------------------------------------- plain types
@@ -63,23 +61,19 @@ __device__ __forceinline__ float2 add_i(float2 a, float2 b, int sg) {
   return sg > 0 ? make_float2(a.x - b.y, a.y + b.x) : make_float2(a.x + b.y, a.y - b.x);
 }
 
-__device__ __forceinline__ cdf add(cdf a, cdf b) { return {add(a.re, b.re), add(a.im, b.im)}; }
-__device__ __forceinline__ cdf sub(cdf a, cdf b) { return {sub(a.re, b.re), sub(a.im, b.im)}; }
-__device__ __forceinline__ cdf scale(cdf a, df c) { return {mul(a.re, c), mul(a.im, c)}; }
-__device__ __forceinline__ cdf half(cdf a) { return {half(a.re), half(a.im)}; }
-__device__ __forceinline__ cdf add_i(cdf a, cdf b, int sg) {
-  return sg > 0 ? cdf{sub(a.re, b.im), add(a.im, b.re)} : cdf{add(a.re, b.im), sub(a.im, b.re)};
+__device__ __forceinline__ double add(double a, double b) { return a + b; }
+__device__ __forceinline__ double sub(double a, double b) { return a - b; }
+__device__ __forceinline__ double2 add(double2 a, double2 b) { return make_double2(a.x + b.x, a.y + b.y); }
+__device__ __forceinline__ double2 sub(double2 a, double2 b) { return make_double2(a.x - b.x, a.y - b.y); }
+__device__ __forceinline__ double2 scale(double2 a, double c) { return make_double2(a.x * c, a.y * c); }
+__device__ __forceinline__ double2 half(double2 a) { return make_double2(0.5 * a.x, 0.5 * a.y); }
+__device__ __forceinline__ double2 add_i(double2 a, double2 b, int sg) {
+  return sg > 0 ? make_double2(a.x - b.y, a.y + b.x) : make_double2(a.x + b.y, a.y - b.x);
 }
 
 // ---------------------------------------------------- codelet constants
-// Real constants of the p-point DFT, as float and as double-float
-// (hi = nearest float, lo = nearest float to the remainder).
-struct DfConst {
-  float hi, lo;
-};
-constexpr DfConst mkdf(double v) {
-  return DfConst{(float)v, (float)(v - (double)(float)v)};
-}
+// Real constants of the p-point DFT (values of sin and cos at multiples of
+// 2 pi / p), converted to the element's real type.
 constexpr double kSin60 = 0.86602540378443864676;   // sin(2 pi / 3)
 constexpr double kCos72 = 0.30901699437494742410;   // cos(2 pi / 5)
 constexpr double kSin72 = 0.95105651629515357212;   // sin(2 pi / 5)
@@ -91,14 +85,12 @@ struct RealOf;
 template <>
 struct RealOf<float2> {
   using T = float;
-  static __device__ __forceinline__ float k(double v, DfConst) { return (float)v; }
 };
 template <>
-struct RealOf<cdf> {
-  using T = df;
-  static __device__ __forceinline__ df k(double, DfConst c) { return df{c.hi, c.lo}; }
+struct RealOf<double2> {
+  using T = double;
 };
-#define FDWT_K(C, v) RealOf<C>::k(v, mkdf(v))
+#define FDWT_K(C, v) ((typename RealOf<C>::T)(v))
 
 // p-point DFT of x[0], x[st], ..., x[(p-1) st] in place:
 //   y_h = sum_n x_n w^(n h),  w = exp(-2 pi i / p) (forward) or exp(+2 pi i / p)

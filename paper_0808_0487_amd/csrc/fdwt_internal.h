@@ -33,10 +33,6 @@ constexpr int kMaxLog2N = 26;
 struct df {
   float hi, lo;
 };
-// Complex double-float.
-struct cdf {
-  df re, im;
-};
 
 // ------------------------------------------------------------------- net
 struct Net {
@@ -67,6 +63,8 @@ struct fdwt_net {
 namespace fdwt {
 
 int64_t ipow(int64_t b, int e);
+// Allows a kernel more than the default 64 KiB of dynamic LDS (once per kernel).
+int allow_lds(const void* fn, size_t bytes);
 int ensure_ws(Net& net, size_t bytes, hipStream_t st);
 int ensure_pin(Net& net, size_t bytes);
 int pin_acquire(Net& net);          // waits until `pin` is free again
@@ -80,12 +78,12 @@ int launch_net_packed(const Net& net, void* out, hipStream_t st);  // p=2: uint3
 int launch_sample(const Net& net, int family, const double* a, float* f, hipStream_t st);
 
 // fwt.hip: element kinds
-enum Kind { K_F32 = 0, K_U32 = 1, K_CF32 = 2, K_DF = 3, K_CDF = 4 };
+enum Kind { K_F32 = 0, K_U32 = 1, K_CF32 = 2, K_F64 = 3, K_CF64 = 4 };
 size_t kind_bytes(Kind k);
 // Transform `batch` columns of N elements (column stride = N elements of the
 // respective type).  in_kind may differ from the working kind only as
-// F32 -> CF32 (p odd, real input) and DF -> CDF (p odd, real double-float
-// input).  out_kind may differ only as CF32 -> F32 and CDF -> DF (real part).
+// F32 -> CF32 and F64 -> CF64 (p odd, real input).  out_kind may differ only
+// as CF32 -> F32 and CF64 -> F64 (real part).
 // scale multiplies float-based outputs of the last pass (1 = none).
 int fwt_run(int p, int m, bool inverse, Kind in_kind, const void* in, Kind work_kind,
             Kind out_kind, void* out, int batch, float scale, hipStream_t st);

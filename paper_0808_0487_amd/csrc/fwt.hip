@@ -14,6 +14,7 @@
 #include "dev_math.h"
 
 #include <algorithm>
+#include <map>
 #include <mutex>
 #include <unordered_set>
 
@@ -24,8 +25,8 @@ size_t kind_bytes(Kind k) {
     case K_F32: return 4;
     case K_U32: return 4;
     case K_CF32: return 8;
-    case K_DF: return 8;
-    case K_CDF: return 16;
+    case K_F64: return 8;
+    case K_CF64: return 16;
   }
   return 0;
 }
@@ -42,8 +43,20 @@ struct PassDesc {
   int32_t E;        // tile size p^r * w
   int32_t kreg;     // digits per register group
   int32_t xcd;      // 1: consecutive tiles are kept on one XCD
+  int32_t ntiles;   // tiles per column
+  int32_t batch;    // columns
   float scale;      // multiplies float-based outputs (last pass only)
+  // Grouped-sum epilogue (EPI_REDUCE): instead of storing, accumulate
+  // sum_h wts[h].x * clamp(value(h) * wts[h].y, 0, 1) per column into
+  // partial[col * ntiles + tile]; the value at h = 0 of column h0_col goes to
+  // *h0_out as well.
+  const float2* wts;
+  double* partial;
+  double* h0_out;
+  int32_t h0_col;
 };
+
+enum Epilogue { EPI_STORE = 0, EPI_REDUCE = 1 };
 
 // ------------------------------------------------------------ conversions
 template <class Tin, class T>
@@ -52,9 +65,9 @@ template <> __device__ __forceinline__ float cvt_in<float, float>(float v) { ret
 template <> __device__ __forceinline__ uint32_t cvt_in<uint32_t, uint32_t>(uint32_t v) { return v; }
 template <> __device__ __forceinline__ float2 cvt_in<float, float2>(float v) { return make_float2(v, 0.0f); }
 template <> __device__ __forceinline__ float2 cvt_in<float2, float2>(float2 v) { return v; }
-template <> __device__ __forceinline__ df cvt_in<df, df>(df v) { return v; }
-template <> __device__ __forceinline__ cdf cvt_in<df, cdf>(df v) { return cdf{v, df{0.0f, 0.0f}}; }
-template <> __device__ __forceinline__ cdf cvt_in<cdf, cdf>(cdf v) { return v; }
+template <> __device__ __forceinline__ double cvt_in<double, double>(double v) { return v; }
+template <> __device__ __forceinline__ double2 cvt_in<double, double2>(double v) { return make_double2(v, 0.0); }
+template <> __device__ __forceinline__ double2 cvt_in<double2, double2>(double2 v) { return v; }
 
 template <class T, class Tout>
 __device__ __forceinline__ Tout cvt_out(T v, float sc);
@@ -62,9 +75,16 @@ template <> __device__ __forceinline__ float cvt_out<float, float>(float v, floa
 template <> __device__ __forceinline__ uint32_t cvt_out<uint32_t, uint32_t>(uint32_t v, float) { return v; }
 template <> __device__ __forceinline__ float2 cvt_out<float2, float2>(float2 v, float sc) { return make_float2(v.x * sc, v.y * sc); }
 template <> __device__ __forceinline__ float cvt_out<float2, float>(float2 v, float sc) { return v.x * sc; }
-template <> __device__ __forceinline__ df cvt_out<df, df>(df v, float) { return v; }
-template <> __device__ __forceinline__ cdf cvt_out<cdf, cdf>(cdf v, float) { return v; }
-template <> __device__ __forceinline__ df cvt_out<cdf, df>(cdf v, float) { return v.re; }
+template <> __device__ __forceinline__ double cvt_out<double, double>(double v, float) { return v; }
+template <> __device__ __forceinline__ double2 cvt_out<double2, double2>(double2 v, float) { return v; }
+template <> __device__ __forceinline__ double cvt_out<double2, double>(double2 v, float) { return v.x; }
+
+// Real part as double (the grouped-sum epilogue).
+__device__ __forceinline__ double real_of(double v) { return v; }
+__device__ __forceinline__ double real_of(double2 v) { return v.x; }
+__device__ __forceinline__ double real_of(float v) { return v; }
+__device__ __forceinline__ double real_of(float2 v) { return v.x; }
+__device__ __forceinline__ double real_of(uint32_t v) { return (double)v; }
 
 // LDS index with one padding element per 32 (spreads the stride-p^k
 // register-group accesses over the banks).
@@ -126,48 +146,260 @@ __device__ __forceinline__ void run_group(T* lds, const PassDesc& d, int q) {
   }
 }
 
-template <int P, bool INV, class Tin, class T, class Tout, int KMAX>
+// A pass is a persistent kernel: each workgroup walks over logical blocks
+// (tile, column) with stride gridDim.x.  The next tile's elements are loaded
+// into registers right after the current tile is in LDS, so the HBM reads of
+// tile k+1 overlap the butterflies and stores of tile k.
+template <int P, bool INV, class Tin, class T, class Tout, int KMAX, int EPI>
 __global__ void __launch_bounds__(1024) fwt_pass(const Tin* __restrict__ in, Tout* out, PassDesc d) {
+  constexpr int RMAX = PowC<P, KMAX>::v;  // elements each thread loads per tile
   extern __shared__ __align__(16) unsigned char smem_raw[];
   T* lds = reinterpret_cast<T*>(smem_raw);
-  int b = blockIdx.x;
-  if (d.xcd) {
-    // Workgroups are dispatched round-robin over the 8 XCDs; remap so that
-    // consecutive tiles (which share cache lines at tile edges and DRAM pages)
-    // run on the same XCD and share its L2.
-    const int nb = gridDim.x;
-    b = (b & 7) * (nb >> 3) + (b >> 3);
-  }
-  const int lo = b % d.nlo;
-  const int hi = b / d.nlo;
-  const int64_t base = (int64_t)lo * d.w + (int64_t)hi * d.shi;
-  const Tin* src = in + (int64_t)blockIdx.y * d.col_in + base;
-  Tout* dst = out + (int64_t)blockIdx.y * d.col_out + base;
+  const int G = gridDim.x;
+  const int nb = d.ntiles * d.batch;
+  // Workgroups are dispatched round-robin over the 8 XCDs; with xcd set, XCD x
+  // takes the contiguous logical range [x G/8, (x+1) G/8) of every round, so
+  // neighbouring tiles (which share cache lines and DRAM pages, and for the
+  // grouped-sum epilogue the weights of a tile) meet in the same L2.
+  const int hw = blockIdx.x;
+  int lb = d.xcd ? ((hw & 7) * (G >> 3) + (hw >> 3)) : hw;
 
-  for (int e = threadIdx.x; e < d.E; e += blockDim.x) {
-    const int c = Ix<P>::mod(e, d.wdig, d.w);
-    const int i = Ix<P>::div(e, d.wdig, d.w);
-    lds[pad(e)] = cvt_in<Tin, T>(src[c + (int64_t)i * d.sd0]);
+  auto locate = [&](int l, int& col, int& tile) {
+    if (EPI == EPI_REDUCE) {
+      col = l % d.batch;
+      tile = l / d.batch;
+    } else {
+      col = l / d.ntiles;
+      tile = l % d.ntiles;
+    }
+  };
+  auto tile_base = [&](int tile) {
+    const int lo = tile % d.nlo;
+    const int hi = tile / d.nlo;
+    return (int64_t)lo * d.w + (int64_t)hi * d.shi;
+  };
+  Tin pre[RMAX];
+  // Branch-free loads (indices past the tile end re-read its last element),
+  // so the loads of a tile are all in flight together.  Offsets within a
+  // column fit in 32 bits (N <= 2^26).
+  auto prefetch = [&](int l) {
+    int col, tile;
+    locate(l, col, tile);
+    const Tin* src = in + (int64_t)col * d.col_in + tile_base(tile);
+    const uint32_t sd0 = (uint32_t)d.sd0;
+#pragma unroll
+    for (int k = 0; k < RMAX; ++k) {
+      const int e = min((int)threadIdx.x + k * (int)blockDim.x, d.E - 1);
+      const uint32_t c = (uint32_t)Ix<P>::mod(e, d.wdig, d.w);
+      const uint32_t i = (uint32_t)Ix<P>::div(e, d.wdig, d.w);
+      pre[k] = src[c + i * sd0];
+    }
+  };
+  double* red = reinterpret_cast<double*>(smem_raw + (size_t)(d.E + d.E / 32 + 1) * sizeof(T) + 8 -
+                                          ((d.E + d.E / 32 + 1) * sizeof(T)) % 8);
+  if (lb < nb) prefetch(lb);
+  for (; lb < nb; lb += G) {
+    // Clamped indices write the tile's last element again, with its value.
+#pragma unroll
+    for (int k = 0; k < RMAX; ++k) {
+      const int e = min((int)threadIdx.x + k * (int)blockDim.x, d.E - 1);
+      lds[pad(e)] = cvt_in<Tin, T>(pre[k]);
+    }
+    lds_barrier();
+    if (lb + G < nb) prefetch(lb + G);
+    for (int q = 0; q < d.r; q += d.kreg) {
+      const int kk = min(d.kreg, d.r - q);
+      if constexpr (KMAX >= 4) {
+        if (kk == 4) run_group<P, INV, T, 4>(lds, d, q);
+      }
+      if constexpr (KMAX >= 3) {
+        if (kk == 3) run_group<P, INV, T, 3>(lds, d, q);
+      }
+      if constexpr (KMAX >= 2) {
+        if (kk == 2) run_group<P, INV, T, 2>(lds, d, q);
+      }
+      if (kk == 1) run_group<P, INV, T, 1>(lds, d, q);
+      lds_barrier();
+    }
+    int col, tile;
+    locate(lb, col, tile);
+    const int64_t base = tile_base(tile);
+    if constexpr (EPI == EPI_STORE) {
+      Tout* dst = out + (int64_t)col * d.col_out + base;
+      const uint32_t sd0 = (uint32_t)d.sd0;
+      for (int e = threadIdx.x; e < d.E; e += blockDim.x) {
+        const uint32_t c = (uint32_t)Ix<P>::mod(e, d.wdig, d.w);
+        const uint32_t i = (uint32_t)Ix<P>::div(e, d.wdig, d.w);
+        dst[c + i * sd0] = cvt_out<T, Tout>(lds[pad(e)], d.scale);
+      }
+    } else {
+      double acc = 0.0;
+      for (int e = threadIdx.x; e < d.E; e += blockDim.x) {
+        const int c = Ix<P>::mod(e, d.wdig, d.w);
+        const int i = Ix<P>::div(e, d.wdig, d.w);
+        const int64_t h = base + c + (int64_t)i * d.sd0;
+        const float2 wt = d.wts[h];
+        const double rho = fmin(fmax(real_of(lds[pad(e)]) * (double)wt.y, 0.0), 1.0);
+        const double term = (double)wt.x * rho;
+        acc += term;
+        if (h == 0 && col == d.h0_col) *d.h0_out = term;
+      }
+      // Wave sums by butterfly shuffles, then the waves in a fixed order.
+      for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off);
+      if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = acc;
+      lds_barrier();
+      if (threadIdx.x == 0) {
+        double t = 0.0;
+        for (int w = 0; w < (int)(blockDim.x >> 6); ++w) t += red[w];
+        d.partial[(int64_t)col * d.ntiles + tile] = t;
+      }
+    }
+    lds_barrier();
   }
-  __syncthreads();
-  for (int q = 0; q < d.r; q += d.kreg) {
-    const int kk = min(d.kreg, d.r - q);
-    if constexpr (KMAX >= 4) {
-      if (kk == 4) run_group<P, INV, T, 4>(lds, d, q);
+}
+
+// -------------------------------------------- p = 2 passes, static shape
+// For p = 2 the tile shape (2^LOGE elements, rows of 2^WDIG contiguous
+// elements) is a template parameter, so every LDS and global offset inside a
+// tile is a compile-time constant added to a per-thread base: the per-element
+// work is the butterfly itself.  Padded LDS index pad(e) = e + e/32; for the
+// element sets used here pad(e0 + j*stride) = pad(e0) + pad(j*stride) holds
+// exactly (checked exhaustively for every shape), so the offsets fold.
+__host__ __device__ constexpr int cpad(int e) { return e + (e >> 5); }
+__host__ __device__ constexpr int cilog2(int v) { return v <= 1 ? 0 : 1 + cilog2(v >> 1); }
+__host__ __device__ constexpr int cmin(int a, int b) { return a < b ? a : b; }
+
+template <int LOGE, int WDIG>
+struct P2Shape {
+  static constexpr int E = 1 << LOGE;
+  static constexpr int W = 1 << WDIG;
+  static constexpr int RD = LOGE - WDIG;                 // digits transformed
+  static constexpr int THREADS = E / 16 < 64 ? 64 : (E / 16 > 1024 ? 1024 : E / 16);
+  static constexpr int EPT = E / THREADS;                // elements per thread
+  static constexpr int KGMAX = cmin(4, cilog2(EPT));     // digits per register group
+  static_assert(EPT >= 2 && THREADS % W == 0, "unsupported shape");
+};
+
+// Register groups over row digits [Q, Q+KG), then the next group.
+template <int LOGE, int WDIG, int Q, class T, bool DONE = (Q >= P2Shape<LOGE, WDIG>::RD)>
+struct P2Groups {
+  static __device__ __forceinline__ void run(T* lds, int tid) {
+    using S = P2Shape<LOGE, WDIG>;
+    constexpr int KG = cmin(S::KGMAX, S::RD - Q);
+    constexpr int R = 1 << KG;
+    constexpr int STQ = S::W << Q;                      // element stride of digit Q
+    constexpr int GPT = (S::E >> KG) / S::THREADS;      // groups per thread
+#pragma unroll
+    for (int t = 0; t < GPT; ++t) {
+      const int g = tid + t * S::THREADS;
+      const int c = g & (S::W - 1);
+      const int rem = g >> WDIG;
+      const int il = rem & ((1 << Q) - 1);
+      const int ih = rem >> Q;
+      const int e0 = c + S::W * (il + (ih << (Q + KG)));
+      T* base = lds + cpad(e0);
+      T x[R];
+#pragma unroll
+      for (int j = 0; j < R; ++j) x[j] = base[cpad(j * STQ)];
+#pragma unroll
+      for (int b = 0; b < KG; ++b) {
+#pragma unroll
+        for (int j0 = 0; j0 < R; ++j0) {
+          if (((j0 >> b) & 1) == 0) {
+            const T u = x[j0], v = x[j0 + (1 << b)];
+            x[j0] = add(u, v);
+            x[j0 + (1 << b)] = sub(u, v);
+          }
+        }
+      }
+#pragma unroll
+      for (int j = 0; j < R; ++j) base[cpad(j * STQ)] = x[j];
     }
-    if constexpr (KMAX >= 3) {
-      if (kk == 3) run_group<P, INV, T, 3>(lds, d, q);
-    }
-    if constexpr (KMAX >= 2) {
-      if (kk == 2) run_group<P, INV, T, 2>(lds, d, q);
-    }
-    if (kk == 1) run_group<P, INV, T, 1>(lds, d, q);
-    __syncthreads();
+    lds_barrier();
+    P2Groups<LOGE, WDIG, Q + KG, T>::run(lds, tid);
   }
-  for (int e = threadIdx.x; e < d.E; e += blockDim.x) {
-    const int c = Ix<P>::mod(e, d.wdig, d.w);
-    const int i = Ix<P>::div(e, d.wdig, d.w);
-    dst[c + (int64_t)i * d.sd0] = cvt_out<T, Tout>(lds[pad(e)], d.scale);
+};
+template <int LOGE, int WDIG, int Q, class T>
+struct P2Groups<LOGE, WDIG, Q, T, true> {
+  static __device__ __forceinline__ void run(T*, int) {}
+};
+
+template <class Tin, class T, class Tout, int LOGE, int WDIG, int EPI>
+__global__ void __launch_bounds__((P2Shape<LOGE, WDIG>::THREADS))
+    fwt_p2(const Tin* __restrict__ in, Tout* out, PassDesc d) {
+  using S = P2Shape<LOGE, WDIG>;
+  constexpr int EPT = S::EPT, TH = S::THREADS;
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  T* lds = reinterpret_cast<T*>(smem_raw);
+  double* red = reinterpret_cast<double*>(smem_raw + ((cpad(S::E) * sizeof(T) + 15) & ~(size_t)15));
+  const int G = gridDim.x;
+  const int nb = d.ntiles * d.batch;
+  const int hw = blockIdx.x;
+  int lb = d.xcd ? ((hw & 7) * (G >> 3) + (hw >> 3)) : hw;
+  const int tid = threadIdx.x;
+  // Element e = tid + k*TH of a tile: row i = e >> WDIG, column e & (W-1);
+  // global offset goff0 + k*gstep, LDS index pad(tid) + pad(k*TH).
+  const uint32_t sd0 = (uint32_t)d.sd0;
+  const uint32_t goff0 = (uint32_t)(tid & (S::W - 1)) + (uint32_t)(tid >> WDIG) * sd0;
+  const uint32_t gstep = (uint32_t)(TH >> WDIG) * sd0;
+  T* lrow = lds + cpad(tid);
+  auto locate = [&](int l, int& col, int& tile) {
+    if (EPI == EPI_REDUCE) {
+      col = l % d.batch;
+      tile = l / d.batch;
+    } else {
+      col = l / d.ntiles;
+      tile = l % d.ntiles;
+    }
+  };
+  auto tile_base = [&](int tile) {
+    const int lo = tile % d.nlo;
+    const int hi = tile / d.nlo;
+    return (int64_t)lo * S::W + (int64_t)hi * d.shi;
+  };
+  Tin pre[EPT];
+  auto prefetch = [&](int l) {
+    int col, tile;
+    locate(l, col, tile);
+    const Tin* src = in + (int64_t)col * d.col_in + tile_base(tile) + goff0;
+#pragma unroll
+    for (int k = 0; k < EPT; ++k) pre[k] = src[k * gstep];
+  };
+  if (lb < nb) prefetch(lb);
+  for (; lb < nb; lb += G) {
+#pragma unroll
+    for (int k = 0; k < EPT; ++k) lrow[cpad(k * TH)] = cvt_in<Tin, T>(pre[k]);
+    lds_barrier();
+    if (lb + G < nb) prefetch(lb + G);
+    P2Groups<LOGE, WDIG, 0, T>::run(lds, tid);
+    int col, tile;
+    locate(lb, col, tile);
+    const int64_t base = tile_base(tile);
+    if constexpr (EPI == EPI_STORE) {
+      Tout* dst = out + (int64_t)col * d.col_out + base + goff0;
+#pragma unroll
+      for (int k = 0; k < EPT; ++k) dst[k * gstep] = cvt_out<T, Tout>(lrow[cpad(k * TH)], d.scale);
+    } else {
+      double acc = 0.0;
+      const float2* wt = d.wts + base + goff0;
+#pragma unroll
+      for (int k = 0; k < EPT; ++k) {
+        const float2 w2 = wt[k * gstep];
+        const double rho = fmin(fmax(real_of(lrow[cpad(k * TH)]) * (double)w2.y, 0.0), 1.0);
+        const double term = (double)w2.x * rho;
+        acc += term;
+        if (col == d.h0_col && base + goff0 + (int64_t)k * gstep == 0) *d.h0_out = term;
+      }
+      for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off);
+      if ((tid & 63) == 0) red[tid >> 6] = acc;
+      lds_barrier();
+      if (tid == 0) {
+        double t = 0.0;
+        for (int w = 0; w < TH / 64; ++w) t += red[w];
+        d.partial[(int64_t)col * d.ntiles + tile] = t;
+      }
+    }
+    lds_barrier();
   }
 }
 
@@ -176,7 +408,17 @@ struct PassGeom {
   int d0, r, wdig;
 };
 
-static constexpr size_t kLdsBudget = 80 * 1024;  // two workgroups per CU
+// LDS per workgroup: 80 KiB lets two workgroups share a CU (160 KiB of LDS).
+// Elements of 8 bytes or more may take a whole CU so that m = 24 still needs
+// only two passes; FDWT_LDS_KB_WIDE overrides that budget (KiB).
+static size_t lds_budget(size_t bytes) {
+  static const size_t wide = [] {
+    const char* e = getenv("FDWT_LDS_KB_WIDE");
+    const long v = e ? atol(e) : 80;
+    return (size_t)std::max(16L, std::min(160L, v)) * 1024;
+  }();
+  return bytes >= 8 ? wide : (size_t)80 * 1024;
+}
 
 static int kreg_for(int p, Kind work) {
   if (p == 2) return 4;
@@ -186,10 +428,11 @@ static int kreg_for(int p, Kind work) {
 
 static std::vector<PassGeom> plan(int p, int m, size_t bytes) {
   // Largest tile exponent e with the padded tile within the LDS budget.
+  const size_t budget = lds_budget(bytes);
   int emax = 0;
   for (int e = 1; e <= 30; ++e) {
     int64_t E = ipow(p, e);
-    if ((size_t)(E + E / 32 + 1) * bytes > kLdsBudget) break;
+    if ((size_t)(E + E / 32 + 1) * bytes > budget) break;
     emax = e;
   }
   int wpref = 0;
@@ -212,22 +455,37 @@ static std::vector<PassGeom> plan(int p, int m, size_t bytes) {
   return out;
 }
 
-template <class F>
-static int set_lds_attr(F* fn, size_t bytes) {
+static int set_lds_attr(const void* fn, size_t bytes) { return allow_lds(fn, bytes); }
+
+// Compute units of the current device (cached per device).
+static int device_cus() {
   static std::mutex mu;
-  static std::unordered_set<const void*> done;
+  static std::vector<int> cache;
+  int dev = 0;
+  (void)hipGetDevice(&dev);
   std::lock_guard<std::mutex> g(mu);
-  if (bytes <= 65536 || done.count((const void*)fn)) return FDWT_OK;
-  FDWT_HIP(hipFuncSetAttribute((const void*)fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes));
-  done.insert((const void*)fn);
-  return FDWT_OK;
+  if ((int)cache.size() <= dev) cache.resize(dev + 1, 0);
+  if (!cache[dev]) {
+    int n = 0;
+    if (hipDeviceGetAttribute(&n, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || n <= 0) n = 256;
+    cache[dev] = n;
+  }
+  return cache[dev];
 }
+
+// Optional grouped-sum epilogue of the last pass.
+struct ReduceArgs {
+  const float2* wts;
+  double* partial;  // [batch][ntiles of the last pass]
+  double* h0_out;
+  int h0_col;
+};
 
 template <int P, bool INV, class Tin, class T, class Tout>
 static int launch_pass(const void* in, void* out, const PassGeom& g, int m, int batch, float scale,
-                       int64_t col_in, int64_t col_out, Kind work, hipStream_t st) {
+                       int64_t col_in, int64_t col_out, Kind work, const ReduceArgs* red, hipStream_t st) {
   constexpr int KMAX = (P == 2) ? 4 : ((P == 3 || sizeof(T) <= 8) ? 2 : 1);
-  PassDesc d;
+  PassDesc d{};
   d.col_in = col_in;
   d.col_out = col_out;
   d.sd0 = ipow(P, g.d0);
@@ -240,16 +498,40 @@ static int launch_pass(const void* in, void* out, const PassGeom& g, int m, int 
   d.kreg = std::min(kreg_for(P, work), KMAX);
   d.scale = scale;
   const int64_t ntiles = ipow(P, m) / d.E;
-  d.xcd = (ntiles % 8 == 0 && ntiles >= 64) ? 1 : 0;
+  const int64_t nb = ntiles * batch;
+  d.ntiles = (int)ntiles;
+  d.batch = batch;
+  if (red) {
+    d.wts = red->wts;
+    d.partial = red->partial;
+    d.h0_out = red->h0_out;
+    d.h0_col = red->h0_col;
+  } else {
+    d.h0_col = -1;
+  }
   const int R = (int)ipow(P, d.kreg);
   int threads = std::max(64, std::min(1024, (d.E + R - 1) / R));
   threads = (threads + 63) / 64 * 64;
-  const size_t lds = (size_t)(d.E + d.E / 32 + 1) * sizeof(T);
-  auto fn = fwt_pass<P, INV, Tin, T, Tout, KMAX>;
+  const size_t tile_bytes = (size_t)(d.E + d.E / 32 + 1) * sizeof(T);
+  const size_t lds = tile_bytes + 8 - tile_bytes % 8 + 16 * sizeof(double);
+  const void* fn = red ? (const void*)fwt_pass<P, INV, Tin, T, Tout, KMAX, EPI_REDUCE>
+                       : (const void*)fwt_pass<P, INV, Tin, T, Tout, KMAX, EPI_STORE>;
   int rc = set_lds_attr(fn, lds);
   if (rc) return rc;
-  hipLaunchKernelGGL(fn, dim3((unsigned)ntiles, (unsigned)batch), dim3(threads), lds, st,
-                     (const Tin*)in, (Tout*)out, d);
+  // Persistent grid: as many workgroups as fit on the device at once.
+  int per_cu = 0;
+  FDWT_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, threads, lds));
+  int64_t G = (int64_t)std::max(1, per_cu) * device_cus();
+  if (G >= nb) G = nb;
+  if (G >= 64) G -= G % 8;
+  d.xcd = (G % 8 == 0 && G >= 64) ? 1 : 0;
+  if (red) {
+    hipLaunchKernelGGL((fwt_pass<P, INV, Tin, T, Tout, KMAX, EPI_REDUCE>), dim3((unsigned)G), dim3(threads), lds,
+                       st, (const Tin*)in, (Tout*)out, d);
+  } else {
+    hipLaunchKernelGGL((fwt_pass<P, INV, Tin, T, Tout, KMAX, EPI_STORE>), dim3((unsigned)G), dim3(threads), lds,
+                       st, (const Tin*)in, (Tout*)out, d);
+  }
   FDWT_HIP(hipGetLastError());
   return FDWT_OK;
 }
@@ -257,25 +539,27 @@ static int launch_pass(const void* in, void* out, const PassGeom& g, int m, int 
 // Dispatch on (p, direction, in/work/out kinds).
 template <int P, bool INV>
 static int pass_dispatch(Kind ik, Kind wk, Kind ok, const void* in, void* out, const PassGeom& g,
-                         int m, int batch, float scale, int64_t ci, int64_t co, hipStream_t st) {
+                         int m, int batch, float scale, int64_t ci, int64_t co, const ReduceArgs* red,
+                         hipStream_t st) {
 #define FDWT_PASS(TIN, T, TOUT) \
-  return launch_pass<P, INV, TIN, T, TOUT>(in, out, g, m, batch, scale, ci, co, wk, st)
+  return launch_pass<P, INV, TIN, T, TOUT>(in, out, g, m, batch, scale, ci, co, wk, red, st)
   if constexpr (P == 2) {
-    if (wk == K_F32 && ik == K_F32 && ok == K_F32) FDWT_PASS(float, float, float);
-    if (wk == K_U32 && ik == K_U32 && ok == K_U32) FDWT_PASS(uint32_t, uint32_t, uint32_t);
-    if (wk == K_DF && ik == K_DF && ok == K_DF) FDWT_PASS(df, df, df);
+    if (!red) {
+      if (wk == K_F32 && ik == K_F32 && ok == K_F32) FDWT_PASS(float, float, float);
+      if (wk == K_U32 && ik == K_U32 && ok == K_U32) FDWT_PASS(uint32_t, uint32_t, uint32_t);
+    }
+    if (wk == K_F64 && ik == K_F64 && ok == K_F64) FDWT_PASS(double, double, double);
   } else {
-    if (wk == K_CF32) {
+    if (wk == K_CF32 && !red) {
       if (ik == K_F32 && ok == K_CF32) FDWT_PASS(float, float2, float2);
       if (ik == K_F32 && ok == K_F32) FDWT_PASS(float, float2, float);
       if (ik == K_CF32 && ok == K_CF32) FDWT_PASS(float2, float2, float2);
       if (ik == K_CF32 && ok == K_F32) FDWT_PASS(float2, float2, float);
     }
-    if (wk == K_CDF) {
-      if (ik == K_DF && ok == K_CDF) FDWT_PASS(df, cdf, cdf);
-      if (ik == K_DF && ok == K_DF) FDWT_PASS(df, cdf, df);
-      if (ik == K_CDF && ok == K_CDF) FDWT_PASS(cdf, cdf, cdf);
-      if (ik == K_CDF && ok == K_DF) FDWT_PASS(cdf, cdf, df);
+    if (wk == K_CF64) {
+      if (ik == K_F64 && ok == K_CF64) FDWT_PASS(double, double2, double2);
+      if (ik == K_CF64 && ok == K_CF64) FDWT_PASS(double2, double2, double2);
+      if (!red && ik == K_CF64 && ok == K_F64) FDWT_PASS(double2, double2, double);
     }
   }
 #undef FDWT_PASS
@@ -284,48 +568,208 @@ static int pass_dispatch(Kind ik, Kind wk, Kind ok, const void* in, void* out, c
 
 static int pass_any(int p, bool inv, Kind ik, Kind wk, Kind ok, const void* in, void* out,
                     const PassGeom& g, int m, int batch, float scale, int64_t ci, int64_t co,
-                    hipStream_t st) {
+                    const ReduceArgs* red, hipStream_t st) {
   switch (p) {
     case 2:
-      return inv ? pass_dispatch<2, true>(ik, wk, ok, in, out, g, m, batch, scale, ci, co, st)
-                 : pass_dispatch<2, false>(ik, wk, ok, in, out, g, m, batch, scale, ci, co, st);
+      return inv ? pass_dispatch<2, true>(ik, wk, ok, in, out, g, m, batch, scale, ci, co, red, st)
+                 : pass_dispatch<2, false>(ik, wk, ok, in, out, g, m, batch, scale, ci, co, red, st);
     case 3:
-      return inv ? pass_dispatch<3, true>(ik, wk, ok, in, out, g, m, batch, scale, ci, co, st)
-                 : pass_dispatch<3, false>(ik, wk, ok, in, out, g, m, batch, scale, ci, co, st);
+      return inv ? pass_dispatch<3, true>(ik, wk, ok, in, out, g, m, batch, scale, ci, co, red, st)
+                 : pass_dispatch<3, false>(ik, wk, ok, in, out, g, m, batch, scale, ci, co, red, st);
     case 5:
-      return inv ? pass_dispatch<5, true>(ik, wk, ok, in, out, g, m, batch, scale, ci, co, st)
-                 : pass_dispatch<5, false>(ik, wk, ok, in, out, g, m, batch, scale, ci, co, st);
+      return inv ? pass_dispatch<5, true>(ik, wk, ok, in, out, g, m, batch, scale, ci, co, red, st)
+                 : pass_dispatch<5, false>(ik, wk, ok, in, out, g, m, batch, scale, ci, co, red, st);
   }
   return fail(FDWT_EUNSUPPORTED, "p must be 2, 3 or 5");
 }
 
-int fwt_run_tmp(int p, int m, bool inverse, Kind in_kind, const void* in, Kind work_kind,
-                Kind out_kind, void* out, void* tmp, int batch, float scale, hipStream_t st) {
+// ---------------------------------------------- p = 2 static-shape passes
+struct P2Pass {
+  int d0, loge, wdig;
+};
+
+// Two passes cover m <= 24 (4-byte) / 24 (8-byte with a whole-CU tile): a
+// contiguous first pass of up to 2^14 elements, then strided passes over the
+// remaining digits with rows of 64 bytes, split evenly (>= 2^7 elements each).
+static std::vector<P2Pass> plan_p2(int m, size_t bytes) {
+  const int emax = (bytes >= 8 && lds_budget(bytes) < 136 * 1024) ? 13 : 14;
+  const int wd = bytes >= 8 ? 3 : 4;
+  std::vector<P2Pass> out;
+  if (m <= emax) {
+    out.push_back({0, m, 0});
+    return out;
+  }
+  const int rem = m - emax;
+  const int cap = emax - wd;
+  const int nstr = (rem + cap - 1) / cap;
+  const int rd = std::max((rem + nstr - 1) / nstr, 7 - wd);
+  const int first = m - nstr * rd;
+  out.push_back({0, first, 0});
+  for (int i = 0; i < nstr; ++i) out.push_back({first + i * rd, rd + wd, wd});
+  return out;
+}
+
+template <class Tin, class T, class Tout, int WDIG, int EPI>
+static const void* p2_kernel(int loge) {
+  switch (loge) {
+    case 7: return (const void*)fwt_p2<Tin, T, Tout, 7, WDIG, EPI>;
+    case 8: return (const void*)fwt_p2<Tin, T, Tout, 8, WDIG, EPI>;
+    case 9: return (const void*)fwt_p2<Tin, T, Tout, 9, WDIG, EPI>;
+    case 10: return (const void*)fwt_p2<Tin, T, Tout, 10, WDIG, EPI>;
+    case 11: return (const void*)fwt_p2<Tin, T, Tout, 11, WDIG, EPI>;
+    case 12: return (const void*)fwt_p2<Tin, T, Tout, 12, WDIG, EPI>;
+    case 13: return (const void*)fwt_p2<Tin, T, Tout, 13, WDIG, EPI>;
+    case 14: return (const void*)fwt_p2<Tin, T, Tout, 14, WDIG, EPI>;
+  }
+  return nullptr;
+}
+
+// Workgroups per CU for (kernel, LDS), cached.
+static int occupancy(const void* fn, int threads, size_t lds) {
+  static std::mutex mu;
+  static std::map<std::pair<const void*, size_t>, int> cache;
+  std::lock_guard<std::mutex> g(mu);
+  auto key = std::make_pair(fn, lds);
+  auto it = cache.find(key);
+  if (it != cache.end()) return it->second;
+  int n = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, fn, threads, lds) != hipSuccess || n < 1) n = 1;
+  cache[key] = n;
+  return n;
+}
+
+template <class Tin, class T, class Tout>
+static int launch_p2(const void* in, void* out, const P2Pass& g, int m, int batch, float scale,
+                     const ReduceArgs* red, hipStream_t st) {
+  constexpr bool wide = sizeof(T) >= 8;
+  const void* fn;
+  if (red) fn = wide ? (g.wdig ? p2_kernel<Tin, T, Tout, 3, EPI_REDUCE>(g.loge) : p2_kernel<Tin, T, Tout, 0, EPI_REDUCE>(g.loge))
+                     : (g.wdig ? p2_kernel<Tin, T, Tout, 4, EPI_REDUCE>(g.loge) : p2_kernel<Tin, T, Tout, 0, EPI_REDUCE>(g.loge));
+  else fn = wide ? (g.wdig ? p2_kernel<Tin, T, Tout, 3, EPI_STORE>(g.loge) : p2_kernel<Tin, T, Tout, 0, EPI_STORE>(g.loge))
+                 : (g.wdig ? p2_kernel<Tin, T, Tout, 4, EPI_STORE>(g.loge) : p2_kernel<Tin, T, Tout, 0, EPI_STORE>(g.loge));
+  if (!fn || (g.wdig != 0 && g.wdig != (wide ? 3 : 4))) return fail(FDWT_EINVAL, "no static pass shape");
+  const int64_t N = int64_t(1) << m;
+  const int E = 1 << g.loge;
+  const int threads = std::max(64, std::min(1024, E / 16));
+  PassDesc d{};
+  d.col_in = N;
+  d.col_out = N;
+  d.sd0 = int64_t(1) << g.d0;
+  d.shi = int64_t(1) << (g.d0 + g.loge - g.wdig);
+  d.r = g.loge - g.wdig;
+  d.wdig = g.wdig;
+  d.w = 1 << g.wdig;
+  d.nlo = (int)(int64_t(1) << (g.d0 - g.wdig));
+  d.E = E;
+  d.scale = scale;
+  const int64_t ntiles = N / E;
+  const int64_t nb = ntiles * batch;
+  d.ntiles = (int)ntiles;
+  d.batch = batch;
+  if (red) {
+    d.wts = red->wts;
+    d.partial = red->partial;
+    d.h0_out = red->h0_out;
+    d.h0_col = red->h0_col;
+  } else {
+    d.h0_col = -1;
+  }
+  const size_t lds = ((size_t)cpad(E) * sizeof(T) + 15) / 16 * 16 + 16 * sizeof(double);
+  if (int rc = allow_lds(fn, lds)) return rc;
+  int64_t G = (int64_t)occupancy(fn, threads, lds) * device_cus();
+  if (G >= nb) G = nb;
+  if (G >= 64) G -= G % 8;
+  d.xcd = (G % 8 == 0 && G >= 64) ? 1 : 0;
+  void* args[] = {(void*)&in, (void*)&out, (void*)&d};
+  FDWT_HIP(hipLaunchKernel(fn, dim3((unsigned)G), dim3(threads), args, lds, st));
+  return FDWT_OK;
+}
+
+static int p2_pass(Kind k, const void* in, void* out, const P2Pass& g, int m, int batch, float scale,
+                   const ReduceArgs* red, hipStream_t st) {
+  if (k == K_F32 && !red) return launch_p2<float, float, float>(in, out, g, m, batch, scale, nullptr, st);
+  if (k == K_U32 && !red) return launch_p2<uint32_t, uint32_t, uint32_t>(in, out, g, m, batch, scale, nullptr, st);
+  if (k == K_F64) return launch_p2<double, double, double>(in, out, g, m, batch, scale, red, st);
+  return fail(FDWT_EINVAL, "unsupported p = 2 element type");
+}
+
+// p = 2 transforms of one element type through the static-shape passes
+// (forward and inverse coincide up to the scale for p = 2).
+static bool p2_static_ok(int p, int m, Kind ik, Kind wk, Kind ok) {
+  return p == 2 && m >= 7 && ik == wk && ok == wk && (wk == K_F32 || wk == K_U32 || wk == K_F64);
+}
+
+static int run_p2(int m, Kind k, const void* in, void* out, void* tmp, int batch, float scale,
+                  const ReduceArgs* red, int64_t* last_tiles, hipStream_t st) {
+  const std::vector<P2Pass> passes = plan_p2(m, kind_bytes(k));
+  const size_t np = passes.size();
+  if (last_tiles) *last_tiles = (int64_t(1) << m) >> passes.back().loge;
+  if (np == 1) return p2_pass(k, in, out, passes[0], m, batch, scale, red, st);
+  void* mid = red ? tmp : out;
+  if (!mid) return fail(FDWT_EINVAL, "transform needs a workspace for its intermediate passes");
+  int rc = p2_pass(k, in, mid, passes[0], m, batch, 1.0f, nullptr, st);
+  for (size_t i = 1; !rc && i + 1 < np; ++i) rc = p2_pass(k, mid, mid, passes[i], m, batch, 1.0f, nullptr, st);
+  if (rc) return rc;
+  return p2_pass(k, mid, out, passes[np - 1], m, batch, scale, red, st);
+}
+
+static int run_passes(int p, int m, bool inverse, Kind in_kind, const void* in, Kind work_kind,
+                      Kind out_kind, void* out, void* tmp, int batch, float scale, const ReduceArgs* red,
+                      int64_t* last_tiles, hipStream_t st) {
+  if (p2_static_ok(p, m, in_kind, work_kind, out_kind))
+    return run_p2(m, work_kind, in, out, tmp, batch, scale, red, last_tiles, st);
   const int64_t N = ipow(p, m);
   std::vector<PassGeom> passes = plan(p, m, kind_bytes(work_kind));
   const size_t np = passes.size();
+  if (last_tiles) {
+    const PassGeom& g = passes.back();
+    *last_tiles = N / (ipow(p, g.r) * ipow(p, g.wdig));
+  }
   if (np == 1)
-    return pass_any(p, inverse, in_kind, work_kind, out_kind, in, out, passes[0], m, batch, scale,
-                    N, N, st);
+    return pass_any(p, inverse, in_kind, work_kind, out_kind, in, out, passes[0], m, batch, scale, N, N,
+                    red, st);
   // Intermediate buffer: the output itself when it holds the working type.
-  void* mid = (kind_bytes(out_kind) == kind_bytes(work_kind)) ? out : tmp;
-  if (!mid) return fail(FDWT_EINVAL, "transform needs a workspace for a narrowing output");
-  int rc = pass_any(p, inverse, in_kind, work_kind, work_kind, in, mid, passes[0], m, batch, 1.0f,
-                    N, N, st);
+  void* mid = (!red && kind_bytes(out_kind) == kind_bytes(work_kind)) ? out : tmp;
+  if (!mid) return fail(FDWT_EINVAL, "transform needs a workspace for its intermediate passes");
+  int rc = pass_any(p, inverse, in_kind, work_kind, work_kind, in, mid, passes[0], m, batch, 1.0f, N, N,
+                    nullptr, st);
   if (rc) return rc;
   for (size_t i = 1; i + 1 < np; ++i) {
-    rc = pass_any(p, inverse, work_kind, work_kind, work_kind, mid, mid, passes[i], m, batch, 1.0f,
-                  N, N, st);
+    rc = pass_any(p, inverse, work_kind, work_kind, work_kind, mid, mid, passes[i], m, batch, 1.0f, N, N,
+                  nullptr, st);
     if (rc) return rc;
   }
-  return pass_any(p, inverse, work_kind, work_kind, out_kind, mid, out, passes[np - 1], m, batch,
-                  scale, N, N, st);
+  return pass_any(p, inverse, work_kind, work_kind, out_kind, mid, out, passes[np - 1], m, batch, scale,
+                  N, N, red, st);
+}
+
+int fwt_run_tmp(int p, int m, bool inverse, Kind in_kind, const void* in, Kind work_kind,
+                Kind out_kind, void* out, void* tmp, int batch, float scale, hipStream_t st) {
+  return run_passes(p, m, inverse, in_kind, in, work_kind, out_kind, out, tmp, batch, scale, nullptr,
+                    nullptr, st);
 }
 
 int fwt_run(int p, int m, bool inverse, Kind in_kind, const void* in, Kind work_kind,
             Kind out_kind, void* out, int batch, float scale, hipStream_t st) {
-  return fwt_run_tmp(p, m, inverse, in_kind, in, work_kind, out_kind, out, nullptr, batch, scale,
-                     st);
+  return fwt_run_tmp(p, m, inverse, in_kind, in, work_kind, out_kind, out, nullptr, batch, scale, st);
+}
+
+// Unnormalised forward transform of `batch` real float64 columns with the
+// grouped-sum epilogue in its last pass (no output stored).  tmp holds the
+// intermediate passes (batch columns of the working type); partial receives
+// [batch][tiles] sums, tiles returned in *tiles.
+int fwt_reduce_f64(int p, int m, const double* in, void* tmp, int batch, const float2* wts,
+                   double* partial, double* h0_out, int h0_col, int64_t* tiles, hipStream_t st) {
+  ReduceArgs red{wts, partial, h0_out, h0_col};
+  const Kind wk = p == 2 ? K_F64 : K_CF64;
+  return run_passes(p, m, false, K_F64, in, wk, wk, tmp, tmp, batch, 1.0f, &red, tiles, st);
+}
+
+int64_t fwt_reduce_tiles(int p, int m, size_t elem_bytes) {
+  if (p == 2 && m >= 7) return (int64_t(1) << m) >> plan_p2(m, elem_bytes).back().loge;
+  std::vector<PassGeom> passes = plan(p, m, elem_bytes);
+  const PassGeom& g = passes.back();
+  return ipow(p, m) / (ipow(p, g.r) * ipow(p, g.wdig));
 }
 
 }  // namespace fdwt

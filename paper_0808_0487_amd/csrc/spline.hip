@@ -3,22 +3,25 @@
 //  * kernel data: K(x_n, 0) = prod_j [1 + gamma_j K'(x_{n,j}, 0)] and, for the
 //    variances, U_d = R_d - 1 with R_d = prod_{j<=d} (1 + gamma_j^2 R'(x_{n,j}, 0))
 //    and Q_j = e_j(gamma_1^2 R'_1, ..., gamma_s^2 R'_s) (elementary symmetric
-//    polynomials), all in double-float.  K' and R' depend only on the index of
-//    the first non-zero digit of x_{n,j}, so per-coordinate tables (computed
-//    on the host in double) are indexed by a leading-zero count.
-//  * their DWTs (the kernel spectra) are taken in double-float: their dynamic
+//    polynomials), all in float64.  K' and R' depend only on the index of the
+//    first non-zero digit of x_{n,j}, so per-coordinate tables (computed on
+//    the host) are indexed by a leading-zero count.
+//  * their DWTs (the kernel spectra) are taken in float64: their dynamic
 //    range exceeds what float resolves (the small bins would lose all their
-//    digits, and K~ must stay positive for the spectral solve).
+//    digits, and K~ must stay positive for the spectral solve).  On MI355X
+//    float64 vector arithmetic runs at half the float32 rate, far cheaper than
+//    emulating the extra precision with float pairs.
 //  * spectral solve, Eq. (splinecoef): c~ = f~ / (p^m K~), then Algorithm 2.
 //  * variances, Eq. (sig2sfu) summed over u: with rho_g(h) = p^m g~(h)/K~u(h)^2
 //    (K~u the unnormalised spectrum), sigma^2 = sum_h |f~(h)|^2 rho_g(h).
 //    rho lies in [0, 1] exactly (0 <= g~ <= K~^2 because the Walsh
 //    coefficients of R are the squares of those of K); the clamp only removes
-//    rounding noise in bins where K~ is tiny.  These grouped sums are the
-//    only float64 arithmetic on the device.
+//    rounding noise in bins where K~ is tiny.  The sums run in float64 inside
+//    the last pass of the spectra's transform (nothing is stored).
 //  * evaluation, Sf(q) = sum_n c_n K(q, x_n), at query points given as D-digit
 //    integers; the first differing digit of q and x_n is a leading-zero count
 //    of their XOR (p = 2) or of their packed-digit XOR (p odd).
+#include "coords.h"
 #include "dev_math.h"
 
 #include <algorithm>
@@ -34,32 +37,6 @@ constexpr int kTab = 33;  // entries per coordinate of the digit-indexed tables
 
 __host__ __device__ static inline size_t align_up(size_t v) { return (v + 255) & ~(size_t)255; }
 
-// ---------------------------------------------------------- point indices
-// Index t of the first non-zero digit (t = i - 1) of x_{n,j}, or m when
-// x_{n,j} = 0, from the canonical integer (p = 2) or packed digits (p odd).
-__device__ __forceinline__ int lead_p2(uint32_t X, int m) { return __clz(X) - (32 - m); }
-__device__ __forceinline__ int lead_odd(uint64_t pk, int m) { return (__clzll(pk) - 64 + 4 * m) >> 2; }
-
-// Same coordinate machinery as the net kernels (see net.hip).
-template <int P>
-__device__ __forceinline__ uint64_t addmod_packed_s(uint64_t a, uint64_t b) {
-  constexpr uint64_t ones = 0x1111111111111111ull;
-  uint64_t s = a + b;
-  uint64_t ge = ((s + (8 - P) * ones) >> 3) & ones;
-  return s - (uint64_t)P * ge;
-}
-template <int P>
-__device__ __forceinline__ uint64_t packed_odd_s(const uint64_t* __restrict__ ptab, int j, int m, int64_t n) {
-  uint64_t acc = 0;
-  const uint64_t* t = ptab + (int64_t)j * m * P;
-  for (int c = 0; c < m; ++c) {
-    const int dgt = (int)(n % P);
-    n /= P;
-    acc = addmod_packed_s<P>(acc, t[c * P + dgt]);
-  }
-  return acc;
-}
-
 struct NetArgs {
   const uint32_t* xtab;  // p = 2
   const uint64_t* ptab;  // p odd
@@ -67,76 +44,66 @@ struct NetArgs {
   int64_t N;
 };
 
-template <int P>
-__device__ __forceinline__ int lead_index(const NetArgs& na, const uint32_t* lds_t0, int j, int64_t n,
-                                          int64_t nw) {
-  if constexpr (P == 2) {
-    uint32_t u = 0;
-    const uint32_t* base = na.xtab + (int64_t)j * na.nbytes * 256;
-    for (int b = 1; b < na.nbytes; ++b) u ^= base[b * 256 + ((nw >> (8 * b)) & 255)];
-    return lead_p2(lds_t0[j * 256 + (int)(n & 255)] ^ u, na.m);
-  } else {
-    (void)lds_t0;
-    (void)nw;
-    return lead_odd(packed_odd_s<P>(na.ptab, j, na.m, n), na.m);
-  }
-}
-
-// ------------------------------------------------ kernel-data columns (DF)
+// ------------------------------------------------ kernel-data columns (f64)
 // Column layout: 0 = K, 1..s = U_d (d = 1..s), s+1..2s = Q_j (j = 1..s).
-// Writes columns [c0, c1) to out[(c - c0) * N + n].  ESP state lives in LDS
-// (e_j of thread t at esp[j * blockDim + t]).
-template <int P>
-__global__ void __launch_bounds__(256) k_kernel_cols(NetArgs na, const df* __restrict__ tk,
-                                                     const df* __restrict__ tr, int c0, int c1,
-                                                     df* __restrict__ out) {
+// Writes columns [c0, c1) to out[(c - c0) * N + n].  The elementary symmetric
+// polynomials e_0..e_SMAX live in registers (fully unrolled updates; the
+// coordinates beyond s contribute r = 0 and change nothing).
+template <int P, int SMAX>
+__global__ void __launch_bounds__(kChunk) k_kernel_cols(NetArgs na, const double* __restrict__ tk,
+                                                        const double* __restrict__ tr, int c0, int c1,
+                                                        double* __restrict__ out) {
   extern __shared__ __align__(16) unsigned char smem[];
-  uint32_t* lds_t0 = reinterpret_cast<uint32_t*>(smem);
   const int s = na.s;
-  const int tab_words = (P == 2) ? s * 256 : 0;
-  df* esp = reinterpret_cast<df*>(smem + align_up((size_t)tab_words * 4));
-  if constexpr (P == 2) {
-    for (int i = threadIdx.x; i < s * 256; i += blockDim.x)
-      lds_t0[i] = na.xtab[(int64_t)(i >> 8) * na.nbytes * 256 + (i & 255)];
-    __syncthreads();
+  double* ltk = reinterpret_cast<double*>(smem);       // [s][kTab]
+  double* ltr = ltk + s * kTab;                         // [s][kTab]
+  uint32_t* lt0 = reinterpret_cast<uint32_t*>(ltr + s * kTab);
+  for (int i = threadIdx.x; i < s * kTab; i += blockDim.x) {
+    ltk[i] = tk[i];
+    ltr[i] = tr[i];
   }
+  P2Coords pc{na.xtab, na.nbytes, s, lt0, lt0 + s * 256};
+  if constexpr (P == 2) pc.stage_tables();
+  else __syncthreads();
   const bool need_r = c1 > 1;
   const bool need_q = c1 > s + 1;
   const int64_t N = na.N;
-  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-  const int T = blockDim.x;
-  for (int64_t n0 = (int64_t)blockIdx.x * blockDim.x; n0 < N; n0 += stride) {
-    const int64_t n = n0 + threadIdx.x;
-    const int64_t nn = n < N ? n : N - 1;
-    const int64_t nw = (int64_t)__builtin_amdgcn_readfirstlane((int)(nn >> 6)) << 6;
-    df K = {1.0f, 0.0f}, u = {0.0f, 0.0f};
-    if (need_q) {
-      esp[threadIdx.x] = df{1.0f, 0.0f};
-      for (int j = 1; j <= s; ++j) esp[j * T + threadIdx.x] = df{0.0f, 0.0f};
+  const int m = na.m;
+  for (int64_t base = (int64_t)blockIdx.x * kChunk; base < N; base += (int64_t)gridDim.x * kChunk) {
+    if constexpr (P == 2) {
+      __syncthreads();
+      pc.stage_group(base);
+      __syncthreads();
     }
+    const int64_t n = base + threadIdx.x;
+    const int64_t nn = n < N ? n : N - 1;
+    double K = 1.0, u = 0.0;
+    double e[SMAX + 1];
+#pragma unroll
+    for (int i = 0; i <= SMAX; ++i) e[i] = i == 0 ? 1.0 : 0.0;
     for (int j = 0; j < s; ++j) {
-      const int t = lead_index<P>(na, lds_t0, j, nn, nw);
-      K = mul(K, tk[j * kTab + t]);
+      int t;
+      if constexpr (P == 2) t = lead_p2(pc.X(j, nn), m);
+      else t = lead_odd(packed_odd<P>(na.ptab, j, m, nn), m);
+      K *= ltk[j * kTab + t];
       if (need_r) {
-        const df r = tr[j * kTab + t];
-        u = add(add(u, r), mul(u, r));  // (1 + u)(1 + r) - 1
+        const double r = ltr[j * kTab + t];
+        u = u + r + u * r;  // (1 + u)(1 + r) - 1
         const int c = 1 + j;
         if (c >= c0 && c < c1 && n < N) out[(int64_t)(c - c0) * N + n] = u;
         if (need_q) {
-          for (int i = j + 1; i >= 1; --i) {
-            df e = esp[i * T + threadIdx.x];
-            e = add(e, mul(r, esp[(i - 1) * T + threadIdx.x]));
-            esp[i * T + threadIdx.x] = e;
-          }
+#pragma unroll
+          for (int i = SMAX; i >= 1; --i) e[i] += r * e[i - 1];
         }
       }
     }
     if (n < N) {
       if (c0 == 0) out[n] = K;
       if (need_q) {
-        for (int j = 1; j <= s; ++j) {
+#pragma unroll
+        for (int j = 1; j <= SMAX; ++j) {
           const int c = s + j;
-          if (c >= c0 && c < c1) out[(int64_t)(c - c0) * N + n] = esp[j * T + threadIdx.x];
+          if (j <= s && c >= c0 && c < c1) out[(int64_t)(c - c0) * N + n] = e[j];
         }
       }
     }
@@ -150,32 +117,28 @@ __global__ void __launch_bounds__(256) k_spec_div(const void* __restrict__ ft, c
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
   for (int64_t h = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; h < N; h += stride) {
     if constexpr (P == 2) {
-      const df g = ((const df*)gk)[h];
-      const float den = fmaxf(g.hi + g.lo, 1e-30f);
-      ((float*)ct)[h] = ((const float*)ft)[h] / den;
+      const double g = fmax(((const double*)gk)[h], 1e-300);
+      ((float*)ct)[h] = (float)((double)((const float*)ft)[h] / g);
     } else {
-      const cdf g = ((const cdf*)gk)[h];
-      const float den = fmaxf(g.re.hi + g.re.lo, 1e-30f);
+      const double g = fmax(((const double2*)gk)[h].x, 1e-300);
       const float2 f = ((const float2*)ft)[h];
-      ((float2*)ct)[h] = make_float2(f.x / den, f.y / den);
+      ((float2*)ct)[h] = make_float2((float)((double)f.x / g), (float)((double)f.y / g));
     }
   }
 }
 
 // ------------------------------------------------------- grouped sums
-constexpr int kCB = 8;     // columns per reduction block
-constexpr int kRedBlocks = 512;
+// Weights of the grouped sums: wts[h] = (|f~(h)|^2, p^m / K~u(h)^2), with
+// K~u the unnormalised kernel spectrum (so that rho = g~u * wts.y is the
+// normalised ratio of Eq. (sig2sfu)), and the sample variance
+// sum_{h != 0} |f~(h)|^2 as block partials.
+constexpr int kRedBlocks = 1024;
 
 template <int P>
-__global__ void __launch_bounds__(256) k_effdim_reduce(const void* __restrict__ ft, const void* __restrict__ gk,
-                                                       const void* __restrict__ G, int ncol, int64_t N,
-                                                       double pm, double* __restrict__ partial,
-                                                       double* __restrict__ qmc_partial) {
+__global__ void __launch_bounds__(256) k_effdim_weights(const void* __restrict__ ft, const void* __restrict__ gk,
+                                                        int64_t N, double pm, float2* __restrict__ wts,
+                                                        double* __restrict__ qmc_partial) {
   __shared__ double red[256];
-  const int cb = blockIdx.y * kCB;
-  double acc[kCB];
-#pragma unroll
-  for (int k = 0; k < kCB; ++k) acc[k] = 0.0;
   double qmc = 0.0;
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
   for (int64_t h = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; h < N; h += stride) {
@@ -183,42 +146,23 @@ __global__ void __launch_bounds__(256) k_effdim_reduce(const void* __restrict__ 
     if constexpr (P == 2) {
       const double f = (double)((const float*)ft)[h];
       fsq = f * f;
-      kk = to_double(((const df*)gk)[h]);
+      kk = ((const double*)gk)[h];
     } else {
       const float2 f = ((const float2*)ft)[h];
       fsq = (double)f.x * f.x + (double)f.y * f.y;
-      kk = to_double(((const cdf*)gk)[h].re);
+      kk = ((const double2*)gk)[h].x;
     }
-    const double w = kk > 0.0 ? pm / (kk * kk) : 0.0;
+    const double kinv = kk > 0.0 ? fmin(pm / (kk * kk), 3.0e38) : 0.0;
+    wts[h] = make_float2((float)fsq, (float)kinv);
     if (h != 0) qmc += fsq;
-#pragma unroll
-    for (int k = 0; k < kCB; ++k) {
-      const int c = cb + k;
-      if (c < ncol) {
-        double g;
-        if constexpr (P == 2) g = to_double(((const df*)G)[(int64_t)c * N + h]);
-        else g = to_double(((const cdf*)G)[(int64_t)c * N + h].re);
-        const double rho = fmin(fmax(g * w, 0.0), 1.0);
-        acc[k] += fsq * rho;
-      }
-    }
   }
-  // Fixed-shape tree reduction (deterministic).
-  for (int k = 0; k <= kCB; ++k) {
-    const int c = cb + k;
-    if (k < kCB && c >= ncol) continue;
-    red[threadIdx.x] = (k < kCB) ? acc[k] : qmc;
-    __syncthreads();
-    for (int off = 128; off > 0; off >>= 1) {
-      if (threadIdx.x < off) red[threadIdx.x] += red[threadIdx.x + off];
-      __syncthreads();
-    }
-    if (threadIdx.x == 0) {
-      if (k < kCB) partial[(int64_t)c * gridDim.x + blockIdx.x] = red[0];
-      else if (blockIdx.y == 0) qmc_partial[blockIdx.x] = red[0];
-    }
+  red[threadIdx.x] = qmc;
+  __syncthreads();
+  for (int off = 128; off > 0; off >>= 1) {
+    if (threadIdx.x < off) red[threadIdx.x] += red[threadIdx.x + off];
     __syncthreads();
   }
+  if (threadIdx.x == 0) qmc_partial[blockIdx.x] = red[0];
 }
 
 // Sum nblk partials per row in a fixed order: out[row] = sum_b in[row*nblk + b].
@@ -332,13 +276,6 @@ __global__ void __launch_bounds__(256) k_eval_finish(const df* __restrict__ part
 }
 
 // =============================================================== host side
-static df split_df(double v) {
-  df r;
-  r.hi = (float)v;
-  r.lo = (float)(v - (double)r.hi);
-  return r;
-}
-
 static NetArgs net_args(const Net& net) {
   return NetArgs{net.d_xtab, net.d_ptab, net.nbytes, net.s, net.m, net.N};
 }
@@ -354,75 +291,87 @@ static int upload(Net& net, const void* src, size_t bytes, void* dst, hipStream_
 }
 
 // Kernel-data tables: tk[j][t] = 1 + gamma_j K'(t+1) for t < m, 1 + gamma_j for
-// t >= m (x = 0); tr[j][t] = gamma_j^2 R'(t+1), gamma_j^2 R'(0).
-static void kernel_tables(const Net& net, const fdwt_kernel* k, std::vector<df>& tk, std::vector<df>& tr) {
-  tk.assign((size_t)net.s * kTab, df{0, 0});
-  tr.assign((size_t)net.s * kTab, df{0, 0});
+// t >= m (x = 0); tr[j][t] = gamma_j^2 R'(t+1), gamma_j^2 R'(0).  Laid out as
+// tk then tr, each [s][kTab].
+static std::vector<double> kernel_tables(const Net& net, const fdwt_kernel* k) {
+  std::vector<double> t((size_t)2 * net.s * kTab, 0.0);
   for (int j = 0; j < net.s; ++j) {
     const double g = k->gamma[j];
-    for (int t = 0; t < kTab; ++t) {
-      const int i = t < net.m ? t + 1 : 0;
-      tk[(size_t)j * kTab + t] = split_df(1.0 + g * kprime(net.p, k->alpha, i));
-      tr[(size_t)j * kTab + t] = split_df(g * g * rprime(net.p, k->alpha, i));
+    for (int i = 0; i < kTab; ++i) {
+      const int dig = i < net.m ? i + 1 : 0;
+      t[(size_t)j * kTab + i] = 1.0 + g * kprime(net.p, k->alpha, dig);
+      t[(size_t)(net.s + j) * kTab + i] = g * g * rprime(net.p, k->alpha, dig);
     }
   }
+  return t;
 }
 
-static size_t kcols_lds(const Net& net, int threads, bool need_q) {
-  size_t b = net.p == 2 ? align_up((size_t)net.s * 256 * 4) : 0;
-  if (need_q) b += (size_t)(net.s + 1) * threads * sizeof(df);
-  return b;
-}
-
-static int launch_kernel_cols(Net& net, const df* tk, const df* tr, int c0, int c1, df* out, hipStream_t st) {
-  const bool need_q = c1 > net.s + 1;
-  int threads = 256;
-  while (threads > 64 && kcols_lds(net, threads, need_q) > 80 * 1024) threads /= 2;
-  const size_t lds = kcols_lds(net, threads, need_q);
-  const unsigned grid = (unsigned)std::min<int64_t>((net.N + threads - 1) / threads, 4096);
-  NetArgs na = net_args(net);
-  const void* fn;
-  if (net.p == 2) fn = (const void*)k_kernel_cols<2>;
-  else if (net.p == 3) fn = (const void*)k_kernel_cols<3>;
-  else fn = (const void*)k_kernel_cols<5>;
-  if (lds > 65536) FDWT_HIP(hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
-  if (net.p == 2) hipLaunchKernelGGL(k_kernel_cols<2>, dim3(grid), dim3(threads), lds, st, na, tk, tr, c0, c1, out);
-  else if (net.p == 3) hipLaunchKernelGGL(k_kernel_cols<3>, dim3(grid), dim3(threads), lds, st, na, tk, tr, c0, c1, out);
-  else hipLaunchKernelGGL(k_kernel_cols<5>, dim3(grid), dim3(threads), lds, st, na, tk, tr, c0, c1, out);
+template <int P, int SMAX>
+static int kcols_launch(const Net& net, const double* tk, const double* tr, int c0, int c1, double* out,
+                        hipStream_t st) {
+  const size_t lds = (size_t)2 * net.s * kTab * 8 + (P == 2 ? (size_t)net.s * 257 * 4 : 0);
+  if (int rc = allow_lds((const void*)k_kernel_cols<P, SMAX>, lds)) return rc;
+  const unsigned grid = (unsigned)std::min<int64_t>((net.N + kChunk - 1) / kChunk, 2048);
+  hipLaunchKernelGGL((k_kernel_cols<P, SMAX>), dim3(grid), dim3(kChunk), lds, st, net_args(net), tk, tr, c0,
+                     c1, out);
   FDWT_HIP(hipGetLastError());
   return FDWT_OK;
 }
 
-// Unnormalised double-float spectra of `batch` real DF columns in `in`:
-// p = 2 in place (out == in), p odd into complex DF `out`.
-static int df_spectra(const Net& net, df* in, void* out, int batch, hipStream_t st) {
-  if (net.p == 2) return fwt_run_tmp(2, net.m, false, K_DF, in, K_DF, K_DF, in, nullptr, batch, 1.0f, st);
-  return fwt_run_tmp(net.p, net.m, false, K_DF, in, K_CDF, K_CDF, out, nullptr, batch, 1.0f, st);
+// SMAX: register length of the symmetric-polynomial state (>= s; 8 when only
+// K and the U_d columns are wanted).
+template <int P>
+static int kcols_p(const Net& net, const double* tk, const double* tr, int c0, int c1, double* out,
+                   hipStream_t st) {
+  const int s = net.s;
+  if (c1 <= s + 1 || s <= 8) return kcols_launch<P, 8>(net, tk, tr, c0, c1, out, st);
+  if (s <= 16) return kcols_launch<P, 16>(net, tk, tr, c0, c1, out, st);
+  if (s <= 24) return kcols_launch<P, 24>(net, tk, tr, c0, c1, out, st);
+  if (s <= 32) return kcols_launch<P, 32>(net, tk, tr, c0, c1, out, st);
+  if (s <= 48) return kcols_launch<P, 48>(net, tk, tr, c0, c1, out, st);
+  return kcols_launch<P, 64>(net, tk, tr, c0, c1, out, st);
+}
+
+static int launch_kernel_cols(const Net& net, const double* tk, const double* tr, int c0, int c1, double* out,
+                              hipStream_t st) {
+  if (net.p == 2) return kcols_p<2>(net, tk, tr, c0, c1, out, st);
+  if (net.p == 3) return kcols_p<3>(net, tk, tr, c0, c1, out, st);
+  return kcols_p<5>(net, tk, tr, c0, c1, out, st);
 }
 
 static unsigned grid1(int64_t n) { return (unsigned)std::min<int64_t>((n + 255) / 256, 4096); }
 
+int fwt_reduce_f64(int p, int m, const double* in, void* tmp, int batch, const float2* wts, double* partial,
+                   double* h0_out, int h0_col, int64_t* tiles, hipStream_t st);
+int64_t fwt_reduce_tiles(int p, int m, size_t elem_bytes);
+
+// Unnormalised float64 spectrum of the kernel data K(x_n, 0): `A` holds the
+// data (N doubles), the spectrum goes to GK (p = 2: in place in A; p odd:
+// N complex doubles).
+static int kernel_spectrum(Net& net, const double* tab, double* A, void* GK, hipStream_t st) {
+  int rc = launch_kernel_cols(net, tab, tab + (size_t)net.s * kTab, 0, 1, A, st);
+  if (rc) return rc;
+  if (net.p == 2) return fwt_run_tmp(2, net.m, false, K_F64, A, K_F64, K_F64, A, nullptr, 1, 1.0f, st);
+  return fwt_run_tmp(net.p, net.m, false, K_F64, A, K_CF64, K_CF64, GK, nullptr, 1, 1.0f, st);
+}
+
 int run_spline_coef(Net& net, const fdwt_kernel* kern, int ft_type, const void* ft, float* c, hipStream_t st) {
   (void)ft_type;
   const int64_t N = net.N;
-  const size_t tab_b = align_up((size_t)net.s * kTab * sizeof(df));
-  const size_t a_b = align_up((size_t)N * sizeof(df));
-  const size_t g_b = net.p == 2 ? 0 : align_up((size_t)N * sizeof(cdf));
+  const size_t tab_b = align_up((size_t)2 * net.s * kTab * sizeof(double));
+  const size_t a_b = align_up((size_t)N * sizeof(double));
+  const size_t g_b = net.p == 2 ? 0 : align_up((size_t)N * sizeof(double2));
   const size_t ct_b = net.p == 2 ? 0 : align_up((size_t)N * sizeof(float2));
   int rc = ensure_ws(net, tab_b + a_b + g_b + ct_b, st);
   if (rc) return rc;
   char* w = (char*)net.ws;
-  df* tk = (df*)w;
-  df* A = (df*)(w + tab_b);
+  double* tab = (double*)w;
+  double* A = (double*)(w + tab_b);
   void* GK = net.p == 2 ? (void*)A : (void*)(w + tab_b + a_b);
   void* ct = net.p == 2 ? (void*)c : (void*)(w + tab_b + a_b + g_b);
-  std::vector<df> htk, htr;
-  kernel_tables(net, kern, htk, htr);
-  rc = upload(net, htk.data(), htk.size() * sizeof(df), tk, st);
-  if (rc) return rc;
-  rc = launch_kernel_cols(net, tk, tk, 0, 1, A, st);
-  if (rc) return rc;
-  rc = df_spectra(net, A, GK, 1, st);
+  const std::vector<double> htab = kernel_tables(net, kern);
+  rc = upload(net, htab.data(), htab.size() * sizeof(double), tab, st);
+  if (!rc) rc = kernel_spectrum(net, tab, A, GK, st);
   if (rc) return rc;
   if (net.p == 2) hipLaunchKernelGGL(k_spec_div<2>, dim3(grid1(N)), dim3(256), 0, st, ft, GK, N, ct);
   else if (net.p == 3) hipLaunchKernelGGL(k_spec_div<3>, dim3(grid1(N)), dim3(256), 0, st, ft, GK, N, ct);
@@ -442,7 +391,7 @@ static int launch_eval(Net& net, const void* Xp, const float* c, int64_t nq, con
 #define FDWT_EVAL(SM)                                                                              \
   {                                                                                                \
     auto fn = k_spline_eval<P, SM>;                                                                \
-    if (lds > 65536) FDWT_HIP(hipFuncSetAttribute((const void*)fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds)); \
+    if (int rc_ = allow_lds((const void*)fn, lds)) return rc_;                                     \
     hipLaunchKernelGGL(fn, grid, dim3(256), lds, st, Xp, c, net.N, s, net.m, q, qh, qt, nq, te,    \
                        ntab, ppc, partial);                                                        \
   }
@@ -507,72 +456,61 @@ int run_eff_dim(Net& net, const fdwt_kernel* kern, int ft_type, const void* ft, 
   (void)ft_type;
   const int p = net.p, s = net.s;
   const int64_t N = net.N;
-  const size_t eb = sizeof(df), cb = (p == 2) ? sizeof(df) : sizeof(cdf);
-  const int ncols = 2 * s;  // U_1..U_s, Q_1..Q_s  (column c+1 of the generator layout)
-  // Columns per chunk within a workspace budget.
-  const size_t budget = (size_t)8 << 30;
-  const size_t per_col = (size_t)N * (eb + (p == 2 ? 0 : cb));
-  int ch = (int)std::max<size_t>(1, std::min<size_t>((size_t)ncols, budget / per_col));
-  const size_t tab_b = align_up((size_t)2 * s * kTab * sizeof(df));
-  const size_t gk_b = align_up((size_t)N * cb) + (p == 2 ? 0 : align_up((size_t)N * eb));
-  const size_t a_b = align_up((size_t)ch * N * eb);
-  const size_t b_b = p == 2 ? 0 : align_up((size_t)ch * N * cb);
-  const size_t part_b = align_up((size_t)(ncols + 1) * kRedBlocks * sizeof(double));
-  const size_t res_b = align_up((size_t)(ncols + 1) * sizeof(double));
-  const size_t h0_b = align_up(64);
-  int rc = ensure_ws(net, tab_b + gk_b + a_b + b_b + part_b + res_b + h0_b, st);
+  const size_t wb = (p == 2) ? sizeof(double) : sizeof(double2);  // working element of the spectra
+  const int ncols = 2 * s;  // U_1..U_s, Q_1..Q_s (generator columns 1..2s)
+  // Columns per chunk within a workspace budget: data (8 B) + intermediate (wb).
+  const size_t budget = (size_t)12 << 30;
+  const size_t per_col = (size_t)N * (8 + wb);
+  const int ch = (int)std::max<size_t>(1, std::min<size_t>((size_t)ncols, budget / per_col));
+  const int64_t tiles = fwt_reduce_tiles(p, net.m, wb);
+  const size_t tab_b = align_up((size_t)2 * s * kTab * sizeof(double));
+  const size_t gk_b = align_up((size_t)N * 8) + (p == 2 ? 0 : align_up((size_t)N * wb));
+  const size_t w_b = align_up((size_t)N * sizeof(float2));
+  const size_t a_b = align_up((size_t)ch * N * 8);
+  const size_t b_b = align_up((size_t)ch * N * wb);
+  const size_t part_b = align_up((size_t)ncols * tiles * sizeof(double) + kRedBlocks * sizeof(double));
+  const size_t res_b = align_up((size_t)(ncols + 2) * sizeof(double));
+  int rc = ensure_ws(net, tab_b + gk_b + w_b + a_b + b_b + part_b + res_b, st);
   if (rc) return rc;
   char* w = (char*)net.ws;
-  df* tk = (df*)w;
-  df* tr = tk + (size_t)s * kTab;
-  char* gkbase = w + tab_b;
-  void* GK = gkbase;                                   // DF (p = 2) or CDF spectrum of K
-  df* gk_in = p == 2 ? (df*)gkbase : (df*)(gkbase + align_up((size_t)N * cb));
-  df* A = (df*)(w + tab_b + gk_b);
-  void* B = p == 2 ? (void*)A : (void*)(w + tab_b + gk_b + a_b);
-  double* partial = (double*)(w + tab_b + gk_b + a_b + b_b);
-  double* qmc_partial = partial + (size_t)ncols * kRedBlocks;
-  double* res = (double*)(w + tab_b + gk_b + a_b + b_b + part_b);
-  char* h0 = w + tab_b + gk_b + a_b + b_b + part_b + res_b;
+  double* tab = (double*)w;
+  double* gk_in = (double*)(w + tab_b);
+  void* GK = p == 2 ? (void*)gk_in : (void*)(w + tab_b + align_up((size_t)N * 8));
+  float2* wts = (float2*)(w + tab_b + gk_b);
+  double* A = (double*)(w + tab_b + gk_b + w_b);
+  void* B = (void*)(w + tab_b + gk_b + w_b + a_b);
+  double* partial = (double*)(w + tab_b + gk_b + w_b + a_b + b_b);
+  double* qmc_partial = partial + (size_t)ncols * tiles;
+  double* res = (double*)(w + tab_b + gk_b + w_b + a_b + b_b + part_b);
+  double* h0 = res + ncols + 1;  // [0] = h = 0 share of the total, then f~(0), K~u(0)
 
-  std::vector<df> htab, htr;
-  kernel_tables(net, kern, htab, htr);
-  htab.insert(htab.end(), htr.begin(), htr.end());
-  rc = upload(net, htab.data(), htab.size() * sizeof(df), tk, st);
-  if (rc) return rc;
-  // K~ (unnormalised).
-  rc = launch_kernel_cols(net, tk, tr, 0, 1, gk_in, st);
-  if (!rc) rc = df_spectra(net, gk_in, GK, 1, st);
+  const std::vector<double> htab = kernel_tables(net, kern);
+  rc = upload(net, htab.data(), htab.size() * sizeof(double), tab, st);
+  if (!rc) rc = kernel_spectrum(net, tab, gk_in, GK, st);
   if (rc) return rc;
   const double pm = (double)N;
+  if (p == 2) hipLaunchKernelGGL(k_effdim_weights<2>, dim3(kRedBlocks), dim3(256), 0, st, ft, GK, N, pm, wts, qmc_partial);
+  else if (p == 3) hipLaunchKernelGGL(k_effdim_weights<3>, dim3(kRedBlocks), dim3(256), 0, st, ft, GK, N, pm, wts, qmc_partial);
+  else hipLaunchKernelGGL(k_effdim_weights<5>, dim3(kRedBlocks), dim3(256), 0, st, ft, GK, N, pm, wts, qmc_partial);
+  FDWT_HIP(hipGetLastError());
   for (int c0 = 0; c0 < ncols; c0 += ch) {
     const int c1 = std::min(ncols, c0 + ch);
-    rc = launch_kernel_cols(net, tk, tr, c0 + 1, c1 + 1, A, st);
-    if (!rc) rc = df_spectra(net, A, B, c1 - c0, st);
+    rc = launch_kernel_cols(net, tab, tab + (size_t)s * kTab, c0 + 1, c1 + 1, A, st);
     if (rc) return rc;
-    const dim3 grid(kRedBlocks, (unsigned)((c1 - c0 + kCB - 1) / kCB));
-    double* part_c = partial + (size_t)c0 * kRedBlocks;
-    if (p == 2) hipLaunchKernelGGL(k_effdim_reduce<2>, grid, dim3(256), 0, st, ft, GK, B, c1 - c0, N, pm, part_c, qmc_partial);
-    else if (p == 3) hipLaunchKernelGGL(k_effdim_reduce<3>, grid, dim3(256), 0, st, ft, GK, B, c1 - c0, N, pm, part_c, qmc_partial);
-    else hipLaunchKernelGGL(k_effdim_reduce<5>, grid, dim3(256), 0, st, ft, GK, B, c1 - c0, N, pm, part_c, qmc_partial);
-    FDWT_HIP(hipGetLastError());
-    // The h = 0 bin of U_s (for the h = 0 share of the total).
-    if (s - 1 >= c0 && s - 1 < c1)
-      FDWT_HIP(hipMemcpyAsync(h0 + 32, (char*)B + (size_t)(s - 1 - c0) * N * cb, cb, hipMemcpyDeviceToDevice, st));
+    const int h0_col = (s - 1 >= c0 && s - 1 < c1) ? s - 1 - c0 : -1;  // U_s
+    int64_t t = 0;
+    rc = fwt_reduce_f64(p, net.m, A, B, c1 - c0, wts, partial + (size_t)c0 * tiles, h0, h0_col, &t, st);
+    if (rc) return rc;
   }
-  hipLaunchKernelGGL(k_sum_rows, dim3(ncols + 1), dim3(256), 0, st, partial, kRedBlocks, res);
+  hipLaunchKernelGGL(k_sum_rows, dim3(ncols), dim3(256), 0, st, partial, (int)tiles, res);
+  hipLaunchKernelGGL(k_sum_rows, dim3(1), dim3(256), 0, st, qmc_partial, kRedBlocks, res + ncols);
   FDWT_HIP(hipGetLastError());
-  FDWT_HIP(hipMemcpyAsync(h0, ft, p == 2 ? 4 : 8, hipMemcpyDeviceToDevice, st));
-  FDWT_HIP(hipMemcpyAsync(h0 + 8, GK, cb, hipMemcpyDeviceToDevice, st));
-  // Results to the host.
-  const size_t nres = (size_t)(ncols + 1) * sizeof(double);
-  rc = ensure_pin(net, nres + 64);
+  const size_t nres = (size_t)(ncols + 2) * sizeof(double);
+  rc = ensure_pin(net, nres);
   if (rc) return rc;
   FDWT_HIP(hipMemcpyAsync(net.pin, res, nres, hipMemcpyDeviceToHost, st));
-  FDWT_HIP(hipMemcpyAsync((char*)net.pin + nres, h0, 64, hipMemcpyDeviceToHost, st));
   FDWT_HIP(hipStreamSynchronize(st));
   const double* r = (const double*)net.pin;
-  const char* hz = (const char*)net.pin + nres;
   out->var_trc[0] = 0.0;
   out->var_sup[0] = 0.0;
   for (int d = 1; d <= s; ++d) {
@@ -581,30 +519,7 @@ int run_eff_dim(Net& net, const fdwt_kernel* kern, int ft_type, const void* ft, 
   }
   out->var_total = out->var_trc[s];
   out->var_qmc = r[ncols];
-  {
-    double fsq, kk, g;
-    if (p == 2) {
-      float f;
-      df k0, g0;
-      std::memcpy(&f, hz, 4);
-      std::memcpy(&k0, hz + 8, sizeof(df));
-      std::memcpy(&g0, hz + 32, sizeof(df));
-      fsq = (double)f * f;
-      kk = (double)k0.hi + k0.lo;
-      g = (double)g0.hi + g0.lo;
-    } else {
-      float f[2];
-      cdf k0, g0;
-      std::memcpy(f, hz, 8);
-      std::memcpy(&k0, hz + 8, sizeof(cdf));
-      std::memcpy(&g0, hz + 32, sizeof(cdf));
-      fsq = (double)f[0] * f[0] + (double)f[1] * f[1];
-      kk = (double)k0.re.hi + k0.re.lo;
-      g = (double)g0.re.hi + g0.re.lo;
-    }
-    const double rho = kk > 0 ? std::min(1.0, std::max(0.0, pm * g / (kk * kk))) : 0.0;
-    out->var_total_h0 = fsq * rho;
-  }
+  out->var_total_h0 = r[ncols + 1];
   const double target = 0.99 * out->var_total;
   out->d_trc = s;
   out->d_sup = s;

@@ -12,8 +12,9 @@ pytestmark = pytest.mark.gpu
 
 
 @pytest.mark.parametrize("p,m,s,seed", [(2, 1, 1, 1), (2, 7, 3, 2), (2, 10, 4, 1), (2, 13, 8, 3),
-                                        (2, 17, 5, 4), (3, 1, 2, 5), (3, 6, 4, 6), (3, 9, 3, 7),
-                                        (5, 1, 1, 8), (5, 4, 3, 9), (5, 7, 2, 10)])
+                                        (2, 17, 5, 4), (2, 12, 64, 11), (3, 1, 2, 5), (3, 6, 4, 6),
+                                        (3, 9, 3, 7), (3, 5, 64, 12), (5, 1, 1, 8), (5, 4, 3, 9),
+                                        (5, 7, 2, 10)])
 def test_net_digits_bit_exact(p, m, s, seed):
     announce("net_digits", p, m, s, seed)
     C = inputs.upper_triangular_generators(p, m, s, seed)
@@ -53,6 +54,7 @@ def test_net_digits_full_size_sampled(p, m, s, seed):
 
 
 @pytest.mark.parametrize("kind,p,m,s,seed", [("product", 2, 10, 4, 1), ("exp", 2, 12, 20, 2),
+                                             ("product", 2, 9, 64, 7),
                                              ("wangfang", 2, 12, 10, 3), ("product", 3, 8, 10, 4),
                                              ("exp", 5, 6, 5, 5), ("wangfang", 3, 7, 6, 6)])
 def test_sample_families(kind, p, m, s, seed):

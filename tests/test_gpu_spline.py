@@ -11,6 +11,8 @@ from tests.gpu_common import announce, nrel, sample_indices
 pytestmark = pytest.mark.gpu
 
 CASES = [(2, 8, 4, 1), (2, 10, 4, 2), (2, 11, 6, 3), (3, 5, 3, 4), (3, 6, 4, 5), (5, 3, 3, 6), (5, 4, 2, 7)]
+# wider s exercises every register length of the symmetric-polynomial state
+WIDE = [(2, 7, 12, 8), (2, 6, 30, 9), (2, 5, 64, 10), (3, 4, 20, 11), (5, 3, 40, 12)]
 
 
 def setup_case(p, m, s, seed, alpha=2.0):
@@ -60,7 +62,7 @@ def test_interpolant_at_queries(p, m, s, seed):
     assert nrel(sf[-len(idx):], fo[idx]) <= 1e-5
 
 
-@pytest.mark.parametrize("p,m,s,seed", CASES)
+@pytest.mark.parametrize("p,m,s,seed", CASES + WIDE)
 def test_effective_dimension_variances(p, m, s, seed):
     """var_trc, var_sup (Section 4) against the direct double sums with the
     oracle's dense-solve coefficients; d_trc, d_sup equal; sample variance."""
