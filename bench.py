@@ -7,20 +7,24 @@ uniform in [-1000, 1000]; Walsh kernel alpha = 2, gamma_j = j^-2.
 
 One step runs the whole path on that input: net generation fused into the
 sampling of f, the forward transform (float32), the int32 forward transform,
-the kernel spectrum and spectral solve with the inverse transform (spline
-coefficients), and the effective-dimension variances.  Inputs are resident in
-device memory before timing starts.
+the kernel spectrum, spectral solve and inverse transform (spline
+coefficients), and the effective-dimension variances.  Inputs are resident
+in device memory before timing starts.
 
-    python bench.py [--gpus 1] [--steps K] [--warmup W]
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu]
 
-Prints one JSON line.  `value` is points per second through one step;
-`roofline` is for the transform kernel (forward, float32) timed on its own
-stream with HIP events; `cpu_baseline` times the oracle's direct definition
-on a bounded sample of coefficients.
+Prints one JSON line.  `value` is points per second through one step.  The
+`roofline` is for the kernel class that takes the largest share of the step
+(timed by the library's launch-timing hook: HIP events recorded on the
+stream each kernel is launched on, during the timed steps), with its
+algorithmic bytes per launch.  `cpu_baseline` times the oracle's direct
+definition on a bounded sample of coefficients.
 """
 import argparse
+import hashlib
 import json
 import os
+import re
 import sys
 import time
 
@@ -30,6 +34,8 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+CLASSES = ["pass_f32", "pass_cf32", "pass_f64", "sample", "kcols", "eval"]
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_c2_step.md")
 
 
 def parse():
@@ -38,9 +44,32 @@ def parse():
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle timing")
+    ap.add_argument("--calib-copy", action="store_true",
+                    help="after timing, run a 256 MiB device copy (reference for HBM byte counters)")
     ap.add_argument("--m", type=int, default=24)
     ap.add_argument("--s", type=int, default=20)
     return ap.parse_args()
+
+
+def kernel_source_hash():
+    h = hashlib.sha256()
+    for f in ["fwt.hip", "dev_math.h", "spline.hip"]:
+        with open(os.path.join(ROOT, "paper_0808_0487_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def committed_traffic(cls):
+    """HBM bytes per launch of `cls` from the committed counter summary, or
+    None when absent or taken on different kernel sources."""
+    if not os.path.exists(TRAFFIC_FILE):
+        return None
+    text = open(TRAFFIC_FILE).read()
+    m = re.search(r"source_hash:\s*(\w+)", text)
+    if not m or m.group(1) != kernel_source_hash():
+        return None
+    m = re.search(r"traffic_bytes_per_launch\[%s\]:\s*([0-9.eE+]+)" % cls, text)
+    return float(m.group(1)) if m else None
 
 
 def cpu_baseline(p, m, s, C, budget_s=15.0):
@@ -65,8 +94,8 @@ def cpu_baseline(p, m, s, C, budget_s=15.0):
     full = t_net + N * t_coef
     return {"value": N / full, "unit": "points/s", "cores": 1, "kind": "oracle",
             "sample": "oracle net+f for all %d points (%.1f s) and %d forward coefficients by the direct "
-                      "O(N) sum (%.3f s each), extrapolated to all N coefficients; spline and eff_dim "
-                      "(O(N^2) in the oracle) not included" % (N, t_net, done, t_coef)}
+                      "O(N) sum (%.3f s each, numpy, one thread), extrapolated to all N coefficients; "
+                      "spline and eff_dim (O(N^2) in the oracle) not included" % (N, t_net, done, t_coef)}
 
 
 def main():
@@ -103,6 +132,7 @@ def main():
     for _ in range(args.warmup):
         res = step()
     torch.cuda.synchronize()
+    fdwt.timing_enable(True)
     ev0 = torch.cuda.Event(enable_timing=True)
     ev1 = torch.cuda.Event(enable_timing=True)
     t0 = time.perf_counter()
@@ -113,22 +143,34 @@ def main():
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     ms = ev0.elapsed_time(ev1) / args.steps
+    classes = {}
+    for cl in CLASSES:
+        tot, n, work = fdwt.timing_query(cl)
+        if n:
+            classes[cl] = {"ms_per_step": tot / args.steps, "launches_per_step": n / args.steps,
+                           "avg_launch_ms": tot / n, "work_per_launch": work / n}
+    fdwt.timing_enable(False)
+    dom = max(classes, key=lambda k: classes[k]["ms_per_step"])
+    dc = classes[dom]
+    achieved = dc["work_per_launch"] / (dc["avg_launch_ms"] * 1e-3) / 1e9
+    traffic = committed_traffic(dom)
 
-    # Roofline of the transform kernel: forward float32 on its own, events
-    # on the stream it is launched on.
-    reps = 50
-    fwd_ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(reps)]
-    for _ in range(5):
+    # Plain forward float32 transform on its own (the two pass launches).
+    fdwt.timing_enable(True)
+    for _ in range(30):
         net.forward(f, out=ft)
     torch.cuda.synchronize()
-    for e0, e1 in fwd_ev:
-        e0.record(stream)
-        net.forward(f, out=ft)
-        e1.record(stream)
-    torch.cuda.synchronize()
-    fwd_ms = float(np.median([e0.elapsed_time(e1) for e0, e1 in fwd_ev]))
-    alg_bytes = 8.0 * N  # read N floats, write N floats
-    achieved = alg_bytes / (fwd_ms * 1e-3) / 1e9
+    ftot, fn, fwork = fdwt.timing_query("pass_f32")
+    fdwt.timing_enable(False)
+    fwd_ms = ftot / 30.0
+    fwd_alg = 8.0 * N / (fwd_ms * 1e-3) / 1e9
+
+    if args.calib_copy:
+        src = torch.empty(1 << 26, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
 
     out = {
         "metric": "transformed points/s & % HBM peak; served p50/p99 latency at equal error",
@@ -147,11 +189,16 @@ def main():
                                "kernel alpha=2 gamma_j=j^-2; step = sample, forward f32, forward i32, "
                                "spline coefficients, eff_dim" % (m, N, s),
                    "p": p, "m": m, "s": s, "points": N},
-        "roofline": {"bound": "hbm", "kernel": "forward transform f32 (all passes)",
-                     "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": None},
-        "plain_forward": {"ms": fwd_ms, "points_per_s": N / (fwd_ms * 1e-3)},
+        "roofline": {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
+                     "launches_per_step": dc["launches_per_step"],
+                     "alg_bytes_per_launch": dc["work_per_launch"]},
+        "classes": classes,
+        "plain_forward_f32": {"ms": fwd_ms, "points_per_s": N / (fwd_ms * 1e-3),
+                              "alg_GBs": fwd_alg, "frac_hbm_peak": fwd_alg / HBM_PEAK_GBS,
+                              "pass_launches": fn / 30.0},
         "eff_dim": {"d_trc": res["d_trc"], "d_sup": res["d_sup"], "var_total": res["var_total"]},
+        "kernel_source_hash": kernel_source_hash(),
         "wall_s": wall,
     }
     if not args.no_cpu:

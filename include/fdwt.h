@@ -132,7 +132,7 @@ int fdwt_query_depth(int p);
  *     c~(h) = ft(h) / (p^m K~(h)),  c = inverse DWT of c~,
  * where ft is the forward transform of the data (dwt_forward output: F32 for
  * p = 2, CF32 for p odd) and K~ the DWT of the kernel data (K(x_n, 0))_n,
- * computed on the device in double-float (about 48-bit) precision.  c_dev is
+ * computed on the device in float64 (its dynamic range is beyond float).  c_dev is
  * float [N]: the c_n with Sf = sum_n c_n K(., x_n) interpolating the data. */
 int fdwt_spline_coef(const fdwt_net* net, const fdwt_kernel* kern, int ft_type,
                      const void* ft_dev, float* c_dev, void* stream);
@@ -163,8 +163,8 @@ int fdwt_walsh_interp(const fdwt_net* net, const fdwt_kernel* kern, const float*
  * (Eq. (varSf), with the h = 0 bin included), var_total_h0 = the h = 0
  * bin's share of it, var_qmc = sum_{h != 0} |ft(h)|^2 (the sample variance
  * of the data), d_trc / d_sup = smallest d with var_*[d] >= 0.99 var_total.
- * The kernel spectra are computed in double-float; the grouped sums over h
- * are accumulated in float64 in a fixed order.  var_trc and var_sup are
+ * The kernel data and spectra are computed in float64 and the grouped sums
+ * over h accumulated in float64 in a fixed order (deterministic).  var_trc and var_sup are
  * caller-owned host arrays of s+1 doubles. */
 typedef struct {
   double* var_trc;
@@ -180,6 +180,29 @@ typedef struct {
  * Synchronises stream before returning. */
 int fdwt_eff_dim(const fdwt_net* net, const fdwt_kernel* kern, int ft_type,
                  const void* ft_dev, fdwt_effdim* out, void* stream);
+
+/* ------------------------------------------------------------ timing */
+
+/* Per-launch timing of the library's kernels, for benchmarks and tracing.
+ * While enabled, every kernel launch of the classes below is bracketed by a
+ * pair of HIP events recorded on the stream it is launched on, together with
+ * its algorithmic work (bytes that must cross HBM for the transform passes:
+ * every element read once and written once, or read once and reduced; bytes
+ * written for the generators; coordinate evaluations for FDWT_TC_EVAL).
+ * Enabling (or disabling) discards earlier records.  fdwt_timing_query
+ * waits for the recorded events of a class and returns the summed duration
+ * in milliseconds, the number of launches and the summed work.  Recording
+ * costs two event records per launch; it is off by default. */
+#define FDWT_TC_PASS_F32   0   /* transform passes, float / int32 elements     */
+#define FDWT_TC_PASS_CF32  1   /* transform passes, complex float              */
+#define FDWT_TC_PASS_F64   2   /* kernel-spectrum passes, double / complex double */
+#define FDWT_TC_SAMPLE     3   /* net generation + test-function sampling      */
+#define FDWT_TC_KCOLS      4   /* kernel-data columns (K, R_d - 1, Q_j)        */
+#define FDWT_TC_EVAL       5   /* interpolant evaluation at queries            */
+#define FDWT_TC_COUNT      6
+
+int fdwt_timing_enable(int on);
+int fdwt_timing_query(int cls, double* total_ms, int64_t* launches, double* work);
 
 /* ------------------------------------------------------------ errors */
 

@@ -40,6 +40,52 @@ int allow_lds(const void* fn, size_t bytes) {
   return FDWT_OK;
 }
 
+// ------------------------------------------------------------ timing
+namespace {
+struct TimedRec {
+  hipEvent_t a, b;
+  int cls;
+  double work;
+};
+std::mutex g_tmu;
+bool g_timing = false;
+std::vector<TimedRec> g_recs;
+
+void drop_records() {
+  for (auto& r : g_recs) {
+    (void)hipEventDestroy(r.a);
+    (void)hipEventDestroy(r.b);
+  }
+  g_recs.clear();
+}
+}  // namespace
+
+hipEvent_t timed_begin(hipStream_t st) {
+  {
+    std::lock_guard<std::mutex> g(g_tmu);
+    if (!g_timing) return nullptr;
+  }
+  hipEvent_t e = nullptr;
+  if (hipEventCreate(&e) != hipSuccess) return nullptr;
+  if (hipEventRecord(e, st) != hipSuccess) {
+    (void)hipEventDestroy(e);
+    return nullptr;
+  }
+  return e;
+}
+
+void timed_end(hipEvent_t begin, hipStream_t st, int cls, double work) {
+  if (!begin) return;
+  hipEvent_t e = nullptr;
+  if (hipEventCreate(&e) != hipSuccess || hipEventRecord(e, st) != hipSuccess) {
+    (void)hipEventDestroy(begin);
+    if (e) (void)hipEventDestroy(e);
+    return;
+  }
+  std::lock_guard<std::mutex> g(g_tmu);
+  g_recs.push_back({begin, e, cls, work});
+}
+
 int query_depth(int p) { return p == 2 ? 32 : (p == 3 ? 20 : (p == 5 ? 13 : 0)); }
 
 // K'(z,0) and R'(z,0) of Section 4 for z whose first non-zero base-p digit is
@@ -196,6 +242,33 @@ using namespace fdwt;
 extern "C" {
 
 const char* fdwt_last_error(void) { return g_err.c_str(); }
+
+int fdwt_timing_enable(int on) {
+  std::lock_guard<std::mutex> g(g_tmu);
+  drop_records();
+  g_timing = on != 0;
+  return FDWT_OK;
+}
+
+int fdwt_timing_query(int cls, double* total_ms, int64_t* launches, double* work) {
+  if (cls < 0 || cls >= FDWT_TC_COUNT) return fail(FDWT_EINVAL, "unknown timing class");
+  std::lock_guard<std::mutex> g(g_tmu);
+  double ms = 0.0, w = 0.0;
+  int64_t n = 0;
+  for (auto& r : g_recs) {
+    if (r.cls != cls) continue;
+    if (hipEventSynchronize(r.b) != hipSuccess) return fail(FDWT_EDEVICE, "event synchronisation failed");
+    float t = 0.0f;
+    if (hipEventElapsedTime(&t, r.a, r.b) != hipSuccess) return fail(FDWT_EDEVICE, "event timing failed");
+    ms += t;
+    w += r.work;
+    ++n;
+  }
+  if (total_ms) *total_ms = ms;
+  if (launches) *launches = n;
+  if (work) *work = w;
+  return FDWT_OK;
+}
 
 int fdwt_query_depth(int p) { return query_depth(p); }
 

@@ -63,6 +63,12 @@ struct fdwt_net {
 namespace fdwt {
 
 int64_t ipow(int64_t b, int e);
+
+// Launch timing (see fdwt_timing_enable).  timed_begin returns an event (or
+// nullptr when timing is off) recorded on st; timed_end records the closing
+// event and files the launch under class cls with its algorithmic work.
+hipEvent_t timed_begin(hipStream_t st);
+void timed_end(hipEvent_t begin, hipStream_t st, int cls, double work);
 // Allows a kernel more than the default 64 KiB of dynamic LDS (once per kernel).
 int allow_lds(const void* fn, size_t bytes);
 int ensure_ws(Net& net, size_t bytes, hipStream_t st);

@@ -15,6 +15,7 @@
 
 #include <algorithm>
 #include <map>
+#include <type_traits>
 #include <mutex>
 #include <unordered_set>
 
@@ -280,12 +281,14 @@ struct P2Shape {
   static_assert(EPT >= 2 && THREADS % W == 0, "unsupported shape");
 };
 
-// Register groups over row digits [Q, Q+KG), then the next group.
-template <int LOGE, int WDIG, int Q, class T, bool DONE = (Q >= P2Shape<LOGE, WDIG>::RD)>
+// Register groups over row digits [Q, Q+KG), then the next group.  KGM caps
+// the group size (fewer live registers when other values must stay live).
+template <int LOGE, int WDIG, int Q, class T, int KGM = 4, int RDL = P2Shape<LOGE, WDIG>::RD,
+          bool DONE = (Q >= RDL)>
 struct P2Groups {
   static __device__ __forceinline__ void run(T* lds, int tid) {
     using S = P2Shape<LOGE, WDIG>;
-    constexpr int KG = cmin(S::KGMAX, S::RD - Q);
+    constexpr int KG = cmin(cmin(S::KGMAX, KGM), RDL - Q);
     constexpr int R = 1 << KG;
     constexpr int STQ = S::W << Q;                      // element stride of digit Q
     constexpr int GPT = (S::E >> KG) / S::THREADS;      // groups per thread
@@ -316,13 +319,29 @@ struct P2Groups {
       for (int j = 0; j < R; ++j) base[cpad(j * STQ)] = x[j];
     }
     lds_barrier();
-    P2Groups<LOGE, WDIG, Q + KG, T>::run(lds, tid);
+    P2Groups<LOGE, WDIG, Q + KG, T, KGM, RDL>::run(lds, tid);
   }
 };
-template <int LOGE, int WDIG, int Q, class T>
-struct P2Groups<LOGE, WDIG, Q, T, true> {
+template <int LOGE, int WDIG, int Q, class T, int KGM, int RDL>
+struct P2Groups<LOGE, WDIG, Q, T, KGM, RDL, true> {
   static __device__ __forceinline__ void run(T*, int) {}
 };
+
+// Radix-2 stages over register-index bits [0, NB) of v.
+template <int NB, class T, int N>
+__device__ __forceinline__ void reg_bfly(T (&v)[N]) {
+#pragma unroll
+  for (int b = 0; b < NB; ++b) {
+#pragma unroll
+    for (int j0 = 0; j0 < N; ++j0) {
+      if (((j0 >> b) & 1) == 0) {
+        const T u = v[j0], w = v[j0 + (1 << b)];
+        v[j0] = add(u, w);
+        v[j0 + (1 << b)] = sub(u, w);
+      }
+    }
+  }
+}
 
 template <class Tin, class T, class Tout, int LOGE, int WDIG, int EPI>
 __global__ void __launch_bounds__((P2Shape<LOGE, WDIG>::THREADS))
@@ -366,25 +385,94 @@ __global__ void __launch_bounds__((P2Shape<LOGE, WDIG>::THREADS))
     for (int k = 0; k < EPT; ++k) pre[k] = src[k * gstep];
   };
   if (lb < nb) prefetch(lb);
+  if constexpr (LOGE >= 10) {
+    // Three stage groups per tile.  The 16 elements a thread loads (e = tid +
+    // k TH) differ in the top 4 bits of e: those stages run in registers
+    // before the tile goes to LDS.  The stages of bits [WDIG, 6) run through
+    // LDS.  The store mapping e = lane + 64 k + 1024 w (still coalesced) puts
+    // bits 6..9 in the register index: the remaining stages run in registers
+    // after reading the tile back.
+    constexpr int NS = (LOGE - 10) < 4 ? (LOGE - 10) : 4;
+    constexpr int RDL = 6 - WDIG;
+    const int lane = tid & 63, wv = tid >> 6;
+    const uint32_t goffS = (uint32_t)(lane & (S::W - 1)) + (uint32_t)((lane >> WDIG) + (1024 >> WDIG) * wv) * sd0;
+    const uint32_t gstepS = (uint32_t)(64 >> WDIG) * sd0;
+    T* lrowS = lds + cpad(lane + 1024 * wv);
+    for (; lb < nb; lb += G) {
+      T v[EPT];
+#pragma unroll
+      for (int k = 0; k < EPT; ++k) v[k] = cvt_in<Tin, T>(pre[k]);
+      reg_bfly<4>(v);
+#pragma unroll
+      for (int k = 0; k < EPT; ++k) lrow[cpad(k * TH)] = v[k];
+      lds_barrier();
+      int col, tile;
+      locate(lb, col, tile);
+      const int64_t base = tile_base(tile);
+      float2 wcur[EPI == EPI_REDUCE ? EPT : 1];
+      if constexpr (EPI == EPI_REDUCE) {
+        const float2* wt = d.wts + base + goffS;
+#pragma unroll
+        for (int k = 0; k < EPT; ++k) wcur[k] = wt[k * gstepS];
+      }
+      if (lb + G < nb) prefetch(lb + G);
+      P2Groups<LOGE, WDIG, 0, T, (EPI == EPI_REDUCE && sizeof(T) >= 8) ? 2 : 4, RDL>::run(lds, tid);
+#pragma unroll
+      for (int k = 0; k < EPT; ++k) v[k] = lrowS[66 * k];
+      reg_bfly<NS>(v);
+      if constexpr (EPI == EPI_STORE) {
+        Tout* dst = out + (int64_t)col * d.col_out + base + goffS;
+#pragma unroll
+        for (int k = 0; k < EPT; ++k) dst[k * gstepS] = cvt_out<T, Tout>(v[k], d.scale);
+      } else {
+        double acc = 0.0;
+#pragma unroll
+        for (int k = 0; k < EPT; ++k) {
+          const double rho = fmin(fmax(real_of(v[k]) * (double)wcur[k].y, 0.0), 1.0);
+          const double term = (double)wcur[k].x * rho;
+          acc += term;
+          if (col == d.h0_col && base + goffS + (int64_t)k * gstepS == 0) *d.h0_out = term;
+        }
+        for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off);
+        if (lane == 0) red[wv] = acc;
+        lds_barrier();
+        if (tid == 0) {
+          double t = 0.0;
+          for (int w = 0; w < TH / 64; ++w) t += red[w];
+          d.partial[(int64_t)col * d.ntiles + tile] = t;
+        }
+      }
+      lds_barrier();
+    }
+    return;
+  }
   for (; lb < nb; lb += G) {
 #pragma unroll
     for (int k = 0; k < EPT; ++k) lrow[cpad(k * TH)] = cvt_in<Tin, T>(pre[k]);
     lds_barrier();
-    if (lb + G < nb) prefetch(lb + G);
-    P2Groups<LOGE, WDIG, 0, T>::run(lds, tid);
     int col, tile;
     locate(lb, col, tile);
     const int64_t base = tile_base(tile);
+    // Grouped-sum weights of this tile: loaded now, used after the butterflies.
+    float2 wcur[EPI == EPI_REDUCE ? EPT : 1];
+    if constexpr (EPI == EPI_REDUCE) {
+      const float2* wt = d.wts + base + goff0;
+#pragma unroll
+      for (int k = 0; k < EPT; ++k) wcur[k] = wt[k * gstep];
+    }
+    if (lb + G < nb) prefetch(lb + G);
+    // The grouped-sum variant keeps this tile's weights live across the
+    // butterflies: 2-digit register groups keep it within 128 registers.
+    P2Groups<LOGE, WDIG, 0, T, (EPI == EPI_REDUCE && sizeof(T) >= 8) ? 2 : 4>::run(lds, tid);
     if constexpr (EPI == EPI_STORE) {
       Tout* dst = out + (int64_t)col * d.col_out + base + goff0;
 #pragma unroll
       for (int k = 0; k < EPT; ++k) dst[k * gstep] = cvt_out<T, Tout>(lrow[cpad(k * TH)], d.scale);
     } else {
       double acc = 0.0;
-      const float2* wt = d.wts + base + goff0;
 #pragma unroll
       for (int k = 0; k < EPT; ++k) {
-        const float2 w2 = wt[k * gstep];
+        const float2 w2 = wcur[k];
         const double rho = fmin(fmax(real_of(lrow[cpad(k * TH)]) * (double)w2.y, 0.0), 1.0);
         const double term = (double)w2.x * rho;
         acc += term;
@@ -409,12 +497,13 @@ struct PassGeom {
 };
 
 // LDS per workgroup: 80 KiB lets two workgroups share a CU (160 KiB of LDS).
-// Elements of 8 bytes or more may take a whole CU so that m = 24 still needs
-// only two passes; FDWT_LDS_KB_WIDE overrides that budget (KiB).
+// Elements of 8 bytes or more take a whole CU so that m = 24 still needs only
+// two passes (measured faster at m = 24 than three passes with two
+// workgroups per CU); FDWT_LDS_KB_WIDE overrides that budget (KiB).
 static size_t lds_budget(size_t bytes) {
   static const size_t wide = [] {
     const char* e = getenv("FDWT_LDS_KB_WIDE");
-    const long v = e ? atol(e) : 80;
+    const long v = e ? atol(e) : 160;
     return (size_t)std::max(16L, std::min(160L, v)) * 1024;
   }();
   return bytes >= 8 ? wide : (size_t)80 * 1024;
@@ -426,13 +515,15 @@ static int kreg_for(int p, Kind work) {
   return work == K_CF32 ? 2 : 1;
 }
 
-static std::vector<PassGeom> plan(int p, int m, size_t bytes) {
-  // Largest tile exponent e with the padded tile within the LDS budget.
+static std::vector<PassGeom> plan(int p, int m, size_t bytes, Kind work) {
+  // Largest tile exponent e with the padded tile within the LDS budget and
+  // at most 1024 threads x p^kreg elements (each thread loads p^kreg).
   const size_t budget = lds_budget(bytes);
+  const int64_t per_block = 1024 * ipow(p, kreg_for(p, work));
   int emax = 0;
   for (int e = 1; e <= 30; ++e) {
     int64_t E = ipow(p, e);
-    if ((size_t)(E + E / 32 + 1) * bytes > budget) break;
+    if ((size_t)(E + E / 32 + 1) * bytes > budget || E > per_block) break;
     emax = e;
   }
   int wpref = 0;
@@ -512,6 +603,8 @@ static int launch_pass(const void* in, void* out, const PassGeom& g, int m, int 
   const int R = (int)ipow(P, d.kreg);
   int threads = std::max(64, std::min(1024, (d.E + R - 1) / R));
   threads = (threads + 63) / 64 * 64;
+  // Every tile element is loaded by exactly the per-thread prefetch.
+  if ((int64_t)threads * PowC<P, KMAX>::v < d.E) return fail(FDWT_EINVAL, "pass tile larger than one workgroup loads");
   const size_t tile_bytes = (size_t)(d.E + d.E / 32 + 1) * sizeof(T);
   const size_t lds = tile_bytes + 8 - tile_bytes % 8 + 16 * sizeof(double);
   const void* fn = red ? (const void*)fwt_pass<P, INV, Tin, T, Tout, KMAX, EPI_REDUCE>
@@ -525,6 +618,12 @@ static int launch_pass(const void* in, void* out, const PassGeom& g, int m, int 
   if (G >= nb) G = nb;
   if (G >= 64) G -= G % 8;
   d.xcd = (G % 8 == 0 && G >= 64) ? 1 : 0;
+  const double elems = (double)ipow(P, m) * batch;
+  const double alg = red ? elems * sizeof(Tin) + (double)ipow(P, m) * sizeof(float2)
+                         : elems * (sizeof(Tin) + sizeof(Tout));
+  const int cls = sizeof(T) >= 16 || std::is_same<T, double>::value ? FDWT_TC_PASS_F64
+                  : (sizeof(T) == 8 ? FDWT_TC_PASS_CF32 : FDWT_TC_PASS_F32);
+  hipEvent_t tb = timed_begin(st);
   if (red) {
     hipLaunchKernelGGL((fwt_pass<P, INV, Tin, T, Tout, KMAX, EPI_REDUCE>), dim3((unsigned)G), dim3(threads), lds,
                        st, (const Tin*)in, (Tout*)out, d);
@@ -533,6 +632,7 @@ static int launch_pass(const void* in, void* out, const PassGeom& g, int m, int 
                        st, (const Tin*)in, (Tout*)out, d);
   }
   FDWT_HIP(hipGetLastError());
+  timed_end(tb, st, cls, alg);
   return FDWT_OK;
 }
 
@@ -588,12 +688,15 @@ struct P2Pass {
   int d0, loge, wdig;
 };
 
-// Two passes cover m <= 24 (4-byte) / 24 (8-byte with a whole-CU tile): a
-// contiguous first pass of up to 2^14 elements, then strided passes over the
-// remaining digits with rows of 64 bytes, split evenly (>= 2^7 elements each).
+// Two passes cover m <= 24: a contiguous first pass of up to 2^14 elements,
+// then strided passes over the remaining digits with rows of 16 elements (64
+// bytes of float, 128 bytes of double: a 128-byte row never shares a cache
+// line with another tile, so the float64 passes, whose tiles of one column
+// are not neighbours in time, do not fetch lines twice), split evenly
+// (>= 2^7 elements per tile).
 static std::vector<P2Pass> plan_p2(int m, size_t bytes) {
   const int emax = (bytes >= 8 && lds_budget(bytes) < 136 * 1024) ? 13 : 14;
-  const int wd = bytes >= 8 ? 3 : 4;
+  const int wd = 4;
   std::vector<P2Pass> out;
   if (m <= emax) {
     out.push_back({0, m, 0});
@@ -642,12 +745,13 @@ template <class Tin, class T, class Tout>
 static int launch_p2(const void* in, void* out, const P2Pass& g, int m, int batch, float scale,
                      const ReduceArgs* red, hipStream_t st) {
   constexpr bool wide = sizeof(T) >= 8;
-  const void* fn;
-  if (red) fn = wide ? (g.wdig ? p2_kernel<Tin, T, Tout, 3, EPI_REDUCE>(g.loge) : p2_kernel<Tin, T, Tout, 0, EPI_REDUCE>(g.loge))
-                     : (g.wdig ? p2_kernel<Tin, T, Tout, 4, EPI_REDUCE>(g.loge) : p2_kernel<Tin, T, Tout, 0, EPI_REDUCE>(g.loge));
-  else fn = wide ? (g.wdig ? p2_kernel<Tin, T, Tout, 3, EPI_STORE>(g.loge) : p2_kernel<Tin, T, Tout, 0, EPI_STORE>(g.loge))
-                 : (g.wdig ? p2_kernel<Tin, T, Tout, 4, EPI_STORE>(g.loge) : p2_kernel<Tin, T, Tout, 0, EPI_STORE>(g.loge));
-  if (!fn || (g.wdig != 0 && g.wdig != (wide ? 3 : 4))) return fail(FDWT_EINVAL, "no static pass shape");
+  const void* fn = nullptr;
+  if (red) {
+    if constexpr (wide) fn = g.wdig ? p2_kernel<Tin, T, Tout, 4, EPI_REDUCE>(g.loge) : p2_kernel<Tin, T, Tout, 0, EPI_REDUCE>(g.loge);
+  } else {
+    fn = g.wdig ? p2_kernel<Tin, T, Tout, 4, EPI_STORE>(g.loge) : p2_kernel<Tin, T, Tout, 0, EPI_STORE>(g.loge);
+  }
+  if (!fn || (g.wdig != 0 && g.wdig != 4)) return fail(FDWT_EINVAL, "no static pass shape");
   const int64_t N = int64_t(1) << m;
   const int E = 1 << g.loge;
   const int threads = std::max(64, std::min(1024, E / 16));
@@ -681,7 +785,11 @@ static int launch_p2(const void* in, void* out, const P2Pass& g, int m, int batc
   if (G >= 64) G -= G % 8;
   d.xcd = (G % 8 == 0 && G >= 64) ? 1 : 0;
   void* args[] = {(void*)&in, (void*)&out, (void*)&d};
+  const double elems = (double)N * batch;
+  const double work = red ? elems * sizeof(Tin) + (double)N * sizeof(float2) : elems * (sizeof(Tin) + sizeof(Tout));
+  hipEvent_t tb = timed_begin(st);
   FDWT_HIP(hipLaunchKernel(fn, dim3((unsigned)G), dim3(threads), args, lds, st));
+  timed_end(tb, st, wide ? FDWT_TC_PASS_F64 : FDWT_TC_PASS_F32, work);
   return FDWT_OK;
 }
 
@@ -719,7 +827,7 @@ static int run_passes(int p, int m, bool inverse, Kind in_kind, const void* in, 
   if (p2_static_ok(p, m, in_kind, work_kind, out_kind))
     return run_p2(m, work_kind, in, out, tmp, batch, scale, red, last_tiles, st);
   const int64_t N = ipow(p, m);
-  std::vector<PassGeom> passes = plan(p, m, kind_bytes(work_kind));
+  std::vector<PassGeom> passes = plan(p, m, kind_bytes(work_kind), work_kind);
   const size_t np = passes.size();
   if (last_tiles) {
     const PassGeom& g = passes.back();
@@ -767,7 +875,7 @@ int fwt_reduce_f64(int p, int m, const double* in, void* tmp, int batch, const f
 
 int64_t fwt_reduce_tiles(int p, int m, size_t elem_bytes) {
   if (p == 2 && m >= 7) return (int64_t(1) << m) >> plan_p2(m, elem_bytes).back().loge;
-  std::vector<PassGeom> passes = plan(p, m, elem_bytes);
+  std::vector<PassGeom> passes = plan(p, m, elem_bytes, elem_bytes >= 16 ? K_CF64 : K_F64);
   const PassGeom& g = passes.back();
   return ipow(p, m) / (ipow(p, g.r) * ipow(p, g.wdig));
 }

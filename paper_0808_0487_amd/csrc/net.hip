@@ -169,12 +169,14 @@ int launch_sample(const Net& net, int family, const double* a, float* f, hipStre
     fa.inv1a[j] = (float)(1.0 / (1.0 + a[j]));
   }
   const unsigned g = grid_for(net.N, 256);
+  hipEvent_t tb = timed_begin(st);
   int rc;
   if (family == FDWT_FAMILY_PRODUCT) rc = sample_fam<FDWT_FAMILY_PRODUCT>(net, fa, f, g, st);
   else if (family == FDWT_FAMILY_EXP) rc = sample_fam<FDWT_FAMILY_EXP>(net, fa, f, g, st);
   else rc = sample_fam<FDWT_FAMILY_WANGFANG>(net, fa, f, g, st);
   if (rc) return rc;
   FDWT_HIP(hipGetLastError());
+  timed_end(tb, st, FDWT_TC_SAMPLE, 4.0 * (double)net.N);
   return FDWT_OK;
 }
 

@@ -312,9 +312,11 @@ static int kcols_launch(const Net& net, const double* tk, const double* tr, int 
   const size_t lds = (size_t)2 * net.s * kTab * 8 + (P == 2 ? (size_t)net.s * 257 * 4 : 0);
   if (int rc = allow_lds((const void*)k_kernel_cols<P, SMAX>, lds)) return rc;
   const unsigned grid = (unsigned)std::min<int64_t>((net.N + kChunk - 1) / kChunk, 2048);
+  hipEvent_t tb = timed_begin(st);
   hipLaunchKernelGGL((k_kernel_cols<P, SMAX>), dim3(grid), dim3(kChunk), lds, st, net_args(net), tk, tr, c0,
                      c1, out);
   FDWT_HIP(hipGetLastError());
+  timed_end(tb, st, FDWT_TC_KCOLS, 8.0 * (double)net.N * (c1 - c0));
   return FDWT_OK;
 }
 
@@ -443,10 +445,12 @@ int run_spline_eval(Net& net, const fdwt_kernel* kern, const float* c, int64_t n
   if (p == 5) hipLaunchKernelGGL(k_query_prep<5>, dim3(grid1((int64_t)s * nq)), dim3(256), 0, st, q, nq, s, m, D, qh, qt);
   FDWT_HIP(hipGetLastError());
   const size_t lds = te_b + (size_t)s * kNS * xb + kNS * 4;
+  hipEvent_t tb = timed_begin(st);
   if (p == 2) rc = launch_eval<2>(net, Xp, c, nq, q, nullptr, nullptr, te, ntab, partial, gy, ppc, lds, st);
   else if (p == 3) rc = launch_eval<3>(net, Xp, c, nq, q, qh, qt, te, ntab, partial, gy, ppc, lds, st);
   else rc = launch_eval<5>(net, Xp, c, nq, q, qh, qt, te, ntab, partial, gy, ppc, lds, st);
   if (rc) return rc;
+  timed_end(tb, st, FDWT_TC_EVAL, (double)nq * (double)N * s);
   hipLaunchKernelGGL(k_eval_finish, dim3(grid1(nq)), dim3(256), 0, st, partial, gy, nq, sf);
   FDWT_HIP(hipGetLastError());
   return FDWT_OK;

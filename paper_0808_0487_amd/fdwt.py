@@ -45,6 +45,8 @@ SIGNATURES = {
     "fdwt_spline_eval": (_i, [_vp, ctypes.POINTER(KernelC), _vp, _i64, _vp, _vp, _vp]),
     "fdwt_walsh_interp": (_i, [_vp, ctypes.POINTER(KernelC), _vp, _vp, _i64, _vp, _vp, _vp]),
     "fdwt_eff_dim": (_i, [_vp, ctypes.POINTER(KernelC), _i, _vp, ctypes.POINTER(EffDimC), _vp]),
+    "fdwt_timing_enable": (_i, [_i]),
+    "fdwt_timing_query": (_i, [_i, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(_i64), ctypes.POINTER(ctypes.c_double)]),
     "fdwt_last_error": (ctypes.c_char_p, []),
 }
 
@@ -231,3 +233,18 @@ class Net:
 
 def query_depth(p):
     return lib().fdwt_query_depth(p)
+
+
+TC = {"pass_f32": 0, "pass_cf32": 1, "pass_f64": 2, "sample": 3, "kcols": 4, "eval": 5}
+
+
+def timing_enable(on=True):
+    _check(lib().fdwt_timing_enable(1 if on else 0))
+
+
+def timing_query(cls):
+    """(total_ms, launches, work) of a kernel class since timing was enabled."""
+    ms, n, w = ctypes.c_double(), ctypes.c_int64(), ctypes.c_double()
+    _check(lib().fdwt_timing_query(TC[cls] if isinstance(cls, str) else cls, ctypes.byref(ms), ctypes.byref(n),
+                                   ctypes.byref(w)))
+    return ms.value, n.value, w.value
