@@ -181,6 +181,44 @@ typedef struct {
 int fdwt_eff_dim(const fdwt_net* net, const fdwt_kernel* kern, int ft_type,
                  const void* ft_dev, fdwt_effdim* out, void* stream);
 
+/* ------------------------------------------------------------- batches */
+
+/* A ragged batch of independent p = 2 forward transforms (float data, job j
+ * of N_j = 2^{m_j} points, 1 <= m_j <= 26, normalised as fdwt_dwt_forward;
+ * in_dev == out_dev allowed).  The transforms are Algorithm 1 applied to raw
+ * data: no net is needed, the output index is the coset label as usual.  Each
+ * job's transform is split into at most three passes; level k of the batch
+ * (pass k of every job that has one) is ONE persistent kernel launch over all
+ * those jobs' tiles, so a batch of any size is at most three launches, and no
+ * workgroup ever waits on another.  Precision:
+ *   FDWT_PREC_F32     float32 butterflies;
+ *   FDWT_PREC_BF16X2  in each job's first pass the stages of index digits
+ *                     0..3 (16-point Walsh-Hadamard blocks) run on the matrix
+ *                     cores as H16 (hi + lo), x split into two bfloat16 terms,
+ *                     float32 accumulation (relative error about 2^-18 per
+ *                     element from the split); other stages float32.
+ * fdwt_batch_create copies the job list to the device (buffers are fixed at
+ * creation); fdwt_batch_run enqueues the level launches (nothing else; it
+ * can be captured in a HIP graph); fdwt_batch_check waits for the stream and
+ * reports any HIP error.  The batch owns its device work list; free it with
+ * fdwt_batch_free (which synchronises the device first).  Jobs' buffers must
+ * not overlap one another. */
+typedef struct {
+  int m;
+  const float* in_dev;
+  float* out_dev;
+} fdwt_batch_job;
+
+#define FDWT_PREC_F32    0
+#define FDWT_PREC_BF16X2 1
+
+typedef struct fdwt_batch fdwt_batch;
+
+int fdwt_batch_create(int n_jobs, const fdwt_batch_job* jobs_host, int precision, fdwt_batch** out);
+int fdwt_batch_run(fdwt_batch* batch, void* stream);
+int fdwt_batch_check(fdwt_batch* batch, void* stream);
+void fdwt_batch_free(fdwt_batch* batch);
+
 /* ------------------------------------------------------------ timing */
 
 /* Per-launch timing of the library's kernels, for benchmarks and tracing.
@@ -199,7 +237,8 @@ int fdwt_eff_dim(const fdwt_net* net, const fdwt_kernel* kern, int ft_type,
 #define FDWT_TC_SAMPLE     3   /* net generation + test-function sampling      */
 #define FDWT_TC_KCOLS      4   /* kernel-data columns (K, R_d - 1, Q_j)        */
 #define FDWT_TC_EVAL       5   /* interpolant evaluation at queries            */
-#define FDWT_TC_COUNT      6
+#define FDWT_TC_BATCH      6   /* one batch run (all its level launches)       */
+#define FDWT_TC_COUNT      7
 
 int fdwt_timing_enable(int on);
 int fdwt_timing_query(int cls, double* total_ms, int64_t* launches, double* work);

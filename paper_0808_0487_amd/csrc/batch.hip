@@ -1,0 +1,275 @@
+// Ragged batches of p = 2 forward transforms.
+//
+// A batch is a list of independent jobs (float data, N_j = 2^{m_j} points,
+// each normalised by 2^-m_j as in Eq. (eq_dwalshcoeff)).  Every job's
+// transform is split into passes (Algorithm 1's stages grouped by digit
+// ranges) and every pass into tiles.  Level k of the batch is the list of all
+// tiles of pass k of every job that has one; each level is one persistent
+// launch whose workgroups take the level's tiles with a fixed stride (largest
+// jobs first), so a batch of any number of jobs is at most three launches and
+// no workgroup ever waits for another: the kernel boundary between levels
+// orders pass k before pass k+1 (on MI355X the L2 of each XCD is not
+// coherent with the others for ordinary device memory inside a kernel).
+//
+// Precision FDWT_PREC_BF16X2: in each job's first pass the stages of index
+// digits 0..3 (16-point Walsh-Hadamard blocks) run on the matrix cores as
+// H16 (hi + lo), with x = hi + lo split into two bfloat16 values, H16's +-1
+// entries exact in bfloat16 and float32 accumulation: one
+// v_mfma_f32_16x16x32_bf16 per 16 vectors of 16 points, A = [H16 | H16],
+// B = [hi ; lo].  All other stages stay in float32.
+#include "pass_core.h"
+
+#include <algorithm>
+#include <cstring>
+
+namespace fdwt {
+
+constexpr int kBThreads = 512;   // threads per workgroup
+constexpr int kBLogE = 13;       // largest tile: 2^13 floats (33 KiB of LDS)
+constexpr int kBMaxPass = 3;
+
+struct BJob {
+  const float* in;
+  float* out;
+  int m;
+  int npass;
+  float scale;            // 2^-m
+  int d0[kBMaxPass], r[kBMaxPass], wdig[kBMaxPass], ntiles[kBMaxPass];
+};
+
+struct BItem {
+  int job, pass, tile, pad_;
+};
+
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
+// Stages of digits 0..3 of a contiguous float tile in LDS on the matrix
+// cores.  Lane l of a wave: vector n = l % 16 of the current 256-point chunk,
+// operand slice q = l / 16.  Operand layout of v_mfma_f32_16x16x32_bf16
+// (checked with a probe on gfx950): A[l%16][8q+i], B[8q+i][l%16] are element i
+// of the lane's A and B vectors; D[4q+i][l%16] is element i of the result.
+__device__ void mfma_low4(float* lds, int E) {
+  const int lane = threadIdx.x & 63;
+  const int wave = threadIdx.x >> 6;
+  const int nw = blockDim.x >> 6;
+  const int n = lane & 15, q = lane >> 4;
+  bf16x8 a;
+#pragma unroll
+  for (int i = 0; i < 8; ++i) {
+    const int k = (8 * q + i) & 15;  // A = [H16 | H16]
+    a[i] = (__builtin_popcount(n & k) & 1) ? (__bf16)(-1.0f) : (__bf16)(1.0f);
+  }
+  for (int c = wave; c < E / 256; c += nw) {
+    const int src = 256 * c + 16 * n + 8 * (q & 1);
+    bf16x8 b;
+#pragma unroll
+    for (int i = 0; i < 8; ++i) {
+      const float x = lds[pad(src + i)];
+      const __bf16 hi = (__bf16)x;
+      b[i] = (q < 2) ? hi : (__bf16)(x - (float)hi);
+    }
+    const f32x4 z = {0.0f, 0.0f, 0.0f, 0.0f};
+    const f32x4 dres = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, z, 0, 0, 0);
+    const int dst = 256 * c + 16 * n + 4 * q;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) lds[pad(dst + i)] = dres[i];
+  }
+}
+
+__global__ void __launch_bounds__(kBThreads) k_batch_fwd(const BJob* __restrict__ jobs, const BItem* __restrict__ items,
+                                                       int n_items, int prec) {
+  extern __shared__ __align__(16) float blds[];
+  for (int it = blockIdx.x; it < n_items; it += gridDim.x) {
+    const BItem I = items[it];
+    const BJob& J = jobs[I.job];
+    const int ps = I.pass;
+    PassDesc d{};
+    d.r = J.r[ps];
+    d.wdig = J.wdig[ps];
+    d.w = 1 << d.wdig;
+    d.sd0 = int64_t(1) << J.d0[ps];
+    d.shi = int64_t(1) << (J.d0[ps] + d.r);
+    d.nlo = 1 << (J.d0[ps] - d.wdig);
+    d.E = 1 << (d.r + d.wdig);
+    d.kreg = 4;
+    const int lo = I.tile % d.nlo, hi = I.tile / d.nlo;
+    const int64_t base = (int64_t)lo * d.w + (int64_t)hi * d.shi;
+    const float* src = (ps == 0 ? J.in : J.out) + base;
+    for (int e = threadIdx.x; e < d.E; e += blockDim.x) {
+      const int c = e & (d.w - 1), i = e >> d.wdig;
+      blds[pad(e)] = src[c + (int64_t)i * d.sd0];
+    }
+    __syncthreads();
+    int q0 = 0;
+    if (prec == FDWT_PREC_BF16X2 && ps == 0 && d.wdig == 0 && d.r >= 8) {
+      mfma_low4(blds, d.E);
+      __syncthreads();
+      q0 = 4;
+    }
+    for (int q = q0; q < d.r; q += 4) {
+      const int kk = min(4, d.r - q);
+      if (kk == 4) run_group<2, false, float, 4>(blds, d, q);
+      else if (kk == 3) run_group<2, false, float, 3>(blds, d, q);
+      else if (kk == 2) run_group<2, false, float, 2>(blds, d, q);
+      else run_group<2, false, float, 1>(blds, d, q);
+      __syncthreads();
+    }
+    const float sc = (ps == J.npass - 1) ? J.scale : 1.0f;
+    float* dst = J.out + base;
+    for (int e = threadIdx.x; e < d.E; e += blockDim.x) {
+      const int c = e & (d.w - 1), i = e >> d.wdig;
+      dst[c + (int64_t)i * d.sd0] = blds[pad(e)] * sc;
+    }
+    __syncthreads();
+  }
+}
+
+}  // namespace fdwt
+
+struct fdwt_batch {
+  int device = 0;
+  int n_jobs = 0, prec = 0;
+  fdwt::BJob* d_jobs = nullptr;
+  fdwt::BItem* d_items = nullptr;
+  int level_begin[fdwt::kBMaxPass + 1] = {0};  // items of level k: [begin[k], begin[k+1])
+  int n_levels = 0;
+  int grid_per_level[fdwt::kBMaxPass] = {0};
+  double alg_bytes = 0.0;
+};
+
+namespace fdwt {
+
+// Pass split of one job with tiles of at most 2^kBLogE elements: a
+// contiguous first pass, then strided passes with rows of 16 floats.
+static int batch_plan_job(int m, BJob& J) {
+  const int emax = kBLogE, wd = 4;
+  J.m = m;
+  if (m <= emax) {
+    J.npass = 1;
+    J.d0[0] = 0;
+    J.r[0] = m;
+    J.wdig[0] = 0;
+  } else {
+    const int rem = m - emax, cap = emax - wd;
+    const int nstr = (rem + cap - 1) / cap;
+    if (nstr + 1 > kBMaxPass) return -1;
+    const int rd = std::max((rem + nstr - 1) / nstr, 1);
+    const int first = m - nstr * rd;
+    J.npass = 1 + nstr;
+    J.d0[0] = 0;
+    J.r[0] = first;
+    J.wdig[0] = 0;
+    for (int i = 0; i < nstr; ++i) {
+      J.d0[1 + i] = first + i * rd;
+      J.r[1 + i] = rd;
+      J.wdig[1 + i] = std::min(wd, first + i * rd);
+    }
+  }
+  for (int k = 0; k < J.npass; ++k) J.ntiles[k] = (int)((int64_t(1) << m) >> (J.r[k] + J.wdig[k]));
+  J.scale = (float)std::ldexp(1.0, -m);
+  return 0;
+}
+
+}  // namespace fdwt
+
+using namespace fdwt;
+
+extern "C" {
+
+int fdwt_batch_create(int n_jobs, const fdwt_batch_job* jobs, int precision, fdwt_batch** out) {
+  if (!out || !jobs || n_jobs < 1 || n_jobs > (1 << 20)) return fail(FDWT_EINVAL, "bad batch arguments");
+  *out = nullptr;
+  if (precision != FDWT_PREC_F32 && precision != FDWT_PREC_BF16X2) return fail(FDWT_EINVAL, "unknown precision");
+  std::vector<BJob> hj(n_jobs);
+  std::vector<BItem> hi;
+  int maxpass = 0;
+  double alg = 0.0;
+  for (int j = 0; j < n_jobs; ++j) {
+    const fdwt_batch_job& u = jobs[j];
+    if (u.m < 1 || u.m > kMaxLog2N) return fail(FDWT_EINVAL, "job m must be in 1..26");
+    if (!u.in_dev || !u.out_dev) return fail(FDWT_EINVAL, "NULL job buffer");
+    BJob& J = hj[j];
+    std::memset(&J, 0, sizeof(J));
+    if (batch_plan_job(u.m, J)) return fail(FDWT_EUNSUPPORTED, "job needs too many passes");
+    J.in = u.in_dev;
+    J.out = u.out_dev;
+    maxpass = std::max(maxpass, J.npass);
+    alg += 8.0 * (double)(int64_t(1) << u.m);
+  }
+  // Level k: every tile of pass k of every job (largest jobs first).
+  std::vector<int> order(n_jobs);
+  for (int j = 0; j < n_jobs; ++j) order[j] = j;
+  std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return hj[a].m > hj[b].m; });
+  int level_begin[kBMaxPass + 1] = {0};
+  for (int ps = 0; ps < maxpass; ++ps) {
+    level_begin[ps] = (int)hi.size();
+    for (int j : order)
+      if (ps < hj[j].npass)
+        for (int t = 0; t < hj[j].ntiles[ps]; ++t) hi.push_back({j, ps, t, 0});
+  }
+  level_begin[maxpass] = (int)hi.size();
+  if (hi.size() > (size_t)INT32_MAX) return fail(FDWT_EINVAL, "batch too large");
+  auto* b = new fdwt_batch();
+  if (hipGetDevice(&b->device) != hipSuccess) {
+    delete b;
+    return fail(FDWT_EDEVICE, "no HIP device");
+  }
+  b->n_jobs = n_jobs;
+  b->prec = precision;
+  b->alg_bytes = alg;
+  b->n_levels = maxpass;
+  for (int k = 0; k <= maxpass; ++k) b->level_begin[k] = level_begin[k];
+  bool ok = hipMalloc(&b->d_jobs, hj.size() * sizeof(BJob)) == hipSuccess &&
+            hipMalloc(&b->d_items, hi.size() * sizeof(BItem)) == hipSuccess;
+  ok = ok && hipMemcpy(b->d_jobs, hj.data(), hj.size() * sizeof(BJob), hipMemcpyHostToDevice) == hipSuccess &&
+       hipMemcpy(b->d_items, hi.data(), hi.size() * sizeof(BItem), hipMemcpyHostToDevice) == hipSuccess;
+  if (!ok) {
+    (void)hipGetLastError();
+    fdwt_batch_free(b);
+    return fail(FDWT_ENOMEM, "batch allocation failed");
+  }
+  const size_t lds = (size_t)((1 << kBLogE) + (1 << kBLogE) / 32 + 1) * sizeof(float);
+  int per_cu = 0, cus = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void*)k_batch_fwd, kBThreads, lds) != hipSuccess ||
+      hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, b->device) != hipSuccess) {
+    (void)hipGetLastError();
+    fdwt_batch_free(b);
+    return fail(FDWT_EDEVICE, "occupancy query failed");
+  }
+  for (int k = 0; k < maxpass; ++k)
+    b->grid_per_level[k] = std::max(1, std::min(level_begin[k + 1] - level_begin[k], std::max(1, per_cu) * cus));
+  *out = b;
+  return FDWT_OK;
+}
+
+int fdwt_batch_run(fdwt_batch* b, void* stream) {
+  if (!b) return fail(FDWT_EINVAL, "NULL batch");
+  hipStream_t st = (hipStream_t)stream;
+  const size_t lds = (size_t)((1 << kBLogE) + (1 << kBLogE) / 32 + 1) * sizeof(float);
+  hipEvent_t tb = timed_begin(st);
+  for (int k = 0; k < b->n_levels; ++k) {
+    const int n = b->level_begin[k + 1] - b->level_begin[k];
+    hipLaunchKernelGGL(k_batch_fwd, dim3(b->grid_per_level[k]), dim3(kBThreads), lds, st, b->d_jobs,
+                       b->d_items + b->level_begin[k], n, b->prec);
+    FDWT_HIP(hipGetLastError());
+  }
+  timed_end(tb, st, FDWT_TC_BATCH, b->alg_bytes);
+  return FDWT_OK;
+}
+
+int fdwt_batch_check(fdwt_batch* b, void* stream) {
+  if (!b) return fail(FDWT_EINVAL, "NULL batch");
+  FDWT_HIP(hipStreamSynchronize((hipStream_t)stream));
+  return FDWT_OK;
+}
+
+void fdwt_batch_free(fdwt_batch* b) {
+  if (!b) return;
+  if (b->d_jobs || b->d_items) (void)hipDeviceSynchronize();
+  if (b->d_jobs) (void)hipFree(b->d_jobs);
+  if (b->d_items) (void)hipFree(b->d_items);
+  delete b;
+}
+
+}  // extern "C"

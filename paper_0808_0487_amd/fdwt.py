@@ -45,6 +45,10 @@ SIGNATURES = {
     "fdwt_spline_eval": (_i, [_vp, ctypes.POINTER(KernelC), _vp, _i64, _vp, _vp, _vp]),
     "fdwt_walsh_interp": (_i, [_vp, ctypes.POINTER(KernelC), _vp, _vp, _i64, _vp, _vp, _vp]),
     "fdwt_eff_dim": (_i, [_vp, ctypes.POINTER(KernelC), _i, _vp, ctypes.POINTER(EffDimC), _vp]),
+    "fdwt_batch_create": (_i, [_i, _vp, _i, ctypes.POINTER(_vp)]),
+    "fdwt_batch_run": (_i, [_vp, _vp]),
+    "fdwt_batch_check": (_i, [_vp, _vp]),
+    "fdwt_batch_free": (None, [_vp]),
     "fdwt_timing_enable": (_i, [_i]),
     "fdwt_timing_query": (_i, [_i, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(_i64), ctypes.POINTER(ctypes.c_double)]),
     "fdwt_last_error": (ctypes.c_char_p, []),
@@ -99,6 +103,46 @@ def _ptr(t):
 def _type_of(t):
     import torch
     return {torch.float32: F32, torch.int32: I32, torch.complex64: CF32}[t.dtype]
+
+
+class BatchJobC(ctypes.Structure):
+    _fields_ = [("m", ctypes.c_int), ("in_dev", ctypes.c_void_p), ("out_dev", ctypes.c_void_p)]
+
+
+PREC = {"f32": 0, "bf16x2": 1}
+
+
+class Batch:
+    """A ragged batch of p = 2 forward transforms run in one persistent
+    launch (fdwt_batch_*).  jobs: list of (m, in_tensor, out_tensor)."""
+
+    def __init__(self, jobs, precision="f32"):
+        arr = (BatchJobC * len(jobs))()
+        for i, (m, x, y) in enumerate(jobs):
+            if x.dtype.itemsize != 4 or x.numel() != 2 ** m or y.numel() != 2 ** m:
+                raise ValueError("job %d: float tensors of 2^m elements expected" % i)
+            arr[i] = BatchJobC(m, _ptr(x).value, _ptr(y).value)
+        self._keep = jobs
+        h = ctypes.c_void_p()
+        _check(lib().fdwt_batch_create(len(jobs), ctypes.cast(arr, ctypes.c_void_p), PREC[precision], ctypes.byref(h)))
+        self.h = h
+
+    def run(self, stream=None):
+        _check(lib().fdwt_batch_run(self.h, _stream(stream)))
+
+    def check(self, stream=None):
+        _check(lib().fdwt_batch_check(self.h, _stream(stream)))
+
+    def close(self):
+        if self.h:
+            lib().fdwt_batch_free(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 class Kernel:
@@ -235,7 +279,7 @@ def query_depth(p):
     return lib().fdwt_query_depth(p)
 
 
-TC = {"pass_f32": 0, "pass_cf32": 1, "pass_f64": 2, "sample": 3, "kcols": 4, "eval": 5}
+TC = {"pass_f32": 0, "pass_cf32": 1, "pass_f64": 2, "sample": 3, "kcols": 4, "eval": 5, "batch": 6}
 
 
 def timing_enable(on=True):

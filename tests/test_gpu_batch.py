@@ -1,0 +1,117 @@
+"""Ragged batches of p = 2 transforms in one persistent launch, against the
+oracle, alone vs in the mix, and under HIP-graph capture."""
+import numpy as np
+import pytest
+import torch
+
+from oracle import walsh
+from paper_0808_0487_amd import fdwt, inputs
+from tests.gpu_common import announce, nrel, sample_indices
+
+pytestmark = pytest.mark.gpu
+
+
+def make_jobs(ms, seed):
+    jobs = []
+    for i, m in enumerate(ms):
+        x = torch.from_numpy(inputs.uniform_float(2 ** m, seed + i)).cuda()
+        jobs.append((m, x, torch.empty_like(x)))
+    return jobs
+
+
+def check_against_oracle(jobs, tol, seed):
+    for i, (m, x, y) in enumerate(jobs):
+        f = x.cpu().numpy().astype(np.float64)
+        hs = sample_indices(2 ** m, 64, seed + i)
+        err = nrel(y.cpu().numpy()[hs], walsh.dwt_phase(2, m, f, hs))
+        assert err <= tol, (i, m, err)
+
+
+MS = [7, 9, 12, 13, 14, 15, 17, 20, 22, 8, 16, 19, 21, 13, 10]
+
+
+@pytest.mark.parametrize("prec,tol", [("f32", 1e-5), ("bf16x2", 2e-5)])
+def test_ragged_batch_against_oracle(prec, tol):
+    announce("batch", prec)
+    jobs = make_jobs(MS, 500)
+    b = fdwt.Batch(jobs, precision=prec)
+    b.run()
+    b.check()
+    check_against_oracle(jobs, tol, 500)
+    b.close()
+
+
+def test_bf16_split_error_is_reported_scale():
+    """The two-term bfloat16 split represents x to about 2^-18; the batched
+    result stays within 1e-5 normwise of the float64 transform, and differs
+    from the float32 path by more than float32 rounding (the MFMA path ran)."""
+    announce("bf16 split error")
+    m = 16
+    jobs32 = make_jobs([m], 900)
+    jobs16 = [(m, jobs32[0][1], torch.empty_like(jobs32[0][1]))]
+    fdwt.Batch(jobs32, "f32").run()
+    fdwt.Batch(jobs16, "bf16x2").run()
+    torch.cuda.synchronize()
+    f = jobs32[0][1].cpu().numpy().astype(np.float64)
+    ref = np.fft.fftn(f.reshape([2] * m, order="F")).reshape(2 ** m, order="F").real / 2 ** m
+    e32 = nrel(jobs32[0][2].cpu().numpy(), ref)
+    e16 = nrel(jobs16[0][2].cpu().numpy(), ref)
+    assert e32 <= 1e-6 and e16 <= 1e-5 and e16 > 2 * e32, (e32, e16)
+
+
+def test_alone_equals_in_the_mix_bit_identical():
+    announce("batch alone vs mix")
+    jobs = make_jobs(MS, 600)
+    fdwt.Batch(jobs, "f32").run()
+    torch.cuda.synchronize()
+    for i in [0, 3, 8, 12]:
+        m, x, y = jobs[i]
+        z = torch.empty_like(x)
+        fdwt.Batch([(m, x, z)], "f32").run()
+        torch.cuda.synchronize()
+        assert torch.equal(y, z), i
+
+
+def test_in_place_and_against_single_transform():
+    announce("batch in place")
+    m = 18
+    x = torch.from_numpy(inputs.uniform_float(2 ** m, 7)).cuda()
+    y = x.clone()
+    fdwt.Batch([(m, y, y)], "f32").run()
+    net = fdwt.Net(2, m, 1, inputs.identity_generators(2, m, 1))
+    ref = net.forward(x)
+    torch.cuda.synchronize()
+    assert float(torch.linalg.norm(y - ref) / torch.linalg.norm(ref)) <= 1e-6
+
+
+def test_graph_capture_replays_match_eager():
+    announce("batch graph capture")
+    jobs = make_jobs([12, 16, 19], 700)
+    b = fdwt.Batch(jobs, "f32")
+    b.run()
+    torch.cuda.synchronize()
+    eager = [y.clone() for _, _, y in jobs]
+    for _, _, y in jobs:
+        y.zero_()
+    s = torch.cuda.Stream()
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g, stream=s):
+        b.run(stream=s)
+    for rep in range(3):
+        for _, _, y in jobs:
+            y.fill_(float(rep + 1))
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        for e, (_, _, y) in zip(eager, jobs):
+            assert torch.equal(e, y), rep
+    b.check()
+
+
+def test_batch_rejects_bad_jobs():
+    x = torch.empty(16, device="cuda")
+    with pytest.raises(ValueError):
+        fdwt.Batch([(5, x, x)])
+    with pytest.raises(KeyError):
+        fdwt.Batch([(4, x, x)], precision="fp8")
