@@ -46,6 +46,8 @@ def parse():
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle timing")
     ap.add_argument("--calib-copy", action="store_true",
                     help="after timing, run a 256 MiB device copy (reference for HBM byte counters)")
+    ap.add_argument("--no-batch", action="store_true", help="skip the ragged-batch leg")
+    ap.add_argument("--batch-jobs", type=int, default=512)
     ap.add_argument("--m", type=int, default=24)
     ap.add_argument("--s", type=int, default=20)
     return ap.parse_args()
@@ -96,6 +98,82 @@ def cpu_baseline(p, m, s, C, budget_s=15.0):
             "sample": "oracle net+f for all %d points (%.1f s) and %d forward coefficients by the direct "
                       "O(N) sum (%.3f s each, numpy, one thread), extrapolated to all N coefficients; "
                       "spline and eff_dim (O(N^2) in the oracle) not included" % (N, t_net, done, t_coef)}
+
+
+def batched_leg(torch, fdwt, inputs, n_jobs, reps=5):
+    """Ragged batch of n_jobs p = 2 functions (m in 12..22, s in 5..50,
+    product family with alpha in [1, 3]): sampled on their own nets, then
+    transformed (a) one job at a time with the plain transform, (b) as one
+    batch in float32, (c) as one batch with the bfloat16-split matrix-core
+    low stages, (d) the float32 batch replayed from a captured graph.
+    Accuracy of each path: normwise error per job against the library's
+    float64 transform of the same data."""
+    specs = inputs.batch_jobs(n_jobs, seed=4)
+    nets, xs = [], []
+    for (m, s, alpha, cseed) in specs:
+        net = fdwt.Net(2, m, s, inputs.upper_triangular_generators(2, m, s, cseed))
+        x = torch.empty(2 ** m, dtype=torch.float32, device="cuda")
+        net.sample("product", inputs.family_params("product", s, alpha=alpha), out=x)
+        nets.append(net)
+        xs.append(x)
+    total = float(sum(2 ** sp[0] for sp in specs))
+    y_plain = [torch.empty_like(x) for x in xs]
+    y32 = [torch.empty_like(x) for x in xs]
+    y16 = [torch.empty_like(x) for x in xs]
+    b32 = fdwt.Batch([(sp[0], x, y) for sp, x, y in zip(specs, xs, y32)], "f32")
+    b16 = fdwt.Batch([(sp[0], x, y) for sp, x, y in zip(specs, xs, y16)], "bf16x2")
+    stream = torch.cuda.current_stream()
+
+    def timed(fn):
+        fn()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        best = []
+        for _ in range(reps):
+            e0.record(stream)
+            fn()
+            e1.record(stream)
+            torch.cuda.synchronize()
+            best.append(e0.elapsed_time(e1))
+        return float(np.median(best))
+
+    def plain():
+        for net, x, y in zip(nets, xs, y_plain):
+            net.forward(x, out=y)
+
+    t_plain = timed(plain)
+    t32 = timed(b32.run)
+    t16 = timed(b16.run)
+    g = torch.cuda.CUDAGraph()
+    gs = torch.cuda.Stream()
+    torch.cuda.synchronize()
+    with torch.cuda.graph(g, stream=gs):
+        b32.run(stream=gs)
+    t_graph = timed(g.replay)
+    b32.check()
+    errs = {"plain": [], "f32": [], "bf16x2": []}
+    for net, x, yp, ya, yb in zip(nets, xs, y_plain, y32, y16):
+        ref = net.forward(x.double())
+        den = float(torch.linalg.norm(ref))
+        for k, y in (("plain", yp), ("f32", ya), ("bf16x2", yb)):
+            errs[k].append(float(torch.linalg.norm(y.double() - ref)) / den)
+    for net in nets:
+        net.close()
+    b32.close()
+    b16.close()
+
+    def path(t, key):
+        e = np.array(errs[key])
+        return {"ms": t, "points_per_s": total / (t * 1e-3), "alg_GBs": 8.0 * total / (t * 1e-3) / 1e9,
+                "err_vs_f64_max": float(e.max()), "err_vs_f64_median": float(np.median(e))}
+
+    return {"jobs": n_jobs, "points": int(total),
+            "recipe": "m uniform 12..22, s uniform 5..50, product family a_j = j^-alpha, alpha uniform [1,3], "
+                      "seed 4; sampling untimed; median of %d runs" % reps,
+            "plain_per_job": path(t_plain, "plain"), "batch_f32": path(t32, "f32"),
+            "batch_bf16x2": path(t16, "bf16x2"),
+            "batch_f32_graph": {"ms": t_graph, "points_per_s": total / (t_graph * 1e-3)},
+            "speedup_batch_vs_plain": t_plain / t32}
 
 
 def main():
@@ -201,6 +279,8 @@ def main():
         "kernel_source_hash": kernel_source_hash(),
         "wall_s": wall,
     }
+    if not args.no_batch:
+        out["batched"] = batched_leg(torch, fdwt, inputs, args.batch_jobs)
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(p, m, s, C)
     print(json.dumps(out), flush=True)

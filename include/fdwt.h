@@ -46,6 +46,8 @@ extern "C" {
 #define FDWT_F32  1   /* float                                               */
 #define FDWT_I32  2   /* int32, arithmetic modulo 2^32 (p = 2 only)          */
 #define FDWT_CF32 3   /* complex float, interleaved (re, im)                 */
+#define FDWT_F64  4   /* double                                              */
+#define FDWT_CF64 5   /* complex double, interleaved (re, im)                */
 
 typedef struct fdwt_net fdwt_net;
 
@@ -98,7 +100,9 @@ int fdwt_sample(const fdwt_net* net, int family, const double* a_host, float* f_
  *     p = 2:  F32 -> F32 (normalised as above);
  *             I32 -> I32 (NOT normalised: out = p^m times the coefficient,
  *                         exact modulo 2^32);
- *     p odd:  F32 -> CF32, CF32 -> CF32 (normalised).
+ *             F64 -> F64 (normalised; a double-precision reference path);
+ *     p odd:  F32 -> CF32, CF32 -> CF32 (normalised);
+ *             F64 -> CF64, CF64 -> CF64 (normalised, double precision).
  * in_dev and out_dev may be the same buffer when both types have the same
  * size.  Sizes: N elements each. */
 int fdwt_dwt_forward(const fdwt_net* net, int in_type, const void* in_dev,
@@ -106,9 +110,10 @@ int fdwt_dwt_forward(const fdwt_net* net, int in_type, const void* in_dev,
 
 /* Inverse transform, Algorithm 2 (Section 3.3), the Lemma's sum:
  *     out[n] = sum_h in[h] omega_p^(+n_vec . h_vec)   (no normalisation).
- * Allowed: p = 2: F32 -> F32, I32 -> I32 (mod 2^32); p odd: CF32 -> CF32, and
- * CF32 -> F32, which returns the real part (exact result when the input is
- * the transform of real data).  In place allowed for equal sizes. */
+ * Allowed: p = 2: F32 -> F32, I32 -> I32 (mod 2^32), F64 -> F64; p odd:
+ * CF32 -> CF32, and CF32 -> F32, which returns the real part (exact result
+ * when the input is the transform of real data); likewise CF64 -> CF64 and
+ * CF64 -> F64.  In place allowed for equal sizes. */
 int fdwt_dwt_inverse(const fdwt_net* net, int in_type, const void* in_dev,
                      int out_type, void* out_dev, void* stream);
 

@@ -185,12 +185,14 @@ static Kind to_kind(int t) {
     case FDWT_F32: return K_F32;
     case FDWT_I32: return K_U32;
     case FDWT_CF32: return K_CF32;
+    case FDWT_F64: return K_F64;
+    case FDWT_CF64: return K_CF64;
   }
   return (Kind)-1;
 }
 
 int fwt_run_tmp(int p, int m, bool inverse, Kind in_kind, const void* in, Kind work_kind,
-                Kind out_kind, void* out, void* tmp, int batch, float scale, hipStream_t st);
+                Kind out_kind, void* out, void* tmp, int batch, double scale, hipStream_t st);
 
 static int transform(Net& net, bool inverse, int in_type, const void* in, int out_type, void* out,
                      hipStream_t st) {
@@ -198,16 +200,18 @@ static int transform(Net& net, bool inverse, int in_type, const void* in, int ou
   Kind ik = to_kind(in_type), ok = to_kind(out_type), wk;
   if ((int)ik < 0 || (int)ok < 0) return fail(FDWT_EINVAL, "unknown element type");
   if (net.p == 2) {
-    if (!((ik == K_F32 && ok == K_F32) || (ik == K_U32 && ok == K_U32)))
-      return fail(FDWT_EINVAL, "p = 2 transforms are F32 -> F32 or I32 -> I32");
+    if (!((ik == K_F32 && ok == K_F32) || (ik == K_U32 && ok == K_U32) || (ik == K_F64 && ok == K_F64)))
+      return fail(FDWT_EINVAL, "p = 2 transforms are F32 -> F32, I32 -> I32 or F64 -> F64");
     wk = ik;
   } else {
-    const bool okf = inverse ? (ik == K_CF32 && (ok == K_CF32 || ok == K_F32))
-                             : ((ik == K_F32 || ik == K_CF32) && ok == K_CF32);
-    if (!okf)
-      return fail(FDWT_EINVAL, inverse ? "odd-p inverse takes CF32 to CF32 or F32"
-                                       : "odd-p forward takes F32 or CF32 to CF32");
-    wk = K_CF32;
+    const bool dbl = (ik == K_F64 || ik == K_CF64);
+    const Kind re = dbl ? K_F64 : K_F32, cx = dbl ? K_CF64 : K_CF32;
+    const bool okf = inverse ? (ik == cx && (ok == cx || ok == re))
+                             : ((ik == re || ik == cx) && ok == cx);
+    if (!okf || ik == K_U32)
+      return fail(FDWT_EINVAL, inverse ? "odd-p inverse takes CF32 to CF32 or F32 (CF64 to CF64 or F64)"
+                                       : "odd-p forward takes F32 or CF32 to CF32 (F64 or CF64 to CF64)");
+    wk = cx;
   }
   if (in == out && kind_bytes(ik) != kind_bytes(ok))
     return fail(FDWT_EINVAL, "in-place transform needs equal input and output element sizes");
@@ -217,8 +221,7 @@ static int transform(Net& net, bool inverse, int in_type, const void* in, int ou
     if (rc) return rc;
     tmp = net.ws;
   }
-  const float scale =
-      (!inverse && wk != K_U32) ? (float)(1.0 / (double)net.N) : 1.0f;  // Eq. (eq_dwalshcoeff)
+  const double scale = (!inverse && wk != K_U32) ? 1.0 / (double)net.N : 1.0;  // Eq. (eq_dwalshcoeff)
   return fwt_run_tmp(net.p, net.m, inverse, ik, in, wk, ok, out, tmp, 1, scale, st);
 }
 

@@ -92,7 +92,7 @@ size_t kind_bytes(Kind k);
 // as CF32 -> F32 and CF64 -> F64 (real part).
 // scale multiplies float-based outputs of the last pass (1 = none).
 int fwt_run(int p, int m, bool inverse, Kind in_kind, const void* in, Kind work_kind,
-            Kind out_kind, void* out, int batch, float scale, hipStream_t st);
+            Kind out_kind, void* out, int batch, double scale, hipStream_t st);
 
 // spline.hip / effdim.hip
 int run_spline_coef(Net& net, const fdwt_kernel* kern, int ft_type, const void* ft, float* c,

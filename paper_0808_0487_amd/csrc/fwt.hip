@@ -116,7 +116,7 @@ __global__ void __launch_bounds__(1024) fwt_pass(const Tin* __restrict__ in, Tou
       for (int e = threadIdx.x; e < d.E; e += blockDim.x) {
         const uint32_t c = (uint32_t)Ix<P>::mod(e, d.wdig, d.w);
         const uint32_t i = (uint32_t)Ix<P>::div(e, d.wdig, d.w);
-        dst[c + i * sd0] = cvt_out<T, Tout>(lds[pad(e)], d.scale);
+        dst[c + i * sd0] = cvt_out<T, Tout>(lds[pad(e)], d.scale, d.scale64);
       }
     } else {
       double acc = 0.0;
@@ -308,7 +308,7 @@ __global__ void __launch_bounds__((P2Shape<LOGE, WDIG>::THREADS))
       if constexpr (EPI == EPI_STORE) {
         Tout* dst = out + (int64_t)col * d.col_out + base + goffS;
 #pragma unroll
-        for (int k = 0; k < EPT; ++k) dst[k * gstepS] = cvt_out<T, Tout>(v[k], d.scale);
+        for (int k = 0; k < EPT; ++k) dst[k * gstepS] = cvt_out<T, Tout>(v[k], d.scale, d.scale64);
       } else {
         double acc = 0.0;
 #pragma unroll
@@ -352,7 +352,7 @@ __global__ void __launch_bounds__((P2Shape<LOGE, WDIG>::THREADS))
     if constexpr (EPI == EPI_STORE) {
       Tout* dst = out + (int64_t)col * d.col_out + base + goff0;
 #pragma unroll
-      for (int k = 0; k < EPT; ++k) dst[k * gstep] = cvt_out<T, Tout>(lrow[cpad(k * TH)], d.scale);
+      for (int k = 0; k < EPT; ++k) dst[k * gstep] = cvt_out<T, Tout>(lrow[cpad(k * TH)], d.scale, d.scale64);
     } else {
       double acc = 0.0;
 #pragma unroll
@@ -458,7 +458,7 @@ struct ReduceArgs {
 };
 
 template <int P, bool INV, class Tin, class T, class Tout>
-static int launch_pass(const void* in, void* out, const PassGeom& g, int m, int batch, float scale,
+static int launch_pass(const void* in, void* out, const PassGeom& g, int m, int batch, double scale,
                        int64_t col_in, int64_t col_out, Kind work, const ReduceArgs* red, hipStream_t st) {
   constexpr int KMAX = (P == 2) ? 4 : ((P == 3 || sizeof(T) <= 8) ? 2 : 1);
   PassDesc d{};
@@ -472,7 +472,8 @@ static int launch_pass(const void* in, void* out, const PassGeom& g, int m, int 
   d.nlo = (int)ipow(P, g.d0 - g.wdig);
   d.E = (int)ipow(P, g.r) * d.w;
   d.kreg = std::min(kreg_for(P, work), KMAX);
-  d.scale = scale;
+  d.scale = (float)scale;
+  d.scale64 = scale;
   const int64_t ntiles = ipow(P, m) / d.E;
   const int64_t nb = ntiles * batch;
   d.ntiles = (int)ntiles;
@@ -524,7 +525,7 @@ static int launch_pass(const void* in, void* out, const PassGeom& g, int m, int 
 // Dispatch on (p, direction, in/work/out kinds).
 template <int P, bool INV>
 static int pass_dispatch(Kind ik, Kind wk, Kind ok, const void* in, void* out, const PassGeom& g,
-                         int m, int batch, float scale, int64_t ci, int64_t co, const ReduceArgs* red,
+                         int m, int batch, double scale, int64_t ci, int64_t co, const ReduceArgs* red,
                          hipStream_t st) {
 #define FDWT_PASS(TIN, T, TOUT) \
   return launch_pass<P, INV, TIN, T, TOUT>(in, out, g, m, batch, scale, ci, co, wk, red, st)
@@ -552,7 +553,7 @@ static int pass_dispatch(Kind ik, Kind wk, Kind ok, const void* in, void* out, c
 }
 
 static int pass_any(int p, bool inv, Kind ik, Kind wk, Kind ok, const void* in, void* out,
-                    const PassGeom& g, int m, int batch, float scale, int64_t ci, int64_t co,
+                    const PassGeom& g, int m, int batch, double scale, int64_t ci, int64_t co,
                     const ReduceArgs* red, hipStream_t st) {
   switch (p) {
     case 2:
@@ -627,7 +628,7 @@ static int occupancy(const void* fn, int threads, size_t lds) {
 }
 
 template <class Tin, class T, class Tout>
-static int launch_p2(const void* in, void* out, const P2Pass& g, int m, int batch, float scale,
+static int launch_p2(const void* in, void* out, const P2Pass& g, int m, int batch, double scale,
                      const ReduceArgs* red, hipStream_t st) {
   constexpr bool wide = sizeof(T) >= 8;
   const void* fn = nullptr;
@@ -650,7 +651,8 @@ static int launch_p2(const void* in, void* out, const P2Pass& g, int m, int batc
   d.w = 1 << g.wdig;
   d.nlo = (int)(int64_t(1) << (g.d0 - g.wdig));
   d.E = E;
-  d.scale = scale;
+  d.scale = (float)scale;
+  d.scale64 = scale;
   const int64_t ntiles = N / E;
   const int64_t nb = ntiles * batch;
   d.ntiles = (int)ntiles;
@@ -678,7 +680,7 @@ static int launch_p2(const void* in, void* out, const P2Pass& g, int m, int batc
   return FDWT_OK;
 }
 
-static int p2_pass(Kind k, const void* in, void* out, const P2Pass& g, int m, int batch, float scale,
+static int p2_pass(Kind k, const void* in, void* out, const P2Pass& g, int m, int batch, double scale,
                    const ReduceArgs* red, hipStream_t st) {
   if (k == K_F32 && !red) return launch_p2<float, float, float>(in, out, g, m, batch, scale, nullptr, st);
   if (k == K_U32 && !red) return launch_p2<uint32_t, uint32_t, uint32_t>(in, out, g, m, batch, scale, nullptr, st);
@@ -692,7 +694,7 @@ static bool p2_static_ok(int p, int m, Kind ik, Kind wk, Kind ok) {
   return p == 2 && m >= 7 && ik == wk && ok == wk && (wk == K_F32 || wk == K_U32 || wk == K_F64);
 }
 
-static int run_p2(int m, Kind k, const void* in, void* out, void* tmp, int batch, float scale,
+static int run_p2(int m, Kind k, const void* in, void* out, void* tmp, int batch, double scale,
                   const ReduceArgs* red, int64_t* last_tiles, hipStream_t st) {
   const std::vector<P2Pass> passes = plan_p2(m, kind_bytes(k));
   const size_t np = passes.size();
@@ -707,7 +709,7 @@ static int run_p2(int m, Kind k, const void* in, void* out, void* tmp, int batch
 }
 
 static int run_passes(int p, int m, bool inverse, Kind in_kind, const void* in, Kind work_kind,
-                      Kind out_kind, void* out, void* tmp, int batch, float scale, const ReduceArgs* red,
+                      Kind out_kind, void* out, void* tmp, int batch, double scale, const ReduceArgs* red,
                       int64_t* last_tiles, hipStream_t st) {
   if (p2_static_ok(p, m, in_kind, work_kind, out_kind))
     return run_p2(m, work_kind, in, out, tmp, batch, scale, red, last_tiles, st);
@@ -737,13 +739,13 @@ static int run_passes(int p, int m, bool inverse, Kind in_kind, const void* in, 
 }
 
 int fwt_run_tmp(int p, int m, bool inverse, Kind in_kind, const void* in, Kind work_kind,
-                Kind out_kind, void* out, void* tmp, int batch, float scale, hipStream_t st) {
+                Kind out_kind, void* out, void* tmp, int batch, double scale, hipStream_t st) {
   return run_passes(p, m, inverse, in_kind, in, work_kind, out_kind, out, tmp, batch, scale, nullptr,
                     nullptr, st);
 }
 
 int fwt_run(int p, int m, bool inverse, Kind in_kind, const void* in, Kind work_kind,
-            Kind out_kind, void* out, int batch, float scale, hipStream_t st) {
+            Kind out_kind, void* out, int batch, double scale, hipStream_t st) {
   return fwt_run_tmp(p, m, inverse, in_kind, in, work_kind, out_kind, out, nullptr, batch, scale, st);
 }
 

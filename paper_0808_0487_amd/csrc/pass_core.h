@@ -22,6 +22,7 @@ struct PassDesc {
   int32_t ntiles;   // tiles per column
   int32_t batch;    // columns
   float scale;      // multiplies float-based outputs (last pass only)
+  double scale64;   // the same factor for double-based outputs
   // Grouped-sum epilogue (EPI_REDUCE): instead of storing, accumulate
   // sum_h wts[h].x * clamp(value(h) * wts[h].y, 0, 1) per column into
   // partial[col * ntiles + tile]; the value at h = 0 of column h0_col goes to
@@ -45,15 +46,16 @@ template <> __device__ __forceinline__ double cvt_in<double, double>(double v) {
 template <> __device__ __forceinline__ double2 cvt_in<double, double2>(double v) { return make_double2(v, 0.0); }
 template <> __device__ __forceinline__ double2 cvt_in<double2, double2>(double2 v) { return v; }
 
+// sc scales float-based outputs, sc64 double-based ones.
 template <class T, class Tout>
-__device__ __forceinline__ Tout cvt_out(T v, float sc);
-template <> __device__ __forceinline__ float cvt_out<float, float>(float v, float sc) { return v * sc; }
-template <> __device__ __forceinline__ uint32_t cvt_out<uint32_t, uint32_t>(uint32_t v, float) { return v; }
-template <> __device__ __forceinline__ float2 cvt_out<float2, float2>(float2 v, float sc) { return make_float2(v.x * sc, v.y * sc); }
-template <> __device__ __forceinline__ float cvt_out<float2, float>(float2 v, float sc) { return v.x * sc; }
-template <> __device__ __forceinline__ double cvt_out<double, double>(double v, float) { return v; }
-template <> __device__ __forceinline__ double2 cvt_out<double2, double2>(double2 v, float) { return v; }
-template <> __device__ __forceinline__ double cvt_out<double2, double>(double2 v, float) { return v.x; }
+__device__ __forceinline__ Tout cvt_out(T v, float sc, double sc64);
+template <> __device__ __forceinline__ float cvt_out<float, float>(float v, float sc, double) { return v * sc; }
+template <> __device__ __forceinline__ uint32_t cvt_out<uint32_t, uint32_t>(uint32_t v, float, double) { return v; }
+template <> __device__ __forceinline__ float2 cvt_out<float2, float2>(float2 v, float sc, double) { return make_float2(v.x * sc, v.y * sc); }
+template <> __device__ __forceinline__ float cvt_out<float2, float>(float2 v, float sc, double) { return v.x * sc; }
+template <> __device__ __forceinline__ double cvt_out<double, double>(double v, float, double sc) { return v * sc; }
+template <> __device__ __forceinline__ double2 cvt_out<double2, double2>(double2 v, float, double sc) { return make_double2(v.x * sc, v.y * sc); }
+template <> __device__ __forceinline__ double cvt_out<double2, double>(double2 v, float, double sc) { return v.x * sc; }
 
 // Real part as double (the grouped-sum epilogue).
 __device__ __forceinline__ double real_of(double v) { return v; }

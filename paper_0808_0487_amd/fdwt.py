@@ -14,7 +14,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libfdwt.so")
 
 OK, EINVAL, ENOMEM, EDEVICE, EBUDGET, EUNSUPPORTED = 0, -1, -2, -3, -4, -5
-F32, I32, CF32 = 1, 2, 3
+F32, I32, CF32, F64, CF64 = 1, 2, 3, 4, 5
 FAMILY = {"product": 1, "exp": 2, "wangfang": 3}
 
 # Every function the header declares, with (restype, argtypes).
@@ -102,7 +102,8 @@ def _ptr(t):
 
 def _type_of(t):
     import torch
-    return {torch.float32: F32, torch.int32: I32, torch.complex64: CF32}[t.dtype]
+    return {torch.float32: F32, torch.int32: I32, torch.complex64: CF32,
+            torch.float64: F64, torch.complex128: CF64}[t.dtype]
 
 
 class BatchJobC(ctypes.Structure):
@@ -113,8 +114,9 @@ PREC = {"f32": 0, "bf16x2": 1}
 
 
 class Batch:
-    """A ragged batch of p = 2 forward transforms run in one persistent
-    launch (fdwt_batch_*).  jobs: list of (m, in_tensor, out_tensor)."""
+    """A ragged batch of p = 2 forward transforms (fdwt_batch_*): one
+    persistent launch per pass level over all jobs' tiles.
+    jobs: list of (m, in_tensor, out_tensor)."""
 
     def __init__(self, jobs, precision="f32"):
         arr = (BatchJobC * len(jobs))()
@@ -215,11 +217,14 @@ class Net:
     # --------------------------------------------------------- transforms
     def forward(self, x, out=None, stream=None):
         """dwt_forward: float32 -> float32 (p = 2) or complex64 (p odd);
-        int32 -> int32 (p = 2, unnormalised, mod 2^32)."""
+        int32 -> int32 (p = 2, unnormalised, mod 2^32); float64 -> float64
+        (p = 2) or complex128 (p odd)."""
         import torch
         if out is None:
             if x.dtype == torch.int32:
                 dt = torch.int32
+            elif x.dtype in (torch.float64, torch.complex128):
+                dt = torch.float64 if self.p == 2 else torch.complex128
             else:
                 dt = torch.float32 if self.p == 2 else torch.complex64
             out = torch.empty(self.N, dtype=dt, device=x.device)
@@ -234,6 +239,8 @@ class Net:
             dt = x.dtype
             if real and x.dtype == torch.complex64:
                 dt = torch.float32
+            elif real and x.dtype == torch.complex128:
+                dt = torch.float64
             out = torch.empty(self.N, dtype=dt, device=x.device)
         _check(lib().fdwt_dwt_inverse(self.h, _type_of(x), _ptr(x), _type_of(out), _ptr(out), _stream(stream)))
         return out

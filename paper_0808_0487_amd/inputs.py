@@ -106,3 +106,17 @@ def log_uniform_m(g, lo, hi, p, cap_points=1 << 26):
     m = int(round(math.exp(g.uniform(math.log(lo), math.log(hi)))))
     mmax = int(math.floor(math.log(cap_points) / math.log(p) + 1e-9))
     return max(1, min(m, mmax))
+
+
+def batch_jobs(n, seed, m_lo=12, m_hi=22, s_lo=5, s_hi=50):
+    """Ragged batch recipe: per job (m, s, alpha, generator seed) with m
+    uniform in m_lo..m_hi, s uniform in s_lo..s_hi and the product family's
+    alpha uniform in [1, 3]."""
+    g = rng(seed)
+    out = []
+    for i in range(n):
+        m = int(g.integers(m_lo, m_hi + 1))
+        s = int(g.integers(s_lo, s_hi + 1))
+        alpha = float(g.uniform(1.0, 3.0))
+        out.append((m, s, alpha, 10_000 + 7 * seed + i))
+    return out

@@ -1,5 +1,5 @@
-"""Ragged batches of p = 2 transforms in one persistent launch, against the
-oracle, alone vs in the mix, and under HIP-graph capture."""
+"""Ragged batches of p = 2 transforms (one persistent launch per pass level),
+against the oracle, alone vs in the mix, and under HIP-graph capture."""
 import numpy as np
 import pytest
 import torch

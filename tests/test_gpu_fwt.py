@@ -163,3 +163,22 @@ def test_in_place_and_errors():
     assert torch.equal(g, ref)
     with pytest.raises(fdwt.FdwtError):
         net.forward(f, out=torch.empty(2 ** m, dtype=torch.int32, device="cuda"))
+
+
+@pytest.mark.parametrize("p,m", [(2, 5), (2, 13), (2, 18), (3, 6), (3, 11), (5, 7)])
+def test_double_precision_transforms(p, m):
+    """F64 (p = 2) and F64 -> CF64 (p odd) forward, CF64/F64 inverse: the
+    double-precision reference path, against the phase form in float64."""
+    announce("f64 forward/inverse", p, m)
+    N = p ** m
+    f = inputs.uniform_float(N, 300 + m, dtype=np.float64)
+    net = fdwt.Net(p, m, 1, inputs.identity_generators(p, m, 1))
+    ft = net.forward(to_dev(f, torch.float64)).cpu().numpy()
+    hs = sample_indices(N, 200, m)
+    ref = walsh.dwt_phase(p, m, f, hs)
+    if p == 2:
+        ref = ref.real
+    assert nrel(ft[hs], ref) <= 1e-13
+    back = net.inverse(torch.from_numpy(ft).cuda(), real=True).cpu().numpy()
+    assert back.dtype == np.float64
+    assert nrel(back, f) <= 1e-13
