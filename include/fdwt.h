@@ -224,6 +224,88 @@ int fdwt_batch_run(fdwt_batch* batch, void* stream);
 int fdwt_batch_check(fdwt_batch* batch, void* stream);
 void fdwt_batch_free(fdwt_batch* batch);
 
+/* ------------------------------------------------------------- serving */
+
+/* A request loop for interpolation and effective-dimension jobs of any
+ * (p, m, s) on one device.  Each request carries its net (p, m, s, C and a
+ * caller-chosen net_key), a test-function family with its parameters
+ * (sampled on the device as fdwt_sample), the kernel (alpha, gamma) of
+ * Section 4 and, for interpolation, nq query points (digits as
+ * fdwt_spline_eval).  An interpolation job computes the coefficients of
+ * Eq. (eq_dwalshcoeff), the spline coefficients of Eq. (splinecoef) and
+ * Sf at the queries (Section 3.3); an effective-dimension job computes the
+ * variances and dimensions of fdwt_eff_dim (Section 5).
+ *
+ * The server holds one device allocation of hbm_budget bytes.  Nets, kernel
+ * spectra (per net_key and kernel) and the packed point coordinates used by
+ * the evaluation (per net_key) stay resident in it between requests and are
+ * evicted least recently used when an arriving job needs room and no running
+ * job holds them.  A job is admitted when one of `lanes` HIP streams is idle
+ * and its buffers fit; admitted jobs run concurrently.  Admission follows
+ * arrival order, except that a job that does not fit may be overtaken by
+ * later ones at most max_bypass times.  A job's results are bit-identical
+ * whether it runs alone or among others.  effdim_chunk_bytes bounds the
+ * kernel-data columns an effective-dimension job holds at once (0: 1 GiB).
+ *
+ * fdwt_server_submit copies the request (the caller may free its arrays on
+ * return) and returns at once with an id; it fails with FDWT_EBUDGET when
+ * the request alone exceeds the budget and with FDWT_EINVAL when net_key
+ * already names different (p, m, s, C).  fdwt_server_wait blocks until job
+ * `id` has finished, fills `info` and the results (sf_host: nq floats for an
+ * interpolation; eff: arrays of s + 1 doubles for an effective-dimension
+ * job; either may be NULL) and forgets the job; it returns the job's status.
+ * Times are seconds on the server's clock (from creation).  Any thread may
+ * submit and wait.  fdwt_server_free finishes every submitted job, then
+ * releases everything. */
+#define FDWT_JOB_INTERP 1
+#define FDWT_JOB_EFFDIM 2
+
+typedef struct {
+  size_t hbm_budget;
+  int lanes;
+  int max_bypass;
+  size_t effdim_chunk_bytes;
+} fdwt_server_config;
+
+typedef struct {
+  int kind;                  /* FDWT_JOB_INTERP or FDWT_JOB_EFFDIM          */
+  int p, m, s;
+  uint64_t net_key;          /* equal keys must mean equal (p, m, s, C)     */
+  const uint8_t* C_host;     /* [s][m][m], as fdwt_net_generate             */
+  int family;                /* FDWT_FAMILY_*                               */
+  const double* a_host;      /* [s] family parameters                       */
+  double alpha;              /* kernel smoothness, > 1                      */
+  const double* gamma_host;  /* [s] kernel weights, > 0                     */
+  int64_t nq;                /* interpolation: 1..2^24 queries              */
+  const uint32_t* q_host;    /* interpolation: [s][nq] query digits         */
+} fdwt_request;
+
+typedef struct {
+  int status;
+  double t_submit, t_admit, t_done;
+  size_t bytes;              /* job buffers held while running (no caches)  */
+  int spectrum_hit;          /* the kernel spectrum was resident            */
+  int packed_hit;            /* the packed coordinates were resident        */
+} fdwt_job_info;
+
+typedef struct {
+  int64_t submitted, completed, failed, rejected, pending, in_flight;
+  size_t arena_bytes, arena_used, arena_peak;
+  int64_t spectrum_hits, spectrum_misses, packed_hits, packed_misses, evictions, nets_built;
+} fdwt_server_counters;
+
+typedef struct fdwt_server fdwt_server;
+
+/* Device bytes a request needs: its own buffers (job_bytes) and the cache
+ * entries it creates on a miss (cache_bytes).  Host-only. */
+int fdwt_server_request_bytes(const fdwt_request* req, size_t effdim_chunk_bytes, size_t* job_bytes,
+                              size_t* cache_bytes);
+int fdwt_server_create(const fdwt_server_config* cfg, fdwt_server** out);
+int fdwt_server_submit(fdwt_server* server, const fdwt_request* req, int64_t* id);
+int fdwt_server_wait(fdwt_server* server, int64_t id, fdwt_job_info* info, float* sf_host, fdwt_effdim* eff);
+int fdwt_server_stats(fdwt_server* server, fdwt_server_counters* stats);
+void fdwt_server_free(fdwt_server* server);
+
 /* ------------------------------------------------------------ timing */
 
 /* Per-launch timing of the library's kernels, for benchmarks and tracing.

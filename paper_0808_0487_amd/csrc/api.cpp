@@ -101,48 +101,74 @@ double rprime(int p, double alpha, int i) {
   return A * (1.0 - std::pow((double)p, i * (1.0 - 2.0 * alpha)) * (p2a - 1.0) / (p - 1.0));
 }
 
-int ensure_ws(Net& net, size_t bytes, hipStream_t st) {
-  if (net.ws_bytes >= bytes) return FDWT_OK;
-  if (net.ws) {
+int ensure_ws(Scratch& sc, size_t bytes, hipStream_t st) {
+  if (sc.ws_bytes >= bytes) return FDWT_OK;
+  if (sc.fixed)
+    return fail(FDWT_EBUDGET, "workspace of " + std::to_string(bytes) + " bytes exceeds the lent " +
+                                  std::to_string(sc.ws_bytes));
+  if (sc.ws) {
     FDWT_HIP(hipStreamSynchronize(st));
-    FDWT_HIP(hipFree(net.ws));
-    net.ws = nullptr;
-    net.ws_bytes = 0;
+    FDWT_HIP(hipFree(sc.ws));
+    sc.ws = nullptr;
+    sc.ws_bytes = 0;
   }
   void* p = nullptr;
   if (hipMalloc(&p, bytes) != hipSuccess) {
     (void)hipGetLastError();
     return fail(FDWT_ENOMEM, "workspace allocation of " + std::to_string(bytes) + " bytes failed");
   }
-  net.ws = p;
-  net.ws_bytes = bytes;
+  sc.ws = p;
+  sc.ws_bytes = bytes;
   return FDWT_OK;
 }
 
-int pin_acquire(Net& net) {
-  if (net.pin_done) FDWT_HIP(hipEventSynchronize(net.pin_done));
-  return FDWT_OK;
-}
-int pin_release(Net& net, hipStream_t st) {
-  if (!net.pin_done) FDWT_HIP(hipEventCreateWithFlags(&net.pin_done, hipEventDisableTiming));
-  FDWT_HIP(hipEventRecord(net.pin_done, st));
-  return FDWT_OK;
-}
-int ensure_pin(Net& net, size_t bytes) {
-  int rc = pin_acquire(net);
-  if (rc) return rc;
-  if (net.pin_bytes >= bytes) return FDWT_OK;
-  if (net.pin) FDWT_HIP(hipHostFree(net.pin));
-  net.pin = nullptr;
-  net.pin_bytes = 0;
-  void* p = nullptr;
-  if (hipHostMalloc(&p, bytes, hipHostMallocDefault) != hipSuccess) {
-    (void)hipGetLastError();
-    return fail(FDWT_ENOMEM, "pinned staging allocation failed");
+int pin_take(Scratch& sc, size_t bytes, void** host) {
+  if (sc.fixed) {
+    const size_t b = align_ws(bytes);
+    if (sc.pin_used + b > sc.pin_bytes) return fail(FDWT_EBUDGET, "lent staging area exhausted");
+    *host = (char*)sc.pin + sc.pin_used;
+    sc.pin_used += b;
+    return FDWT_OK;
   }
-  net.pin = p;
-  net.pin_bytes = bytes;
+  if (sc.pin_done) FDWT_HIP(hipEventSynchronize(sc.pin_done));
+  if (sc.pin_bytes < bytes) {
+    if (sc.pin) FDWT_HIP(hipHostFree(sc.pin));
+    sc.pin = nullptr;
+    sc.pin_bytes = 0;
+    void* p = nullptr;
+    if (hipHostMalloc(&p, bytes, hipHostMallocDefault) != hipSuccess) {
+      (void)hipGetLastError();
+      return fail(FDWT_ENOMEM, "pinned staging allocation failed");
+    }
+    sc.pin = p;
+    sc.pin_bytes = bytes;
+  }
+  *host = sc.pin;
   return FDWT_OK;
+}
+
+int pin_release(Scratch& sc, hipStream_t st) {
+  if (sc.fixed) return FDWT_OK;
+  if (!sc.pin_done) FDWT_HIP(hipEventCreateWithFlags(&sc.pin_done, hipEventDisableTiming));
+  FDWT_HIP(hipEventRecord(sc.pin_done, st));
+  return FDWT_OK;
+}
+
+int upload(Scratch& sc, const void* src, size_t bytes, void* dst, hipStream_t st) {
+  void* h = nullptr;
+  if (int rc = pin_take(sc, bytes, &h)) return rc;
+  std::memcpy(h, src, bytes);
+  FDWT_HIP(hipMemcpyAsync(dst, h, bytes, hipMemcpyHostToDevice, st));
+  return pin_release(sc, st);
+}
+
+void scratch_release(Scratch& sc) {
+  if (sc.fixed) return;
+  if (sc.ws || sc.pin_done) (void)hipDeviceSynchronize();
+  if (sc.ws) (void)hipFree(sc.ws);
+  if (sc.pin) (void)hipHostFree(sc.pin);
+  if (sc.pin_done) (void)hipEventDestroy(sc.pin_done);
+  sc = Scratch{};
 }
 
 // Makes the net's device current for the duration of a call.
@@ -217,9 +243,9 @@ static int transform(Net& net, bool inverse, int in_type, const void* in, int ou
     return fail(FDWT_EINVAL, "in-place transform needs equal input and output element sizes");
   void* tmp = nullptr;
   if (kind_bytes(ok) < kind_bytes(wk)) {
-    int rc = ensure_ws(net, (size_t)net.N * kind_bytes(wk), st);
+    int rc = ensure_ws(net.sc, (size_t)net.N * kind_bytes(wk), st);
     if (rc) return rc;
-    tmp = net.ws;
+    tmp = net.sc.ws;
   }
   const double scale = (!inverse && wk != K_U32) ? 1.0 / (double)net.N : 1.0;  // Eq. (eq_dwalshcoeff)
   return fwt_run_tmp(net.p, net.m, inverse, ik, in, wk, ok, out, tmp, 1, scale, st);
@@ -363,12 +389,10 @@ void fdwt_net_free(fdwt_net* h) {
   if (!h) return;
   Net& n = h->n;
   DeviceGuard g(n.device);
-  if (n.ws || n.pin_done) (void)hipDeviceSynchronize();
+  scratch_release(n.sc);
+  if (n.d_xtab || n.d_ptab) (void)hipDeviceSynchronize();
   if (n.d_xtab) (void)hipFree(n.d_xtab);
   if (n.d_ptab) (void)hipFree(n.d_ptab);
-  if (n.ws) (void)hipFree(n.ws);
-  if (n.pin) (void)hipHostFree(n.pin);
-  if (n.pin_done) (void)hipEventDestroy(n.pin_done);
   delete h;
 }
 
@@ -433,7 +457,8 @@ int fdwt_spline_coef(const fdwt_net* h, const fdwt_kernel* kern, int ft_type, co
   if (ft_type != (h->n.p == 2 ? FDWT_F32 : FDWT_CF32))
     return fail(FDWT_EINVAL, "coefficients must be F32 (p = 2) or CF32 (p odd)");
   DeviceGuard g(h->n.device);
-  return run_spline_coef(const_cast<Net&>(h->n), kern, ft_type, ft_dev, c_dev, (hipStream_t)stream);
+  Net& net = const_cast<Net&>(h->n);
+  return run_spline_coef(net, net.sc, kern, nullptr, ft_dev, c_dev, (hipStream_t)stream);
   FDWT_GUARD_END
 }
 
@@ -446,7 +471,8 @@ int fdwt_spline_eval(const fdwt_net* h, const fdwt_kernel* kern, const float* c_
   if (nq == 0) return FDWT_OK;
   if (!c_dev || !q_dev || !sf_dev) return fail(FDWT_EINVAL, "NULL data pointer");
   DeviceGuard g(h->n.device);
-  return run_spline_eval(const_cast<Net&>(h->n), kern, c_dev, nq, q_dev, sf_dev, (hipStream_t)stream);
+  Net& net = const_cast<Net&>(h->n);
+  return run_spline_eval(net, net.sc, kern, nullptr, c_dev, nq, q_dev, sf_dev, (hipStream_t)stream);
   FDWT_GUARD_END
 }
 
@@ -472,8 +498,8 @@ int fdwt_walsh_interp(const fdwt_net* h, const fdwt_kernel* kern, const float* f
   }
   if (!c) c = (float*)((char*)ft + ftb);
   int rc = transform(net, false, FDWT_F32, f_dev, net.p == 2 ? FDWT_F32 : FDWT_CF32, ft, st);
-  if (!rc) rc = run_spline_coef(net, kern, net.p == 2 ? FDWT_F32 : FDWT_CF32, ft, c, st);
-  if (!rc && nq > 0) rc = run_spline_eval(net, kern, c, nq, q_dev, sf_dev, st);
+  if (!rc) rc = run_spline_coef(net, net.sc, kern, nullptr, ft, c, st);
+  if (!rc && nq > 0) rc = run_spline_eval(net, net.sc, kern, nullptr, c, nq, q_dev, sf_dev, st);
   (void)hipFreeAsync(ft, st);
   return rc;
   FDWT_GUARD_END
@@ -488,7 +514,8 @@ int fdwt_eff_dim(const fdwt_net* h, const fdwt_kernel* kern, int ft_type, const 
   if (ft_type != (h->n.p == 2 ? FDWT_F32 : FDWT_CF32))
     return fail(FDWT_EINVAL, "coefficients must be F32 (p = 2) or CF32 (p odd)");
   DeviceGuard g(h->n.device);
-  return run_eff_dim(const_cast<Net&>(h->n), kern, ft_type, ft_dev, out, (hipStream_t)stream);
+  Net& net = const_cast<Net&>(h->n);
+  return run_eff_dim(net, net.sc, kern, ft_dev, out, (hipStream_t)stream);
   FDWT_GUARD_END
 }
 

@@ -34,6 +34,24 @@ struct df {
   float hi, lo;
 };
 
+// --------------------------------------------------------------- scratch
+// Device workspace and pinned host staging used by one chain of calls.
+// Owned mode (fixed = false): grow-only, reused call after call; a staging
+// upload waits until the previous one has left `pin`.  Lent mode (fixed =
+// true, the server's jobs): both areas are carved out by the caller at their
+// final size; a request beyond them fails with FDWT_EBUDGET, and staging is
+// handed out in consecutive slices (pin_used) that are never reused while the
+// chain runs, so nothing waits on the host.
+struct Scratch {
+  void* ws = nullptr;
+  size_t ws_bytes = 0;
+  bool fixed = false;
+  void* pin = nullptr;
+  size_t pin_bytes = 0;
+  size_t pin_used = 0;
+  hipEvent_t pin_done = nullptr;  // owned mode: last copy through `pin` finished
+};
+
 // ------------------------------------------------------------------- net
 struct Net {
   int p = 0, m = 0, s = 0;
@@ -45,13 +63,8 @@ struct Net {
   // p odd: uint64 [s][m][p]: packed digits (4-bit fields, digit y_{r+1} at
   // bits 4(m-1-r)) of v * column c of C_j mod p.
   uint64_t* d_ptab = nullptr;
-  // Grow-only workspace owned by the handle.
-  void* ws = nullptr;
-  size_t ws_bytes = 0;
-  // Pinned host staging for small per-call tables and results.
-  void* pin = nullptr;
-  size_t pin_bytes = 0;
-  hipEvent_t pin_done = nullptr;  // last copy out of/into `pin` finished
+  // Workspace and staging of the handle's own calls (grow-only).
+  Scratch sc;
 };
 
 }  // namespace fdwt
@@ -71,10 +84,15 @@ hipEvent_t timed_begin(hipStream_t st);
 void timed_end(hipEvent_t begin, hipStream_t st, int cls, double work);
 // Allows a kernel more than the default 64 KiB of dynamic LDS (once per kernel).
 int allow_lds(const void* fn, size_t bytes);
-int ensure_ws(Net& net, size_t bytes, hipStream_t st);
-int ensure_pin(Net& net, size_t bytes);
-int pin_acquire(Net& net);          // waits until `pin` is free again
-int pin_release(Net& net, hipStream_t st);
+int ensure_ws(Scratch& sc, size_t bytes, hipStream_t st);
+// Host staging of `bytes` for one copy on st: *host receives the slice; call
+// pin_release after enqueuing the copy.
+int pin_take(Scratch& sc, size_t bytes, void** host);
+int pin_release(Scratch& sc, hipStream_t st);
+// Enqueues a host-to-device copy of `bytes` from src through the staging.
+int upload(Scratch& sc, const void* src, size_t bytes, void* dst, hipStream_t st);
+void scratch_release(Scratch& sc);  // owned mode: frees both areas
+inline size_t align_ws(size_t b) { return (b + 255) & ~(size_t)255; }  // workspace slice alignment
 
 // --------------------------------------------------------- kernel launchers
 // net.hip
@@ -94,13 +112,27 @@ size_t kind_bytes(Kind k);
 int fwt_run(int p, int m, bool inverse, Kind in_kind, const void* in, Kind work_kind,
             Kind out_kind, void* out, int batch, double scale, hipStream_t st);
 
-// spline.hip / effdim.hip
-int run_spline_coef(Net& net, const fdwt_kernel* kern, int ft_type, const void* ft, float* c,
+// spline.hip.  Every step takes an explicit Scratch; *_ws_bytes return the
+// workspace a step needs (the step lays it out the same way), so a caller
+// can lend exactly that much.
+size_t kernel_tables_bytes(const Net& net);  // staged kernel tables (K' and R' per coordinate)
+size_t spectrum_bytes(const Net& net);     // kernel spectrum: N doubles (p = 2), N complex doubles
+size_t spectrum_ws_bytes(const Net& net);
+int run_spectrum(Net& net, Scratch& sc, const fdwt_kernel* kern, void* gk, hipStream_t st);
+size_t spline_coef_ws_bytes(const Net& net, bool have_spectrum);
+int run_spline_coef(Net& net, Scratch& sc, const fdwt_kernel* kern, const void* gk, const void* ft, float* c,
                     hipStream_t st);
-int run_spline_eval(Net& net, const fdwt_kernel* kern, const float* c, int64_t nq,
-                    const uint32_t* q, float* sf, hipStream_t st);
-int run_eff_dim(Net& net, const fdwt_kernel* kern, int ft_type, const void* ft, fdwt_effdim* out,
-                hipStream_t st);
+size_t packed_bytes(const Net& net);       // packed coordinates of all points (launch_net_packed)
+size_t spline_eval_ws_bytes(const Net& net, int64_t nq, bool have_packed);
+int run_spline_eval(Net& net, Scratch& sc, const fdwt_kernel* kern, const void* packed, const float* c,
+                    int64_t nq, const uint32_t* q, float* sf, hipStream_t st);
+int eff_dim_chunk(const Net& net, size_t budget);
+size_t eff_dim_res_bytes(const Net& net);
+size_t eff_dim_ws_bytes(const Net& net, bool have_spectrum, int chunk);
+int eff_dim_enqueue(Net& net, Scratch& sc, const fdwt_kernel* kern, const void* gk, const void* ft, int chunk,
+                    double* res_host, const double** res_dev, hipStream_t st);
+void eff_dim_finish(int s, const double* res, fdwt_effdim* out);
+int run_eff_dim(Net& net, Scratch& sc, const fdwt_kernel* kern, const void* ft, fdwt_effdim* out, hipStream_t st);
 
 // Host tables of the kernel closed forms in double, for coordinates j and
 // first-differing-digit index i (0 = no differing digit).

@@ -280,16 +280,6 @@ static NetArgs net_args(const Net& net) {
   return NetArgs{net.d_xtab, net.d_ptab, net.nbytes, net.s, net.m, net.N};
 }
 
-// Upload `bytes` from host `src` to device `dst` through the pinned staging
-// buffer, ordered on `st`.
-static int upload(Net& net, const void* src, size_t bytes, void* dst, hipStream_t st) {
-  int rc = ensure_pin(net, bytes);
-  if (rc) return rc;
-  std::memcpy(net.pin, src, bytes);
-  FDWT_HIP(hipMemcpyAsync(dst, net.pin, bytes, hipMemcpyHostToDevice, st));
-  return pin_release(net, st);
-}
-
 // Kernel-data tables: tk[j][t] = 1 + gamma_j K'(t+1) for t < m, 1 + gamma_j for
 // t >= m (x = 0); tr[j][t] = gamma_j^2 R'(t+1), gamma_j^2 R'(0).  Laid out as
 // tk then tr, each [s][kTab].
@@ -305,6 +295,20 @@ static std::vector<double> kernel_tables(const Net& net, const fdwt_kernel* k) {
   }
   return t;
 }
+
+size_t kernel_tables_bytes(const Net& net) { return (size_t)2 * net.s * kTab * sizeof(double); }
+
+// Consecutive slices of a workspace; with base == nullptr it only measures.
+struct Carve {
+  char* base;
+  size_t off = 0;
+  explicit Carve(void* b) : base((char*)b) {}
+  void* take(size_t bytes) {
+    void* r = base ? base + off : nullptr;
+    off += align_up(bytes);
+    return r;
+  }
+};
 
 template <int P, int SMAX>
 static int kcols_launch(const Net& net, const double* tk, const double* tr, int c0, int c1, double* out,
@@ -347,43 +351,98 @@ int fwt_reduce_f64(int p, int m, const double* in, void* tmp, int batch, const f
                    double* h0_out, int h0_col, int64_t* tiles, hipStream_t st);
 int64_t fwt_reduce_tiles(int p, int m, size_t elem_bytes);
 
-// Unnormalised float64 spectrum of the kernel data K(x_n, 0): `A` holds the
-// data (N doubles), the spectrum goes to GK (p = 2: in place in A; p odd:
-// N complex doubles).
-static int kernel_spectrum(Net& net, const double* tab, double* A, void* GK, hipStream_t st) {
-  int rc = launch_kernel_cols(net, tab, tab + (size_t)net.s * kTab, 0, 1, A, st);
-  if (rc) return rc;
-  if (net.p == 2) return fwt_run_tmp(2, net.m, false, K_F64, A, K_F64, K_F64, A, nullptr, 1, 1.0f, st);
-  return fwt_run_tmp(net.p, net.m, false, K_F64, A, K_CF64, K_CF64, GK, nullptr, 1, 1.0f, st);
+// ------------------------------------------------------ kernel spectrum
+// Unnormalised float64 spectrum of the kernel data K(x_n, 0): p = 2, N
+// doubles; p odd, N complex doubles.
+size_t spectrum_bytes(const Net& net) { return (size_t)net.N * (net.p == 2 ? 8 : 16); }
+
+struct SpecWs {
+  double* tab;  // kernel tables
+  double* A;    // kernel data (p odd; p = 2 transforms in place in the spectrum)
+};
+static void spec_layout(const Net& net, Carve& cv, SpecWs& w) {
+  w.tab = (double*)cv.take((size_t)2 * net.s * kTab * sizeof(double));
+  w.A = net.p == 2 ? nullptr : (double*)cv.take((size_t)net.N * 8);
+}
+size_t spectrum_ws_bytes(const Net& net) {
+  Carve cv(nullptr);
+  SpecWs w;
+  spec_layout(net, cv, w);
+  return cv.off;
 }
 
-int run_spline_coef(Net& net, const fdwt_kernel* kern, int ft_type, const void* ft, float* c, hipStream_t st) {
-  (void)ft_type;
+// Computes the spectrum into gk (spectrum_bytes); the tables and, for p odd,
+// the data go through the first spectrum_ws_bytes of ws.  tab_dev: tables
+// already on the device (then they are not staged again), or nullptr.
+static int spectrum_into(Net& net, Scratch& sc, const fdwt_kernel* kern, void* ws, void* gk, hipStream_t st,
+                         const double* tab_dev = nullptr) {
+  Carve cv(ws);
+  SpecWs w;
+  spec_layout(net, cv, w);
+  int rc = FDWT_OK;
+  const double* tab = tab_dev;
+  if (!tab) {
+    const std::vector<double> htab = kernel_tables(net, kern);
+    rc = upload(sc, htab.data(), htab.size() * sizeof(double), w.tab, st);
+    if (rc) return rc;
+    tab = w.tab;
+  }
+  double* A = net.p == 2 ? (double*)gk : w.A;
+  rc = launch_kernel_cols(net, tab, tab + (size_t)net.s * kTab, 0, 1, A, st);
+  if (rc) return rc;
+  if (net.p == 2) return fwt_run_tmp(2, net.m, false, K_F64, A, K_F64, K_F64, A, nullptr, 1, 1.0, st);
+  return fwt_run_tmp(net.p, net.m, false, K_F64, A, K_CF64, K_CF64, gk, nullptr, 1, 1.0, st);
+}
+
+int run_spectrum(Net& net, Scratch& sc, const fdwt_kernel* kern, void* gk, hipStream_t st) {
+  int rc = ensure_ws(sc, spectrum_ws_bytes(net), st);
+  if (rc) return rc;
+  return spectrum_into(net, sc, kern, sc.ws, gk, st);
+}
+
+// ------------------------------------------------- spline coefficients
+struct CoefWs {
+  void* gk;  // spectrum (when not given)
+  void* sw;  // its workspace
+  float2* ct;  // p odd: c~ (complex)
+};
+static void coef_layout(const Net& net, bool have_gk, Carve& cv, CoefWs& w) {
+  w.gk = have_gk ? nullptr : cv.take(spectrum_bytes(net));
+  w.sw = have_gk ? nullptr : cv.take(spectrum_ws_bytes(net));
+  w.ct = net.p == 2 ? nullptr : (float2*)cv.take((size_t)net.N * sizeof(float2));
+}
+size_t spline_coef_ws_bytes(const Net& net, bool have_spectrum) {
+  Carve cv(nullptr);
+  CoefWs w;
+  coef_layout(net, have_spectrum, cv, w);
+  return cv.off;
+}
+
+int run_spline_coef(Net& net, Scratch& sc, const fdwt_kernel* kern, const void* gk_given, const void* ft, float* c,
+                    hipStream_t st) {
   const int64_t N = net.N;
-  const size_t tab_b = align_up((size_t)2 * net.s * kTab * sizeof(double));
-  const size_t a_b = align_up((size_t)N * sizeof(double));
-  const size_t g_b = net.p == 2 ? 0 : align_up((size_t)N * sizeof(double2));
-  const size_t ct_b = net.p == 2 ? 0 : align_up((size_t)N * sizeof(float2));
-  int rc = ensure_ws(net, tab_b + a_b + g_b + ct_b, st);
+  int rc = ensure_ws(sc, spline_coef_ws_bytes(net, gk_given != nullptr), st);
   if (rc) return rc;
-  char* w = (char*)net.ws;
-  double* tab = (double*)w;
-  double* A = (double*)(w + tab_b);
-  void* GK = net.p == 2 ? (void*)A : (void*)(w + tab_b + a_b);
-  void* ct = net.p == 2 ? (void*)c : (void*)(w + tab_b + a_b + g_b);
-  const std::vector<double> htab = kernel_tables(net, kern);
-  rc = upload(net, htab.data(), htab.size() * sizeof(double), tab, st);
-  if (!rc) rc = kernel_spectrum(net, tab, A, GK, st);
-  if (rc) return rc;
+  Carve cv(sc.ws);
+  CoefWs w;
+  coef_layout(net, gk_given != nullptr, cv, w);
+  const void* GK = gk_given;
+  if (!GK) {
+    rc = spectrum_into(net, sc, kern, w.sw, w.gk, st);
+    if (rc) return rc;
+    GK = w.gk;
+  }
+  void* ct = net.p == 2 ? (void*)c : (void*)w.ct;
   if (net.p == 2) hipLaunchKernelGGL(k_spec_div<2>, dim3(grid1(N)), dim3(256), 0, st, ft, GK, N, ct);
   else if (net.p == 3) hipLaunchKernelGGL(k_spec_div<3>, dim3(grid1(N)), dim3(256), 0, st, ft, GK, N, ct);
   else hipLaunchKernelGGL(k_spec_div<5>, dim3(grid1(N)), dim3(256), 0, st, ft, GK, N, ct);
   FDWT_HIP(hipGetLastError());
   // Algorithm 2 (no normalisation); p odd returns the real part.
-  if (net.p == 2) return fwt_run_tmp(2, net.m, true, K_F32, ct, K_F32, K_F32, c, nullptr, 1, 1.0f, st);
-  return fwt_run_tmp(net.p, net.m, true, K_CF32, ct, K_CF32, K_F32, c, ct, 1, 1.0f, st);
+  if (net.p == 2) return fwt_run_tmp(2, net.m, true, K_F32, ct, K_F32, K_F32, c, nullptr, 1, 1.0, st);
+  return fwt_run_tmp(net.p, net.m, true, K_CF32, ct, K_CF32, K_F32, c, ct, 1, 1.0, st);
 }
 
+// ----------------------------------------------------------- evaluation
 template <int P>
 static int launch_eval(Net& net, const void* Xp, const float* c, int64_t nq, const uint32_t* q,
                        const uint64_t* qh, const uint32_t* qt, const float* te, int ntab, df* partial,
@@ -406,115 +465,185 @@ static int launch_eval(Net& net, const void* Xp, const float* c, int64_t nq, con
   return FDWT_OK;
 }
 
-int run_spline_eval(Net& net, const fdwt_kernel* kern, const float* c, int64_t nq, const uint32_t* q,
-                    float* sf, hipStream_t st) {
-  const int p = net.p, s = net.s, m = net.m;
-  const int D = query_depth(p);
-  const int ntab = D + 1;
-  const int64_t N = net.N;
-  const size_t xb = (p == 2) ? 4 : 8;
-  // Grid: query blocks x point chunks, >= ~2048 workgroups in total.
+size_t packed_bytes(const Net& net) { return (size_t)net.s * net.N * (net.p == 2 ? 4 : 8); }
+
+// Grid of the evaluation: query blocks x point chunks, >= ~2048 workgroups in
+// total; it depends on (N, nq) only, so a result never depends on where or
+// alongside what it runs.
+static void eval_grid(int64_t N, int64_t nq, int* gy_out, int64_t* ppc_out) {
   const int64_t qb = (nq + 255) / 256;
   int gy = (int)std::max<int64_t>(1, std::min<int64_t>((2048 + qb - 1) / qb, (N + kNS - 1) / kNS));
   int64_t ppc = (N + gy - 1) / gy;
   ppc = (ppc + kNS - 1) / kNS * kNS;
   gy = (int)((N + ppc - 1) / ppc);
-  const size_t te_b = align_up((size_t)s * ntab * 4);
-  const size_t x_b = align_up((size_t)s * N * xb);
-  const size_t qh_b = p == 2 ? 0 : align_up((size_t)s * nq * 8);
-  const size_t qt_b = p == 2 ? 0 : align_up((size_t)s * nq * 4);
-  const size_t pa_b = align_up((size_t)gy * nq * sizeof(df));
-  int rc = ensure_ws(net, te_b + x_b + qh_b + qt_b + pa_b, st);
+  *gy_out = gy;
+  *ppc_out = ppc;
+}
+
+struct EvalWs {
+  float* te;
+  void* Xp;
+  uint64_t* qh;
+  uint32_t* qt;
+  df* partial;
+};
+static void eval_layout(const Net& net, int64_t nq, bool have_packed, Carve& cv, EvalWs& w) {
+  const int p = net.p, s = net.s;
+  int gy;
+  int64_t ppc;
+  eval_grid(net.N, nq, &gy, &ppc);
+  w.te = (float*)cv.take((size_t)s * (query_depth(p) + 1) * 4);
+  w.Xp = have_packed ? nullptr : cv.take(packed_bytes(net));
+  w.qh = p == 2 ? nullptr : (uint64_t*)cv.take((size_t)s * nq * 8);
+  w.qt = p == 2 ? nullptr : (uint32_t*)cv.take((size_t)s * nq * 4);
+  w.partial = (df*)cv.take((size_t)gy * nq * sizeof(df));
+}
+size_t spline_eval_ws_bytes(const Net& net, int64_t nq, bool have_packed) {
+  Carve cv(nullptr);
+  EvalWs w;
+  eval_layout(net, nq, have_packed, cv, w);
+  return cv.off;
+}
+
+int run_spline_eval(Net& net, Scratch& sc, const fdwt_kernel* kern, const void* packed, const float* c, int64_t nq,
+                    const uint32_t* q, float* sf, hipStream_t st) {
+  const int p = net.p, s = net.s, m = net.m;
+  const int D = query_depth(p);
+  const int ntab = D + 1;
+  const int64_t N = net.N;
+  const size_t xb = (p == 2) ? 4 : 8;
+  int gy;
+  int64_t ppc;
+  eval_grid(N, nq, &gy, &ppc);
+  int rc = ensure_ws(sc, spline_eval_ws_bytes(net, nq, packed != nullptr), st);
   if (rc) return rc;
-  char* w = (char*)net.ws;
-  float* te = (float*)w;
-  void* Xp = w + te_b;
-  uint64_t* qh = (uint64_t*)(w + te_b + x_b);
-  uint32_t* qt = (uint32_t*)(w + te_b + x_b + qh_b);
-  df* partial = (df*)(w + te_b + x_b + qh_b + qt_b);
+  Carve cv(sc.ws);
+  EvalWs w;
+  eval_layout(net, nq, packed != nullptr, cv, w);
   // te[j][t]: 1 + gamma_j K'(t+1) for t < D, 1 + gamma_j for t = D (equal digits).
   std::vector<float> hte((size_t)s * ntab);
   for (int j = 0; j < s; ++j)
     for (int t = 0; t < ntab; ++t)
       hte[(size_t)j * ntab + t] = (float)(1.0 + kern->gamma[j] * kprime(p, kern->alpha, t < D ? t + 1 : 0));
-  rc = upload(net, hte.data(), hte.size() * 4, te, st);
+  rc = upload(sc, hte.data(), hte.size() * 4, w.te, st);
   if (rc) return rc;
-  rc = launch_net_packed(net, Xp, st);
-  if (rc) return rc;
-  if (p == 3) hipLaunchKernelGGL(k_query_prep<3>, dim3(grid1((int64_t)s * nq)), dim3(256), 0, st, q, nq, s, m, D, qh, qt);
-  if (p == 5) hipLaunchKernelGGL(k_query_prep<5>, dim3(grid1((int64_t)s * nq)), dim3(256), 0, st, q, nq, s, m, D, qh, qt);
+  const void* Xp = packed;
+  if (!Xp) {
+    rc = launch_net_packed(net, w.Xp, st);
+    if (rc) return rc;
+    Xp = w.Xp;
+  }
+  if (p == 3) hipLaunchKernelGGL(k_query_prep<3>, dim3(grid1((int64_t)s * nq)), dim3(256), 0, st, q, nq, s, m, D, w.qh, w.qt);
+  if (p == 5) hipLaunchKernelGGL(k_query_prep<5>, dim3(grid1((int64_t)s * nq)), dim3(256), 0, st, q, nq, s, m, D, w.qh, w.qt);
   FDWT_HIP(hipGetLastError());
-  const size_t lds = te_b + (size_t)s * kNS * xb + kNS * 4;
+  const size_t lds = align_up((size_t)s * ntab * 4) + (size_t)s * kNS * xb + kNS * 4;
   hipEvent_t tb = timed_begin(st);
-  if (p == 2) rc = launch_eval<2>(net, Xp, c, nq, q, nullptr, nullptr, te, ntab, partial, gy, ppc, lds, st);
-  else if (p == 3) rc = launch_eval<3>(net, Xp, c, nq, q, qh, qt, te, ntab, partial, gy, ppc, lds, st);
-  else rc = launch_eval<5>(net, Xp, c, nq, q, qh, qt, te, ntab, partial, gy, ppc, lds, st);
+  if (p == 2) rc = launch_eval<2>(net, Xp, c, nq, q, nullptr, nullptr, w.te, ntab, w.partial, gy, ppc, lds, st);
+  else if (p == 3) rc = launch_eval<3>(net, Xp, c, nq, q, w.qh, w.qt, w.te, ntab, w.partial, gy, ppc, lds, st);
+  else rc = launch_eval<5>(net, Xp, c, nq, q, w.qh, w.qt, w.te, ntab, w.partial, gy, ppc, lds, st);
   if (rc) return rc;
   timed_end(tb, st, FDWT_TC_EVAL, (double)nq * (double)N * s);
-  hipLaunchKernelGGL(k_eval_finish, dim3(grid1(nq)), dim3(256), 0, st, partial, gy, nq, sf);
+  hipLaunchKernelGGL(k_eval_finish, dim3(grid1(nq)), dim3(256), 0, st, w.partial, gy, nq, sf);
   FDWT_HIP(hipGetLastError());
   return FDWT_OK;
 }
 
-int run_eff_dim(Net& net, const fdwt_kernel* kern, int ft_type, const void* ft, fdwt_effdim* out, hipStream_t st) {
-  (void)ft_type;
+// -------------------------------------------------- effective dimension
+// Columns of kernel data per chunk so that data (8 B) + intermediate (8 or
+// 16 B) per column stay within `budget` bytes.  The variances do not depend
+// on the chunking: every column is transformed and reduced on its own.
+int eff_dim_chunk(const Net& net, size_t budget) {
+  const size_t wb = (net.p == 2) ? 8 : 16;
+  const size_t per_col = (size_t)net.N * (8 + wb);
+  return (int)std::max<size_t>(1, std::min<size_t>((size_t)2 * net.s, budget / per_col));
+}
+
+size_t eff_dim_res_bytes(const Net& net) { return (size_t)(2 * net.s + 2) * sizeof(double); }
+
+struct EffWs {
+  void* gk;
+  void* sw;
+  double* tab;
+  float2* wts;
+  double* A;
+  void* B;
+  double* partial;
+  double* qmc_partial;
+  double* res;
+};
+static void eff_layout(const Net& net, bool have_gk, int ch, Carve& cv, EffWs& w) {
+  const int ncols = 2 * net.s;
+  const size_t wb = (net.p == 2) ? sizeof(double) : sizeof(double2);
+  const int64_t tiles = fwt_reduce_tiles(net.p, net.m, wb);
+  w.gk = have_gk ? nullptr : cv.take(spectrum_bytes(net));
+  w.sw = have_gk ? nullptr : cv.take(spectrum_ws_bytes(net));
+  w.tab = (double*)cv.take((size_t)2 * net.s * kTab * sizeof(double));
+  w.wts = (float2*)cv.take((size_t)net.N * sizeof(float2));
+  w.A = (double*)cv.take((size_t)ch * net.N * 8);
+  w.B = cv.take((size_t)ch * net.N * wb);
+  w.partial = (double*)cv.take((size_t)ncols * tiles * sizeof(double) + kRedBlocks * sizeof(double));
+  w.qmc_partial = w.partial ? w.partial + (size_t)ncols * tiles : nullptr;
+  w.res = (double*)cv.take(eff_dim_res_bytes(net));
+}
+size_t eff_dim_ws_bytes(const Net& net, bool have_spectrum, int chunk) {
+  Carve cv(nullptr);
+  EffWs w;
+  eff_layout(net, have_spectrum, chunk, cv, w);
+  return cv.off;
+}
+
+// Enqueues the whole variance computation on st; the 2s + 2 result doubles
+// (sigma^2_trc(d) for d = 1..s, the superposition increments for j = 1..s,
+// sigma^2_QMC and the h = 0 share) land in res_host (pinned) when st reaches
+// this point (when res_host is given; *res_dev receives their device copy).
+// gk_given: a cached spectrum, or nullptr to compute it here.
+int eff_dim_enqueue(Net& net, Scratch& sc, const fdwt_kernel* kern, const void* gk_given, const void* ft, int ch,
+                    double* res_host, const double** res_dev, hipStream_t st) {
   const int p = net.p, s = net.s;
   const int64_t N = net.N;
-  const size_t wb = (p == 2) ? sizeof(double) : sizeof(double2);  // working element of the spectra
+  const size_t wb = (p == 2) ? sizeof(double) : sizeof(double2);
   const int ncols = 2 * s;  // U_1..U_s, Q_1..Q_s (generator columns 1..2s)
-  // Columns per chunk within a workspace budget: data (8 B) + intermediate (wb).
-  const size_t budget = (size_t)12 << 30;
-  const size_t per_col = (size_t)N * (8 + wb);
-  const int ch = (int)std::max<size_t>(1, std::min<size_t>((size_t)ncols, budget / per_col));
   const int64_t tiles = fwt_reduce_tiles(p, net.m, wb);
-  const size_t tab_b = align_up((size_t)2 * s * kTab * sizeof(double));
-  const size_t gk_b = align_up((size_t)N * 8) + (p == 2 ? 0 : align_up((size_t)N * wb));
-  const size_t w_b = align_up((size_t)N * sizeof(float2));
-  const size_t a_b = align_up((size_t)ch * N * 8);
-  const size_t b_b = align_up((size_t)ch * N * wb);
-  const size_t part_b = align_up((size_t)ncols * tiles * sizeof(double) + kRedBlocks * sizeof(double));
-  const size_t res_b = align_up((size_t)(ncols + 2) * sizeof(double));
-  int rc = ensure_ws(net, tab_b + gk_b + w_b + a_b + b_b + part_b + res_b, st);
+  int rc = ensure_ws(sc, eff_dim_ws_bytes(net, gk_given != nullptr, ch), st);
   if (rc) return rc;
-  char* w = (char*)net.ws;
-  double* tab = (double*)w;
-  double* gk_in = (double*)(w + tab_b);
-  void* GK = p == 2 ? (void*)gk_in : (void*)(w + tab_b + align_up((size_t)N * 8));
-  float2* wts = (float2*)(w + tab_b + gk_b);
-  double* A = (double*)(w + tab_b + gk_b + w_b);
-  void* B = (void*)(w + tab_b + gk_b + w_b + a_b);
-  double* partial = (double*)(w + tab_b + gk_b + w_b + a_b + b_b);
-  double* qmc_partial = partial + (size_t)ncols * tiles;
-  double* res = (double*)(w + tab_b + gk_b + w_b + a_b + b_b + part_b);
-  double* h0 = res + ncols + 1;  // [0] = h = 0 share of the total, then f~(0), K~u(0)
-
+  Carve cv(sc.ws);
+  EffWs w;
+  eff_layout(net, gk_given != nullptr, ch, cv, w);
   const std::vector<double> htab = kernel_tables(net, kern);
-  rc = upload(net, htab.data(), htab.size() * sizeof(double), tab, st);
-  if (!rc) rc = kernel_spectrum(net, tab, gk_in, GK, st);
+  rc = upload(sc, htab.data(), htab.size() * sizeof(double), w.tab, st);
   if (rc) return rc;
+  const void* GK = gk_given;
+  if (!GK) {
+    rc = spectrum_into(net, sc, kern, w.sw, w.gk, st, w.tab);
+    if (rc) return rc;
+    GK = w.gk;
+  }
+  double* h0 = w.res + ncols + 1;  // h = 0 share of the total
   const double pm = (double)N;
-  if (p == 2) hipLaunchKernelGGL(k_effdim_weights<2>, dim3(kRedBlocks), dim3(256), 0, st, ft, GK, N, pm, wts, qmc_partial);
-  else if (p == 3) hipLaunchKernelGGL(k_effdim_weights<3>, dim3(kRedBlocks), dim3(256), 0, st, ft, GK, N, pm, wts, qmc_partial);
-  else hipLaunchKernelGGL(k_effdim_weights<5>, dim3(kRedBlocks), dim3(256), 0, st, ft, GK, N, pm, wts, qmc_partial);
+  if (p == 2) hipLaunchKernelGGL(k_effdim_weights<2>, dim3(kRedBlocks), dim3(256), 0, st, ft, GK, N, pm, w.wts, w.qmc_partial);
+  else if (p == 3) hipLaunchKernelGGL(k_effdim_weights<3>, dim3(kRedBlocks), dim3(256), 0, st, ft, GK, N, pm, w.wts, w.qmc_partial);
+  else hipLaunchKernelGGL(k_effdim_weights<5>, dim3(kRedBlocks), dim3(256), 0, st, ft, GK, N, pm, w.wts, w.qmc_partial);
   FDWT_HIP(hipGetLastError());
   for (int c0 = 0; c0 < ncols; c0 += ch) {
     const int c1 = std::min(ncols, c0 + ch);
-    rc = launch_kernel_cols(net, tab, tab + (size_t)s * kTab, c0 + 1, c1 + 1, A, st);
+    rc = launch_kernel_cols(net, w.tab, w.tab + (size_t)s * kTab, c0 + 1, c1 + 1, w.A, st);
     if (rc) return rc;
     const int h0_col = (s - 1 >= c0 && s - 1 < c1) ? s - 1 - c0 : -1;  // U_s
     int64_t t = 0;
-    rc = fwt_reduce_f64(p, net.m, A, B, c1 - c0, wts, partial + (size_t)c0 * tiles, h0, h0_col, &t, st);
+    rc = fwt_reduce_f64(p, net.m, w.A, w.B, c1 - c0, w.wts, w.partial + (size_t)c0 * tiles, h0, h0_col, &t, st);
     if (rc) return rc;
   }
-  hipLaunchKernelGGL(k_sum_rows, dim3(ncols), dim3(256), 0, st, partial, (int)tiles, res);
-  hipLaunchKernelGGL(k_sum_rows, dim3(1), dim3(256), 0, st, qmc_partial, kRedBlocks, res + ncols);
+  hipLaunchKernelGGL(k_sum_rows, dim3(ncols), dim3(256), 0, st, w.partial, (int)tiles, w.res);
+  hipLaunchKernelGGL(k_sum_rows, dim3(1), dim3(256), 0, st, w.qmc_partial, kRedBlocks, w.res + ncols);
   FDWT_HIP(hipGetLastError());
-  const size_t nres = (size_t)(ncols + 2) * sizeof(double);
-  rc = ensure_pin(net, nres);
-  if (rc) return rc;
-  FDWT_HIP(hipMemcpyAsync(net.pin, res, nres, hipMemcpyDeviceToHost, st));
-  FDWT_HIP(hipStreamSynchronize(st));
-  const double* r = (const double*)net.pin;
+  if (res_dev) *res_dev = w.res;
+  if (res_host) FDWT_HIP(hipMemcpyAsync(res_host, w.res, eff_dim_res_bytes(net), hipMemcpyDeviceToHost, st));
+  return FDWT_OK;
+}
+
+// Variances and dimensions from the 2s + 2 result doubles (Section 5's
+// definitions: the smallest d whose variance reaches 0.99 sigma^2).
+void eff_dim_finish(int s, const double* r, fdwt_effdim* out) {
   out->var_trc[0] = 0.0;
   out->var_sup[0] = 0.0;
   for (int d = 1; d <= s; ++d) {
@@ -522,8 +651,8 @@ int run_eff_dim(Net& net, const fdwt_kernel* kern, int ft_type, const void* ft, 
     out->var_sup[d] = out->var_sup[d - 1] + r[s + d - 1];
   }
   out->var_total = out->var_trc[s];
-  out->var_qmc = r[ncols];
-  out->var_total_h0 = r[ncols + 1];
+  out->var_qmc = r[2 * s];
+  out->var_total_h0 = r[2 * s + 1];
   const double target = 0.99 * out->var_total;
   out->d_trc = s;
   out->d_sup = s;
@@ -537,6 +666,17 @@ int run_eff_dim(Net& net, const fdwt_kernel* kern, int ft_type, const void* ft, 
       out->d_sup = d;
       break;
     }
+}
+
+int run_eff_dim(Net& net, Scratch& sc, const fdwt_kernel* kern, const void* ft, fdwt_effdim* out, hipStream_t st) {
+  const int ch = eff_dim_chunk(net, (size_t)12 << 30);
+  const double* res_dev = nullptr;
+  int rc = eff_dim_enqueue(net, sc, kern, nullptr, ft, ch, nullptr, &res_dev, st);
+  if (rc) return rc;
+  std::vector<double> res(2 * net.s + 2);
+  FDWT_HIP(hipStreamSynchronize(st));
+  FDWT_HIP(hipMemcpy(res.data(), res_dev, eff_dim_res_bytes(net), hipMemcpyDeviceToHost));
+  eff_dim_finish(net.s, res.data(), out);
   return FDWT_OK;
 }
 

@@ -31,6 +31,32 @@ class EffDimC(ctypes.Structure):
                 ("var_qmc", ctypes.c_double), ("d_trc", ctypes.c_int), ("d_sup", ctypes.c_int)]
 
 
+class ServerConfigC(ctypes.Structure):
+    _fields_ = [("hbm_budget", ctypes.c_size_t), ("lanes", ctypes.c_int), ("max_bypass", ctypes.c_int),
+                ("effdim_chunk_bytes", ctypes.c_size_t)]
+
+
+class RequestC(ctypes.Structure):
+    _fields_ = [("kind", ctypes.c_int), ("p", ctypes.c_int), ("m", ctypes.c_int), ("s", ctypes.c_int),
+                ("net_key", ctypes.c_uint64), ("C_host", ctypes.c_void_p), ("family", ctypes.c_int),
+                ("a_host", ctypes.c_void_p), ("alpha", ctypes.c_double), ("gamma_host", ctypes.c_void_p),
+                ("nq", ctypes.c_int64), ("q_host", ctypes.c_void_p)]
+
+
+class JobInfoC(ctypes.Structure):
+    _fields_ = [("status", ctypes.c_int), ("t_submit", ctypes.c_double), ("t_admit", ctypes.c_double),
+                ("t_done", ctypes.c_double), ("bytes", ctypes.c_size_t), ("spectrum_hit", ctypes.c_int),
+                ("packed_hit", ctypes.c_int)]
+
+
+class ServerCountersC(ctypes.Structure):
+    _fields_ = [(n, ctypes.c_int64) for n in ["submitted", "completed", "failed", "rejected", "pending",
+                                               "in_flight"]] + \
+               [(n, ctypes.c_size_t) for n in ["arena_bytes", "arena_used", "arena_peak"]] + \
+               [(n, ctypes.c_int64) for n in ["spectrum_hits", "spectrum_misses", "packed_hits", "packed_misses",
+                                               "evictions", "nets_built"]]
+
+
 SIGNATURES = {
     "fdwt_net_generate": (_i, [_i, _i, _i, _vp, ctypes.POINTER(_vp)]),
     "fdwt_net_info": (_i, [_vp, ctypes.POINTER(_i), ctypes.POINTER(_i), ctypes.POINTER(_i), ctypes.POINTER(_i64)]),
@@ -49,6 +75,13 @@ SIGNATURES = {
     "fdwt_batch_run": (_i, [_vp, _vp]),
     "fdwt_batch_check": (_i, [_vp, _vp]),
     "fdwt_batch_free": (None, [_vp]),
+    "fdwt_server_request_bytes": (_i, [ctypes.POINTER(RequestC), ctypes.c_size_t,
+                                       ctypes.POINTER(ctypes.c_size_t), ctypes.POINTER(ctypes.c_size_t)]),
+    "fdwt_server_create": (_i, [ctypes.POINTER(ServerConfigC), ctypes.POINTER(_vp)]),
+    "fdwt_server_submit": (_i, [_vp, ctypes.POINTER(RequestC), ctypes.POINTER(_i64)]),
+    "fdwt_server_wait": (_i, [_vp, _i64, ctypes.POINTER(JobInfoC), _vp, ctypes.POINTER(EffDimC)]),
+    "fdwt_server_stats": (_i, [_vp, ctypes.POINTER(ServerCountersC)]),
+    "fdwt_server_free": (None, [_vp]),
     "fdwt_timing_enable": (_i, [_i]),
     "fdwt_timing_query": (_i, [_i, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(_i64), ctypes.POINTER(ctypes.c_double)]),
     "fdwt_last_error": (ctypes.c_char_p, []),
@@ -280,6 +313,98 @@ class Net:
         _check(lib().fdwt_eff_dim(self.h, kern.c, _type_of(ft), _ptr(ft), ctypes.byref(out), _stream(stream)))
         return {"var_trc": trc, "var_sup": sup, "var_total": out.var_total, "var_total_h0": out.var_total_h0,
                 "var_qmc": out.var_qmc, "d_trc": out.d_trc, "d_sup": out.d_sup}
+
+
+JOB = {"interp": 1, "eff_dim": 2}
+
+
+class Request:
+    """One serving request (fdwt_request): kind 'interp' or 'eff_dim', the
+    net (p, m, s, C, net_key), the test-function family and its parameters a,
+    the kernel (alpha, gamma) and, for 'interp', queries uint32 [s][nq]."""
+
+    def __init__(self, kind, p, m, s, C, net_key, family, a, alpha, gamma, queries=None):
+        self.kind, self.p, self.m, self.s = kind, p, m, s
+        self.C = np.ascontiguousarray(C, dtype=np.uint8)
+        self.a = np.ascontiguousarray(a, dtype=np.float64)
+        self.gamma = np.ascontiguousarray(gamma, dtype=np.float64)
+        self.q = None if queries is None else np.ascontiguousarray(queries, dtype=np.uint32)
+        self.net_key, self.family, self.alpha = int(net_key), family, float(alpha)
+        if self.C.shape != (s, m, m) or self.a.shape != (s,) or self.gamma.shape != (s,):
+            raise ValueError("C (s, m, m), a (s,) and gamma (s,) expected")
+        if kind == "interp" and (self.q is None or self.q.ndim != 2 or self.q.shape[0] != s):
+            raise ValueError("interp requests need queries of shape (s, nq)")
+
+    @property
+    def nq(self):
+        return 0 if self.q is None else self.q.shape[1]
+
+    def c(self):
+        return RequestC(JOB[self.kind], self.p, self.m, self.s, self.net_key, self.C.ctypes.data,
+                        FAMILY[self.family], self.a.ctypes.data, self.alpha, self.gamma.ctypes.data,
+                        self.nq, None if self.q is None else self.q.ctypes.data)
+
+
+def request_bytes(req, effdim_chunk_bytes=0):
+    """(job_bytes, cache_bytes) of a request (host-only)."""
+    jb, cb = ctypes.c_size_t(), ctypes.c_size_t()
+    rc = req.c()
+    _check(lib().fdwt_server_request_bytes(ctypes.byref(rc), effdim_chunk_bytes, ctypes.byref(jb), ctypes.byref(cb)))
+    return jb.value, cb.value
+
+
+class Server:
+    """The serving loop (fdwt_server_*): submit() returns a job id at once;
+    wait(id) blocks and returns (info dict, result) with result = Sf at the
+    queries (float32 numpy array) or the eff_dim dict."""
+
+    def __init__(self, hbm_budget, lanes=8, max_bypass=8, effdim_chunk_bytes=0):
+        cfg = ServerConfigC(int(hbm_budget), lanes, max_bypass, int(effdim_chunk_bytes))
+        h = ctypes.c_void_p()
+        _check(lib().fdwt_server_create(ctypes.byref(cfg), ctypes.byref(h)))
+        self.h = h
+        self._reqs = {}
+
+    def submit(self, req):
+        jid = ctypes.c_int64()
+        rc = req.c()
+        _check(lib().fdwt_server_submit(self.h, ctypes.byref(rc), ctypes.byref(jid)))
+        self._reqs[jid.value] = (req.kind, req.s, req.nq)
+        return jid.value
+
+    def wait(self, jid):
+        kind, s, nq = self._reqs.pop(jid)
+        info = JobInfoC()
+        if kind == "interp":
+            sf = np.empty(nq, dtype=np.float32)
+            rc = lib().fdwt_server_wait(self.h, jid, ctypes.byref(info), sf.ctypes.data, None)
+            res = sf
+        else:
+            trc, sup = np.zeros(s + 1), np.zeros(s + 1)
+            out = EffDimC(trc.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                          sup.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), 0.0, 0.0, 0.0, 0, 0)
+            rc = lib().fdwt_server_wait(self.h, jid, ctypes.byref(info), None, ctypes.byref(out))
+            res = {"var_trc": trc, "var_sup": sup, "var_total": out.var_total, "var_total_h0": out.var_total_h0,
+                   "var_qmc": out.var_qmc, "d_trc": out.d_trc, "d_sup": out.d_sup}
+        _check(rc)
+        return ({"t_submit": info.t_submit, "t_admit": info.t_admit, "t_done": info.t_done, "bytes": info.bytes,
+                 "spectrum_hit": bool(info.spectrum_hit), "packed_hit": bool(info.packed_hit)}, res)
+
+    def stats(self):
+        c = ServerCountersC()
+        _check(lib().fdwt_server_stats(self.h, ctypes.byref(c)))
+        return {n: getattr(c, n) for n, _ in ServerCountersC._fields_}
+
+    def close(self):
+        if self.h:
+            lib().fdwt_server_free(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 def query_depth(p):

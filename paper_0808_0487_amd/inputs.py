@@ -120,3 +120,38 @@ def batch_jobs(n, seed, m_lo=12, m_hi=22, s_lo=5, s_hi=50):
         alpha = float(g.uniform(1.0, 3.0))
         out.append((m, s, alpha, 10_000 + 7 * seed + i))
     return out
+
+
+def serving_workload(duration_s, rate, seed, n_nets=64, nq=4096, m_lo=10, m_hi=26, s_lo=2, s_hi=50,
+                     cap_points=1 << 26):
+    """Serving recipe: Poisson arrivals at `rate` per second for duration_s
+    seconds; each request picks one of n_nets seeded nets (p uniform in
+    {2, 3, 5}, m = round(exp(U[ln m_lo, ln m_hi])) capped so that p^m <=
+    cap_points, s uniform in s_lo..s_hi), is an interpolation or an
+    effective-dimension job with equal odds, and samples the product or the
+    exponential family with equal odds (parameters drawn per request).
+    Interpolation jobs carry nq uniform query points.  Returns (nets, reqs):
+    nets[i] = (p, m, s, generator seed); reqs = list of dicts with keys t
+    (arrival, s), net, kind, family, a, qseed."""
+    g = rng(seed)
+    nets = []
+    for i in range(n_nets):
+        p = int(g.choice([2, 3, 5]))
+        m = log_uniform_m(g, m_lo, m_hi, p, cap_points)
+        s = int(g.integers(s_lo, s_hi + 1))
+        nets.append((p, m, s, 50_000 + 13 * seed + i))
+    reqs = []
+    t = 0.0
+    k = 0
+    while True:
+        t += float(g.exponential(1.0 / rate))
+        if t >= duration_s:
+            break
+        ni = int(g.integers(0, n_nets))
+        kind = "interp" if g.random() < 0.5 else "eff_dim"
+        family = "product" if g.random() < 0.5 else "exp"
+        fseed = 70_000 + 17 * seed + k
+        reqs.append({"t": t, "net": ni, "kind": kind, "family": family,
+                     "a": family_params(family, nets[ni][2], seed=fseed), "qseed": fseed})
+        k += 1
+    return nets, reqs
