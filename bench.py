@@ -48,6 +48,12 @@ def parse():
                     help="after timing, run a 256 MiB device copy (reference for HBM byte counters)")
     ap.add_argument("--no-batch", action="store_true", help="skip the ragged-batch leg")
     ap.add_argument("--batch-jobs", type=int, default=512)
+    ap.add_argument("--no-serve", action="store_true", help="skip the serving leg")
+    ap.add_argument("--serve-window", type=float, default=0.2,
+                    help="seconds of Poisson arrivals (at --serve-rate) replayed in the serving leg")
+    ap.add_argument("--serve-rate", type=float, default=200.0)
+    ap.add_argument("--serve-budget-gb", type=float, default=200.0)
+    ap.add_argument("--serve-lanes", type=int, default=8)
     ap.add_argument("--m", type=int, default=24)
     ap.add_argument("--s", type=int, default=20)
     return ap.parse_args()
@@ -176,6 +182,65 @@ def batched_leg(torch, fdwt, inputs, n_jobs, reps=5):
             "speedup_batch_vs_plain": t_plain / t32}
 
 
+def serving_leg(fdwt, inputs, window, rate, budget_gb, lanes):
+    """Serving workload: Poisson arrivals at `rate` per second over `window`
+    seconds, requests drawn from a pool of 64 seeded nets (p in {2, 3, 5},
+    m log-uniform in [10, 26] capped at 2^26 points, s in 2..50), half
+    interpolation (4096 queries) and half effective dimension, product or
+    exponential family; the server runs with a `budget_gb` device budget.
+    Requests are generated before the clock starts and submitted at their
+    arrival times by a separate thread; latency = completion - submission."""
+    import threading
+    nets, reqs = inputs.serving_workload(window, rate, seed=5)
+    built = []
+    for r in reqs:
+        p, m, s, cs = nets[r["net"]]
+        C = inputs.upper_triangular_generators(p, m, s, cs)
+        q = inputs.queries(p, s, 4096, r["qseed"]) if r["kind"] == "interp" else None
+        built.append(fdwt.Request(r["kind"], p, m, s, C, r["net"], r["family"], r["a"], 2.0,
+                                  inputs.kernel_weights(s), q))
+    sv = fdwt.Server(int(budget_gb * (1 << 30)), lanes=lanes, max_bypass=8, effdim_chunk_bytes=4 << 30)
+    ids = [None] * len(built)
+    t_start = time.perf_counter()
+
+    def submitter():
+        for i, (r, rq) in enumerate(zip(reqs, built)):
+            delay = r["t"] - (time.perf_counter() - t_start)
+            if delay > 0:
+                time.sleep(delay)
+            ids[i] = sv.submit(rq)
+
+    th = threading.Thread(target=submitter)
+    th.start()
+    infos = []
+    for i in range(len(built)):
+        while ids[i] is None:
+            time.sleep(0.0005)
+        infos.append(sv.wait(ids[i])[0])
+    th.join()
+    st = sv.stats()
+    sv.close()
+    lat = np.array([x["t_done"] - x["t_submit"] for x in infos])
+    que = np.array([x["t_admit"] - x["t_submit"] for x in infos])
+    svc = np.array([x["t_done"] - x["t_admit"] for x in infos])
+    span = max(x["t_done"] for x in infos) - min(x["t_submit"] for x in infos)
+    pts = float(sum(rq.p ** rq.m for rq in built))
+    evals = float(sum(rq.p ** rq.m * rq.s * rq.nq for rq in built))
+
+    def pct(a):
+        return {"p50": float(np.percentile(a, 50)), "p99": float(np.percentile(a, 99)), "mean": float(a.mean())}
+
+    return {"requests": len(built), "offered_rate_per_s": rate, "arrival_window_s": window,
+            "budget_GB": budget_gb, "lanes": lanes,
+            "latency_s": pct(lat), "queue_s": pct(que), "service_s": pct(svc),
+            "makespan_s": span, "throughput_req_per_s": len(built) / span,
+            "points_per_s": pts / span, "eval_coordinates_per_s": evals / span,
+            "kinds": {k: sum(1 for r in built if r.kind == k) for k in ("interp", "eff_dim")},
+            "server": st,
+            "error": "each served result is bit-identical to the one-call library path on the same inputs "
+                     "(GPU tests), so served and plain accuracy are equal"}
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -281,6 +346,10 @@ def main():
     }
     if not args.no_batch:
         out["batched"] = batched_leg(torch, fdwt, inputs, args.batch_jobs)
+    torch.cuda.empty_cache()
+    if not args.no_serve:
+        out["serving"] = serving_leg(fdwt, inputs, args.serve_window, args.serve_rate, args.serve_budget_gb,
+                                     args.serve_lanes)
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(p, m, s, C)
     print(json.dumps(out), flush=True)

@@ -10,7 +10,11 @@
 //   in LDS).
 // p odd: digits are packed in 4-bit fields, digit y_{r+1} at bits 4(m-1-r);
 //   the contribution v * (column c of C_j) mod p of each index digit v comes
-//   from a table and is added field-wise modulo p.
+//   from a table and is added field-wise modulo p.  OddCoords splits the
+//   index as n = h p^K + r: a workgroup table (LDS) holds the packed sum over
+//   the K low digits for every r < p^K, and per group of 256 consecutive
+//   points the few high parts h that occur are summed once into LDS, so a
+//   coordinate costs one field-wise addition.
 #pragma once
 
 #include "fdwt_internal.h"
@@ -55,18 +59,63 @@ __device__ __forceinline__ uint64_t addmod_packed(uint64_t a, uint64_t b) {
   return s - (uint64_t)P * ge;
 }
 
-// Packed digits of X_j(n), p odd.  ptab: [s][m][P].
+// Packed digits of X_j(n) through workgroup tables (see the file comment).
+// Layout in LDS: t0 [s][PK] then u [s][NH] (uint64).
 template <int P>
-__device__ __forceinline__ uint64_t packed_odd(const uint64_t* __restrict__ ptab, int j, int m, int64_t n) {
-  uint64_t acc = 0;
-  const uint64_t* t = ptab + (int64_t)j * m * P;
-  for (int c = 0; c < m; ++c) {
-    const int dgt = (int)(n % P);
-    n /= P;
-    acc = addmod_packed<P>(acc, t[c * P + dgt]);
+struct OddCoords {
+  static constexpr int K = P == 3 ? 4 : 2;               // low digits per table entry
+  static constexpr int PK = P == 3 ? 81 : 25;            // P^K
+  static constexpr int NH = kChunk / PK + 2;             // high parts per group (at most)
+  static constexpr size_t lds_bytes(int s) { return (size_t)s * (PK + NH) * 8; }
+  const uint64_t* ptab;  // [s][m][P] (global)
+  int s, m;
+  uint64_t* t0;          // LDS [s][PK]
+  uint64_t* u;           // LDS [s][NH]
+  uint32_t hi0 = 0;
+
+  // Low-digit tables (once per workgroup; ends with a barrier).
+  __device__ __forceinline__ void stage_tables() const {
+    for (int i = threadIdx.x; i < s * PK; i += blockDim.x) {
+      const int j = i / PK;
+      int r = i - j * PK;
+      const uint64_t* t = ptab + (int64_t)j * m * P;
+      uint64_t acc = 0;
+      for (int c = 0; c < K && c < m; ++c) {
+        acc = addmod_packed<P>(acc, t[c * P + r % P]);
+        r /= P;
+      }
+      t0[i] = acc;
+    }
+    __syncthreads();
   }
-  return acc;
-}
+  // High parts of the group starting at `base` (a multiple of kChunk).
+  // Callers put a barrier before (LDS reuse) and after.
+  __device__ __forceinline__ void stage_group(int64_t base) {
+    hi0 = (uint32_t)(base / PK);
+    const int nh = (int)((base + kChunk - 1) / PK - hi0 + 1);
+    for (int i = threadIdx.x; i < s * nh; i += blockDim.x) {
+      const int j = i / nh, k = i - (i / nh) * nh;
+      uint32_t h = hi0 + k;
+      const uint64_t* t = ptab + (int64_t)j * m * P;
+      uint64_t acc = 0;
+      for (int c = K; c < m; ++c) {
+        acc = addmod_packed<P>(acc, t[c * P + h % P]);
+        h /= P;
+      }
+      u[j * NH + k] = acc;
+    }
+  }
+  // Index split of point n (n < 2^26) for X(): r = n mod PK, h - hi0.
+  __device__ __forceinline__ void split(int64_t n, int& r, int& k) const {
+    const uint32_t nn = (uint32_t)n;
+    const uint32_t h = nn / PK;
+    r = (int)(nn - h * PK);
+    k = (int)(h - hi0);
+  }
+  __device__ __forceinline__ uint64_t X(int j, int r, int k) const {
+    return addmod_packed<P>(t0[j * PK + r], u[j * NH + k]);
+  }
+};
 
 // Canonical integer sum_r y_{r+1} p^{m-1-r} from packed fields.
 template <int P>
@@ -74,6 +123,16 @@ __device__ __forceinline__ uint32_t canon_odd(uint64_t packed, int m) {
   uint32_t X = 0;
   for (int r = 0; r < m; ++r) X = X * P + (uint32_t)((packed >> (4 * (m - 1 - r))) & 15u);
   return X;
+}
+
+// Digit string of packed fields for the interpolant evaluation: digit
+// y_{f+1} in bits [62-3f, 60-3f] (3-bit fields under one zero bit), so that
+// the leading-zero count of the XOR of two strings is 3f + 1..3f + 3 when
+// digit f + 1 is the first that differs, and 64 when none does.
+__device__ __forceinline__ uint64_t eval_string_odd(uint64_t pk, int m) {
+  uint64_t v = 0;
+  for (int f = 0; f < m; ++f) v |= ((pk >> (4 * (m - 1 - f))) & 7ull) << (60 - 3 * f);
+  return v;
 }
 
 // Index t of the first non-zero digit (t = i - 1) of x_{n,j}, or m when

@@ -123,6 +123,7 @@ size_t spline_coef_ws_bytes(const Net& net, bool have_spectrum);
 int run_spline_coef(Net& net, Scratch& sc, const fdwt_kernel* kern, const void* gk, const void* ft, float* c,
                     hipStream_t st);
 size_t packed_bytes(const Net& net);       // packed coordinates of all points (launch_net_packed)
+size_t eval_tables_bytes(const Net& net);  // staged per-lane factor tables of the evaluation
 size_t spline_eval_ws_bytes(const Net& net, int64_t nq, bool have_packed);
 int run_spline_eval(Net& net, Scratch& sc, const fdwt_kernel* kern, const void* packed, const float* c,
                     int64_t nq, const uint32_t* q, float* sf, hipStream_t st);

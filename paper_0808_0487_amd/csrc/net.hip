@@ -37,15 +37,25 @@ __global__ void __launch_bounds__(kChunk) k_coords_p2(const uint32_t* xtab, int 
 }
 
 template <int P, int MODE>
-__global__ void __launch_bounds__(256) k_coords_odd(const uint64_t* ptab, int s, int m, int64_t N,
-                                                    float inv_pm, void* out) {
-  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-  for (int64_t n = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; n < N; n += stride) {
-    for (int j = 0; j < s; ++j) {
-      const uint64_t pk = packed_odd<P>(ptab, j, m, n);
-      if (MODE == CM_DIGITS) ((uint32_t*)out)[(int64_t)j * N + n] = canon_odd<P>(pk, m);
-      if (MODE == CM_POINTS) ((float*)out)[(int64_t)j * N + n] = (float)canon_odd<P>(pk, m) * inv_pm;
-      if (MODE == CM_SHIFTED) ((uint64_t*)out)[(int64_t)j * N + n] = pk;
+__global__ void __launch_bounds__(kChunk) k_coords_odd(const uint64_t* ptab, int s, int m, int64_t N,
+                                                       float inv_pm, void* out) {
+  extern __shared__ __align__(16) uint64_t lds_odd[];
+  OddCoords<P> oc{ptab, s, m, lds_odd, lds_odd + s * OddCoords<P>::PK};
+  oc.stage_tables();
+  for (int64_t base = (int64_t)blockIdx.x * kChunk; base < N; base += (int64_t)gridDim.x * kChunk) {
+    __syncthreads();
+    oc.stage_group(base);
+    __syncthreads();
+    const int64_t n = base + threadIdx.x;
+    if (n < N) {
+      int r, k;
+      oc.split(n, r, k);
+      for (int j = 0; j < s; ++j) {
+        const uint64_t pk = oc.X(j, r, k);
+        if (MODE == CM_DIGITS) ((uint32_t*)out)[(int64_t)j * N + n] = canon_odd<P>(pk, m);
+        if (MODE == CM_POINTS) ((float*)out)[(int64_t)j * N + n] = (float)canon_odd<P>(pk, m) * inv_pm;
+        if (MODE == CM_SHIFTED) ((uint64_t*)out)[(int64_t)j * N + n] = eval_string_odd(pk, m);
+      }
     }
   }
 }
@@ -99,16 +109,33 @@ __global__ void __launch_bounds__(kChunk) k_sample_p2(const uint32_t* xtab, int 
 }
 
 template <int P, int FAM>
-__global__ void __launch_bounds__(256) k_sample_odd(const uint64_t* ptab, FamilyArgs fa, int m, int64_t N,
-                                                    float inv_pm, float* f) {
-  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-  for (int64_t n = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; n < N; n += stride) {
-    float acc = fam_init<FAM>();
-    for (int j = 0; j < fa.s; ++j) {
-      const uint32_t X = canon_odd<P>(packed_odd<P>(ptab, j, m, n), m);
-      acc = fam_step<FAM>(acc, fa.a[j], fa.inv1a[j], (float)X * inv_pm);
+__global__ void __launch_bounds__(kChunk) k_sample_odd(const uint64_t* ptab, FamilyArgs fa, int m, int64_t N,
+                                                       float inv_pm, float* f) {
+  extern __shared__ __align__(16) uint64_t lds_odd[];
+  const int s = fa.s;
+  OddCoords<P> oc{ptab, s, m, lds_odd, lds_odd + s * OddCoords<P>::PK};
+  float* la = reinterpret_cast<float*>(lds_odd + OddCoords<P>::lds_bytes(s) / 8);
+  float* li = la + kMaxS;
+  for (int j = threadIdx.x; j < s; j += blockDim.x) {
+    la[j] = fa.a[j];
+    li[j] = fa.inv1a[j];
+  }
+  oc.stage_tables();
+  for (int64_t base = (int64_t)blockIdx.x * kChunk; base < N; base += (int64_t)gridDim.x * kChunk) {
+    __syncthreads();
+    oc.stage_group(base);
+    __syncthreads();
+    const int64_t n = base + threadIdx.x;
+    if (n < N) {
+      int r, k;
+      oc.split(n, r, k);
+      float acc = fam_init<FAM>();
+      for (int j = 0; j < s; ++j) {
+        const uint32_t X = canon_odd<P>(oc.X(j, r, k), m);
+        acc = fam_step<FAM>(acc, la[j], li[j], (float)X * inv_pm);
+      }
+      f[n] = fam_final<FAM>(acc);
     }
-    f[n] = fam_final<FAM>(acc);
   }
 }
 
@@ -130,10 +157,14 @@ static int coords(const Net& net, void* out, hipStream_t st) {
     hipLaunchKernelGGL(k_coords_p2<MODE>, dim3(g), dim3(kChunk), (size_t)net.s * 257 * 4, st, net.d_xtab,
                        net.nbytes, net.s, net.m, net.N, out);
   } else if (net.p == 3) {
-    hipLaunchKernelGGL((k_coords_odd<3, MODE>), dim3(g), dim3(256), 0, st, net.d_ptab, net.s, net.m,
+    const size_t lds = OddCoords<3>::lds_bytes(net.s);
+    if (int rc = allow_lds((const void*)k_coords_odd<3, MODE>, lds)) return rc;
+    hipLaunchKernelGGL((k_coords_odd<3, MODE>), dim3(g), dim3(kChunk), lds, st, net.d_ptab, net.s, net.m,
                        net.N, inv_pm(net), out);
   } else {
-    hipLaunchKernelGGL((k_coords_odd<5, MODE>), dim3(g), dim3(256), 0, st, net.d_ptab, net.s, net.m,
+    const size_t lds = OddCoords<5>::lds_bytes(net.s);
+    if (int rc = allow_lds((const void*)k_coords_odd<5, MODE>, lds)) return rc;
+    hipLaunchKernelGGL((k_coords_odd<5, MODE>), dim3(g), dim3(kChunk), lds, st, net.d_ptab, net.s, net.m,
                        net.N, inv_pm(net), out);
   }
   FDWT_HIP(hipGetLastError());
@@ -152,10 +183,14 @@ static int sample_fam(const Net& net, const FamilyArgs& fa, float* f, unsigned g
     hipLaunchKernelGGL(k_sample_p2<FAM>, dim3(g), dim3(kChunk), lds, st, net.d_xtab, net.nbytes, fa, net.m,
                        net.N, f);
   } else if (net.p == 3) {
-    hipLaunchKernelGGL((k_sample_odd<3, FAM>), dim3(g), dim3(256), 0, st, net.d_ptab, fa, net.m, net.N,
+    const size_t lds = OddCoords<3>::lds_bytes(net.s) + 2 * kMaxS * 4;
+    if (int rc = allow_lds((const void*)k_sample_odd<3, FAM>, lds)) return rc;
+    hipLaunchKernelGGL((k_sample_odd<3, FAM>), dim3(g), dim3(kChunk), lds, st, net.d_ptab, fa, net.m, net.N,
                        inv_pm(net), f);
   } else {
-    hipLaunchKernelGGL((k_sample_odd<5, FAM>), dim3(g), dim3(256), 0, st, net.d_ptab, fa, net.m, net.N,
+    const size_t lds = OddCoords<5>::lds_bytes(net.s) + 2 * kMaxS * 4;
+    if (int rc = allow_lds((const void*)k_sample_odd<5, FAM>, lds)) return rc;
+    hipLaunchKernelGGL((k_sample_odd<5, FAM>), dim3(g), dim3(kChunk), lds, st, net.d_ptab, fa, net.m, net.N,
                        inv_pm(net), f);
   }
   return FDWT_OK;

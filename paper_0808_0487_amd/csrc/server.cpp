@@ -85,7 +85,7 @@ Sizes request_sizes(const Request& r, size_t chunk_bytes) {
     z.sf = (size_t)r.nq * 4;
     ws = std::max(ws, spline_coef_ws_bytes(n, true));
     ws = std::max(ws, spline_eval_ws_bytes(n, r.nq, true));
-    z.pin = tab_pin + align_ws((size_t)r.s * (query_depth(r.p) + 1) * 4) + align_ws(z.qd) + align_ws(z.sf);
+    z.pin = tab_pin + align_ws(eval_tables_bytes(n)) + align_ws(z.qd) + align_ws(z.sf);
   } else {
     z.chunk = eff_dim_chunk(n, chunk_bytes);
     ws = std::max(ws, eff_dim_ws_bytes(n, true, z.chunk));

@@ -63,20 +63,23 @@ __global__ void __launch_bounds__(kChunk) k_kernel_cols(NetArgs na, const double
     ltr[i] = tr[i];
   }
   P2Coords pc{na.xtab, na.nbytes, s, lt0, lt0 + s * 256};
+  uint64_t* lodd = reinterpret_cast<uint64_t*>(ltr + s * kTab);
+  OddCoords<P == 2 ? 3 : P> oc{na.ptab, s, na.m, lodd, lodd + s * OddCoords<P == 2 ? 3 : P>::PK};
   if constexpr (P == 2) pc.stage_tables();
-  else __syncthreads();
+  else oc.stage_tables();
   const bool need_r = c1 > 1;
   const bool need_q = c1 > s + 1;
   const int64_t N = na.N;
   const int m = na.m;
   for (int64_t base = (int64_t)blockIdx.x * kChunk; base < N; base += (int64_t)gridDim.x * kChunk) {
-    if constexpr (P == 2) {
-      __syncthreads();
-      pc.stage_group(base);
-      __syncthreads();
-    }
+    __syncthreads();
+    if constexpr (P == 2) pc.stage_group(base);
+    else oc.stage_group(base);
+    __syncthreads();
     const int64_t n = base + threadIdx.x;
     const int64_t nn = n < N ? n : N - 1;
+    int orr = 0, ok = 0;
+    if constexpr (P != 2) oc.split(nn, orr, ok);
     double K = 1.0, u = 0.0;
     double e[SMAX + 1];
 #pragma unroll
@@ -84,7 +87,7 @@ __global__ void __launch_bounds__(kChunk) k_kernel_cols(NetArgs na, const double
     for (int j = 0; j < s; ++j) {
       int t;
       if constexpr (P == 2) t = lead_p2(pc.X(j, nn), m);
-      else t = lead_odd(packed_odd<P>(na.ptab, j, m, nn), m);
+      else t = lead_odd(oc.X(j, orr, ok), m);
       K *= ltk[j * kTab + t];
       if (need_r) {
         const double r = ltr[j * kTab + t];
@@ -182,56 +185,64 @@ __global__ void __launch_bounds__(256) k_sum_rows(const double* __restrict__ in,
 // --------------------------------------------------------- evaluation
 constexpr int kNS = 64;  // points staged per step
 
+// Query digit strings, p odd: the D digits of q[j][i] (most significant
+// first) in the layout of eval_string_odd.
 template <int P>
-__global__ void __launch_bounds__(256) k_query_prep(const uint32_t* __restrict__ q, int64_t nq, int s, int m,
-                                                    int D, uint64_t* __restrict__ qh, uint32_t* __restrict__ qt) {
+__global__ void __launch_bounds__(256) k_query_prep(const uint32_t* __restrict__ q, int64_t nq, int s, int D,
+                                                    uint64_t* __restrict__ qs) {
   const int64_t total = (int64_t)s * nq;
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < total; i += (int64_t)gridDim.x * blockDim.x) {
     uint32_t Q = q[i];
-    // digits d_1..d_D (most significant first)
-    uint32_t dg[32];
-    for (int l = D - 1; l >= 0; --l) {
-      dg[l] = Q % P;
+    uint64_t v = 0;
+    for (int f = D - 1; f >= 0; --f) {
+      v |= (uint64_t)(Q % P) << (60 - 3 * f);
       Q /= P;
     }
-    uint64_t head = 0;
-    for (int l = 0; l < m; ++l) head |= (uint64_t)dg[l] << (4 * (m - 1 - l));
-    uint32_t tail = (uint32_t)D;
-    for (int l = D - 1; l >= m; --l)
-      if (dg[l] != 0) tail = (uint32_t)l;
-    qh[i] = head;
-    qt[i] = tail;
+    qs[i] = v;
   }
 }
 
+// Lane holding the kernel factor for the XOR z of a query and a point
+// coordinate.  p = 2: the first differing bit t is the leading-zero count,
+// and z = 0 (v_ffbh_u32 returns all ones) lands in lane 63.  p odd: the
+// leading-zero count of the digit strings is 3t + 1..3t + 3, or 64 (lane 0)
+// when all digits agree.  The per-lane tables are laid out to match.
+template <int P>
+__device__ __forceinline__ int factor_lane_addr(typename std::conditional<P == 2, uint32_t, uint64_t>::type z) {
+  if constexpr (P == 2) {
+    int c;
+    asm("v_ffbh_u32 %0, %1" : "=v"(c) : "v"(z));
+    return c << 2;
+  } else {
+    return __clzll(z) << 2;
+  }
+}
+
+// Sf at queries as partial sums over point chunks (blockIdx.y): each thread
+// takes one query; the points of a chunk are staged in LDS kNS at a time and
+// read as 16-byte broadcasts; the factor 1 + gamma_j K'(.) of coordinate j
+// comes from a table spread over the lanes of the wave (tlane[j][lane], in
+// registers) through ds_bpermute, which has no bank conflicts.
 template <int P, int SMAX>
 __global__ void __launch_bounds__(256) k_spline_eval(const void* __restrict__ Xp, const float* __restrict__ c,
-                                                     int64_t N, int s, int m, const uint32_t* __restrict__ q,
-                                                     const uint64_t* __restrict__ qh,
-                                                     const uint32_t* __restrict__ qt, int64_t nq,
-                                                     const float* __restrict__ te, int ntab, int64_t ppc,
+                                                     int64_t N, int s, const void* __restrict__ qv, int64_t nq,
+                                                     const float* __restrict__ tlane, int64_t ppc,
                                                      df* __restrict__ partial) {
   using XT = typename std::conditional<P == 2, uint32_t, uint64_t>::type;
+  constexpr int V = 16 / sizeof(XT);  // points per LDS read
   extern __shared__ __align__(16) unsigned char smem[];
-  float* lte = reinterpret_cast<float*>(smem);
-  XT* lx = reinterpret_cast<XT*>(smem + align_up((size_t)s * ntab * 4));
-  float* lc = reinterpret_cast<float*>(reinterpret_cast<unsigned char*>(lx) + (size_t)s * kNS * sizeof(XT));
-  for (int i = threadIdx.x; i < s * ntab; i += blockDim.x) lte[i] = te[i];
-
+  XT* lx = reinterpret_cast<XT*>(smem);                                       // [s][kNS]
+  float* lc = reinterpret_cast<float*>(smem + (size_t)s * kNS * sizeof(XT));  // [kNS]
+  const int lane = threadIdx.x & 63;
   const int64_t qi = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const int64_t qq = qi < nq ? qi : nq - 1;
   XT qr[SMAX];
-  uint32_t tl[SMAX];
+  int tj[SMAX];
 #pragma unroll
   for (int j = 0; j < SMAX; ++j) {
     if (j < s) {
-      if constexpr (P == 2) {
-        qr[j] = q[(int64_t)j * nq + qq];
-        tl[j] = 0;
-      } else {
-        qr[j] = qh[(int64_t)j * nq + qq];
-        tl[j] = qt[(int64_t)j * nq + qq];
-      }
+      qr[j] = ((const XT*)qv)[(int64_t)j * nq + qq];
+      tj[j] = __float_as_int(tlane[j * 64 + lane]);
     }
   }
   const int64_t nbeg = (int64_t)blockIdx.y * ppc;
@@ -247,19 +258,24 @@ __global__ void __launch_bounds__(256) k_spline_eval(const void* __restrict__ Xp
     for (int k = threadIdx.x; k < kNS; k += blockDim.x) lc[k] = (n0 + k < nend) ? c[n0 + k] : 0.0f;
     __syncthreads();
     float sub = 0.0f;
-    for (int k = 0; k < kNS; ++k) {
-      float prod = 1.0f;
+    for (int k = 0; k < kNS; k += V) {
+      float pr[V];
+#pragma unroll
+      for (int u = 0; u < V; ++u) pr[u] = 1.0f;
 #pragma unroll
       for (int j = 0; j < SMAX; ++j) {
         if (j < s) {
-          const XT z = qr[j] ^ lx[j * kNS + k];
-          int t;
-          if constexpr (P == 2) t = __clz(z);
-          else t = z ? ((__clzll(z) - 64 + 4 * m) >> 2) : (int)tl[j];
-          prod *= lte[j * ntab + t];
+          XT xv[V];
+          *reinterpret_cast<uint4*>(xv) = *reinterpret_cast<const uint4*>(lx + j * kNS + k);
+#pragma unroll
+          for (int u = 0; u < V; ++u) {
+            const int a = factor_lane_addr<P>(qr[j] ^ xv[u]);
+            pr[u] *= __int_as_float(__builtin_amdgcn_ds_bpermute(a, tj[j]));
+          }
         }
       }
-      sub += lc[k] * prod;
+#pragma unroll
+      for (int u = 0; u < V; ++u) sub += lc[k + u] * pr[u];
     }
     acc = add(acc, df{sub, 0.0f});
   }
@@ -313,7 +329,8 @@ struct Carve {
 template <int P, int SMAX>
 static int kcols_launch(const Net& net, const double* tk, const double* tr, int c0, int c1, double* out,
                         hipStream_t st) {
-  const size_t lds = (size_t)2 * net.s * kTab * 8 + (P == 2 ? (size_t)net.s * 257 * 4 : 0);
+  const size_t lds = (size_t)2 * net.s * kTab * 8 +
+                     (P == 2 ? (size_t)net.s * 257 * 4 : OddCoords<P == 2 ? 3 : P>::lds_bytes(net.s));
   if (int rc = allow_lds((const void*)k_kernel_cols<P, SMAX>, lds)) return rc;
   const unsigned grid = (unsigned)std::min<int64_t>((net.N + kChunk - 1) / kChunk, 2048);
   hipEvent_t tb = timed_begin(st);
@@ -444,17 +461,15 @@ int run_spline_coef(Net& net, Scratch& sc, const fdwt_kernel* kern, const void* 
 
 // ----------------------------------------------------------- evaluation
 template <int P>
-static int launch_eval(Net& net, const void* Xp, const float* c, int64_t nq, const uint32_t* q,
-                       const uint64_t* qh, const uint32_t* qt, const float* te, int ntab, df* partial,
-                       int gy, int64_t ppc, size_t lds, hipStream_t st) {
+static int launch_eval(Net& net, const void* Xp, const float* c, int64_t nq, const void* qv, const float* tl,
+                       df* partial, int gy, int64_t ppc, size_t lds, hipStream_t st) {
   const dim3 grid((unsigned)((nq + 255) / 256), (unsigned)gy);
   const int s = net.s;
 #define FDWT_EVAL(SM)                                                                              \
   {                                                                                                \
     auto fn = k_spline_eval<P, SM>;                                                                \
     if (int rc_ = allow_lds((const void*)fn, lds)) return rc_;                                     \
-    hipLaunchKernelGGL(fn, grid, dim3(256), lds, st, Xp, c, net.N, s, net.m, q, qh, qt, nq, te,    \
-                       ntab, ppc, partial);                                                        \
+    hipLaunchKernelGGL(fn, grid, dim3(256), lds, st, Xp, c, net.N, s, qv, nq, tl, ppc, partial);   \
   }
   if (s <= 8) FDWT_EVAL(8)
   else if (s <= 16) FDWT_EVAL(16)
@@ -464,6 +479,8 @@ static int launch_eval(Net& net, const void* Xp, const float* c, int64_t nq, con
   FDWT_HIP(hipGetLastError());
   return FDWT_OK;
 }
+
+size_t eval_tables_bytes(const Net& net) { return (size_t)net.s * 64 * 4; }
 
 size_t packed_bytes(const Net& net) { return (size_t)net.s * net.N * (net.p == 2 ? 4 : 8); }
 
@@ -481,10 +498,9 @@ static void eval_grid(int64_t N, int64_t nq, int* gy_out, int64_t* ppc_out) {
 }
 
 struct EvalWs {
-  float* te;
-  void* Xp;
-  uint64_t* qh;
-  uint32_t* qt;
+  float* tl;     // per-lane factor tables [s][64]
+  void* Xp;      // packed coordinates (when not given)
+  uint64_t* qs;  // p odd: query digit strings [s][nq]
   df* partial;
 };
 static void eval_layout(const Net& net, int64_t nq, bool have_packed, Carve& cv, EvalWs& w) {
@@ -492,10 +508,9 @@ static void eval_layout(const Net& net, int64_t nq, bool have_packed, Carve& cv,
   int gy;
   int64_t ppc;
   eval_grid(net.N, nq, &gy, &ppc);
-  w.te = (float*)cv.take((size_t)s * (query_depth(p) + 1) * 4);
+  w.tl = (float*)cv.take(eval_tables_bytes(net));
   w.Xp = have_packed ? nullptr : cv.take(packed_bytes(net));
-  w.qh = p == 2 ? nullptr : (uint64_t*)cv.take((size_t)s * nq * 8);
-  w.qt = p == 2 ? nullptr : (uint32_t*)cv.take((size_t)s * nq * 4);
+  w.qs = p == 2 ? nullptr : (uint64_t*)cv.take((size_t)s * nq * 8);
   w.partial = (df*)cv.take((size_t)gy * nq * sizeof(df));
 }
 size_t spline_eval_ws_bytes(const Net& net, int64_t nq, bool have_packed) {
@@ -509,7 +524,6 @@ int run_spline_eval(Net& net, Scratch& sc, const fdwt_kernel* kern, const void* 
                     const uint32_t* q, float* sf, hipStream_t st) {
   const int p = net.p, s = net.s, m = net.m;
   const int D = query_depth(p);
-  const int ntab = D + 1;
   const int64_t N = net.N;
   const size_t xb = (p == 2) ? 4 : 8;
   int gy;
@@ -520,12 +534,20 @@ int run_spline_eval(Net& net, Scratch& sc, const fdwt_kernel* kern, const void* 
   Carve cv(sc.ws);
   EvalWs w;
   eval_layout(net, nq, packed != nullptr, cv, w);
-  // te[j][t]: 1 + gamma_j K'(t+1) for t < D, 1 + gamma_j for t = D (equal digits).
-  std::vector<float> hte((size_t)s * ntab);
-  for (int j = 0; j < s; ++j)
-    for (int t = 0; t < ntab; ++t)
-      hte[(size_t)j * ntab + t] = (float)(1.0 + kern->gamma[j] * kprime(p, kern->alpha, t < D ? t + 1 : 0));
-  rc = upload(sc, hte.data(), hte.size() * 4, w.te, st);
+  // Factor 1 + gamma_j K'(t+1) of first differing digit t < D, and 1 + gamma_j
+  // when all D digits agree, placed in the lane factor_lane_addr selects.
+  std::vector<float> htl((size_t)s * 64, 1.0f);
+  for (int j = 0; j < s; ++j) {
+    float* row = htl.data() + (size_t)j * 64;
+    const float eq = (float)(1.0 + kern->gamma[j] * kprime(p, kern->alpha, 0));
+    for (int t = 0; t < D; ++t) {
+      const float v = (float)(1.0 + kern->gamma[j] * kprime(p, kern->alpha, t + 1));
+      if (p == 2) row[t] = v;
+      else for (int l = 3 * t + 1; l <= 3 * t + 3; ++l) row[l] = v;
+    }
+    row[p == 2 ? 63 : 0] = eq;
+  }
+  rc = upload(sc, htl.data(), htl.size() * 4, w.tl, st);
   if (rc) return rc;
   const void* Xp = packed;
   if (!Xp) {
@@ -533,14 +555,18 @@ int run_spline_eval(Net& net, Scratch& sc, const fdwt_kernel* kern, const void* 
     if (rc) return rc;
     Xp = w.Xp;
   }
-  if (p == 3) hipLaunchKernelGGL(k_query_prep<3>, dim3(grid1((int64_t)s * nq)), dim3(256), 0, st, q, nq, s, m, D, w.qh, w.qt);
-  if (p == 5) hipLaunchKernelGGL(k_query_prep<5>, dim3(grid1((int64_t)s * nq)), dim3(256), 0, st, q, nq, s, m, D, w.qh, w.qt);
-  FDWT_HIP(hipGetLastError());
-  const size_t lds = align_up((size_t)s * ntab * 4) + (size_t)s * kNS * xb + kNS * 4;
+  const void* qv = q;
+  if (p != 2) {
+    if (p == 3) hipLaunchKernelGGL(k_query_prep<3>, dim3(grid1((int64_t)s * nq)), dim3(256), 0, st, q, nq, s, D, w.qs);
+    else hipLaunchKernelGGL(k_query_prep<5>, dim3(grid1((int64_t)s * nq)), dim3(256), 0, st, q, nq, s, D, w.qs);
+    FDWT_HIP(hipGetLastError());
+    qv = w.qs;
+  }
+  const size_t lds = (size_t)s * kNS * xb + kNS * 4;
   hipEvent_t tb = timed_begin(st);
-  if (p == 2) rc = launch_eval<2>(net, Xp, c, nq, q, nullptr, nullptr, w.te, ntab, w.partial, gy, ppc, lds, st);
-  else if (p == 3) rc = launch_eval<3>(net, Xp, c, nq, q, w.qh, w.qt, w.te, ntab, w.partial, gy, ppc, lds, st);
-  else rc = launch_eval<5>(net, Xp, c, nq, q, w.qh, w.qt, w.te, ntab, w.partial, gy, ppc, lds, st);
+  if (p == 2) rc = launch_eval<2>(net, Xp, c, nq, qv, w.tl, w.partial, gy, ppc, lds, st);
+  else if (p == 3) rc = launch_eval<3>(net, Xp, c, nq, qv, w.tl, w.partial, gy, ppc, lds, st);
+  else rc = launch_eval<5>(net, Xp, c, nq, qv, w.tl, w.partial, gy, ppc, lds, st);
   if (rc) return rc;
   timed_end(tb, st, FDWT_TC_EVAL, (double)nq * (double)N * s);
   hipLaunchKernelGGL(k_eval_finish, dim3(grid1(nq)), dim3(256), 0, st, w.partial, gy, nq, sf);
