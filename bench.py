@@ -110,8 +110,10 @@ def batched_leg(torch, fdwt, inputs, n_jobs, reps=5):
     """Ragged batch of n_jobs p = 2 functions (m in 12..22, s in 5..50,
     product family with alpha in [1, 3]): sampled on their own nets, then
     transformed (a) one job at a time with the plain transform, (b) as one
-    batch in float32, (c) as one batch with the bfloat16-split matrix-core
-    low stages, (d) the float32 batch replayed from a captured graph.
+    batch of grouped static passes with autotuned plans, (c) through the
+    generic persistent launch per pass level in float32 and (d) with the
+    bfloat16-split matrix-core low stages, (e) batch (b) replayed from a
+    captured graph.
     Accuracy of each path: normwise error per job against the library's
     float64 transform of the same data."""
     specs = inputs.batch_jobs(n_jobs, seed=4)
@@ -125,8 +127,14 @@ def batched_leg(torch, fdwt, inputs, n_jobs, reps=5):
     total = float(sum(2 ** sp[0] for sp in specs))
     y_plain = [torch.empty_like(x) for x in xs]
     y32 = [torch.empty_like(x) for x in xs]
+    y32g = [torch.empty_like(x) for x in xs]
     y16 = [torch.empty_like(x) for x in xs]
     b32 = fdwt.Batch([(sp[0], x, y) for sp, x, y in zip(specs, xs, y32)], "f32")
+    t0 = time.perf_counter()
+    b32.autotune(reps=3)
+    torch.cuda.synchronize()
+    t_tune = time.perf_counter() - t0
+    b32g = fdwt.Batch([(sp[0], x, y) for sp, x, y in zip(specs, xs, y32g)], "f32_generic")
     b16 = fdwt.Batch([(sp[0], x, y) for sp, x, y in zip(specs, xs, y16)], "bf16x2")
     stream = torch.cuda.current_stream()
 
@@ -149,6 +157,7 @@ def batched_leg(torch, fdwt, inputs, n_jobs, reps=5):
 
     t_plain = timed(plain)
     t32 = timed(b32.run)
+    t32g = timed(b32g.run)
     t16 = timed(b16.run)
     g = torch.cuda.CUDAGraph()
     gs = torch.cuda.Stream()
@@ -157,15 +166,17 @@ def batched_leg(torch, fdwt, inputs, n_jobs, reps=5):
         b32.run(stream=gs)
     t_graph = timed(g.replay)
     b32.check()
-    errs = {"plain": [], "f32": [], "bf16x2": []}
-    for net, x, yp, ya, yb in zip(nets, xs, y_plain, y32, y16):
+    errs = {"plain": [], "f32": [], "f32_generic": [], "bf16x2": []}
+    for net, x, yp, ya, yg, yb in zip(nets, xs, y_plain, y32, y32g, y16):
         ref = net.forward(x.double())
         den = float(torch.linalg.norm(ref))
-        for k, y in (("plain", yp), ("f32", ya), ("bf16x2", yb)):
+        for k, y in (("plain", yp), ("f32", ya), ("f32_generic", yg), ("bf16x2", yb)):
             errs[k].append(float(torch.linalg.norm(y.double() - ref)) / den)
     for net in nets:
         net.close()
+    plans = b32.describe()
     b32.close()
+    b32g.close()
     b16.close()
 
     def path(t, key):
@@ -177,7 +188,8 @@ def batched_leg(torch, fdwt, inputs, n_jobs, reps=5):
             "recipe": "m uniform 12..22, s uniform 5..50, product family a_j = j^-alpha, alpha uniform [1,3], "
                       "seed 4; sampling untimed; median of %d runs" % reps,
             "plain_per_job": path(t_plain, "plain"), "batch_f32": path(t32, "f32"),
-            "batch_bf16x2": path(t16, "bf16x2"),
+            "batch_f32_generic": path(t32g, "f32_generic"), "batch_bf16x2": path(t16, "bf16x2"),
+            "tuned_plans_m_emax_jobs": plans, "autotune_s": t_tune,
             "batch_f32_graph": {"ms": t_graph, "points_per_s": total / (t_graph * 1e-3)},
             "speedup_batch_vs_plain": t_plain / t32}
 

@@ -190,38 +190,50 @@ int fdwt_eff_dim(const fdwt_net* net, const fdwt_kernel* kern, int ft_type,
 
 /* A ragged batch of independent p = 2 forward transforms (float data, job j
  * of N_j = 2^{m_j} points, 1 <= m_j <= 26, normalised as fdwt_dwt_forward;
- * in_dev == out_dev allowed).  The transforms are Algorithm 1 applied to raw
- * data: no net is needed, the output index is the coset label as usual.  Each
- * job's transform is split into at most three passes; level k of the batch
- * (pass k of every job that has one) is ONE persistent kernel launch over all
- * those jobs' tiles, so a batch of any size is at most three launches, and no
- * workgroup ever waits on another.  Precision:
- *   FDWT_PREC_F32     float32 butterflies;
- *   FDWT_PREC_BF16X2  in each job's first pass the stages of index digits
- *                     0..3 (16-point Walsh-Hadamard blocks) run on the matrix
- *                     cores as H16 (hi + lo), x split into two bfloat16 terms,
- *                     float32 accumulation (relative error about 2^-18 per
- *                     element from the split); other stages float32.
- * fdwt_batch_create copies the job list to the device (buffers are fixed at
- * creation); fdwt_batch_run enqueues the level launches (nothing else; it
- * can be captured in a HIP graph); fdwt_batch_check waits for the stream and
- * reports any HIP error.  The batch owns its device work list; free it with
- * fdwt_batch_free (which synchronises the device first).  Jobs' buffers must
- * not overlap one another. */
+ * in_dev == out_dev allowed; different jobs' buffers must not overlap).  The
+ * transforms are Algorithm 1 applied to raw data: no net is needed, the
+ * output index is the coset label as usual.  Precision / kernel family:
+ *   FDWT_PREC_F32          float32; jobs of equal m (>= 7) form a group and
+ *                          each pass of a group is one launch of the static
+ *                          pass kernels over all its jobs (pointer tables);
+ *                          the per-group plan comes from fdwt_batch_autotune
+ *                          (or an earlier tuning of that m in the process);
+ *   FDWT_PREC_F32_GENERIC  float32 through one persistent launch per pass
+ *                          level over all jobs' tiles (at most three);
+ *   FDWT_PREC_BF16X2       as FDWT_PREC_F32_GENERIC, but in each job's first
+ *                          pass the stages of index digits 0..3 (16-point
+ *                          Walsh-Hadamard blocks) run on the matrix cores as
+ *                          H16 (hi + lo), x split into two bfloat16 terms,
+ *                          float32 accumulation (relative error about 2^-18
+ *                          per element from the split).
+ * Jobs with m < 7 always take the generic path.  No workgroup waits on
+ * another in any of them.  fdwt_batch_create copies the job list to the
+ * device (buffers are fixed at creation); fdwt_batch_run enqueues the
+ * launches (nothing else; it can be captured in a HIP graph);
+ * fdwt_batch_check waits for the stream and reports any HIP error.
+ * fdwt_batch_autotune times every distinct plan of every group (first pass
+ * of 2^10 .. 2^14 elements) `reps` times on `stream` and keeps the fastest
+ * (median); it overwrites the outputs and skips groups with a job in place.
+ * fdwt_batch_describe reports the groups (m, plan's first-pass bound emax,
+ * jobs), up to `cap` of them.  The batch owns its device lists; free it with
+ * fdwt_batch_free (which synchronises the device first). */
 typedef struct {
   int m;
   const float* in_dev;
   float* out_dev;
 } fdwt_batch_job;
 
-#define FDWT_PREC_F32    0
-#define FDWT_PREC_BF16X2 1
+#define FDWT_PREC_F32         0
+#define FDWT_PREC_BF16X2      1
+#define FDWT_PREC_F32_GENERIC 2
 
 typedef struct fdwt_batch fdwt_batch;
 
 int fdwt_batch_create(int n_jobs, const fdwt_batch_job* jobs_host, int precision, fdwt_batch** out);
 int fdwt_batch_run(fdwt_batch* batch, void* stream);
 int fdwt_batch_check(fdwt_batch* batch, void* stream);
+int fdwt_batch_autotune(fdwt_batch* batch, int reps, void* stream);
+int fdwt_batch_describe(const fdwt_batch* batch, int cap, int* m, int* emax, int* njobs, int* n_groups);
 void fdwt_batch_free(fdwt_batch* batch);
 
 /* ------------------------------------------------------------- serving */

@@ -3,12 +3,20 @@
 // A batch is a list of independent jobs (float data, N_j = 2^{m_j} points,
 // each normalised by 2^-m_j as in Eq. (eq_dwalshcoeff)).  Every job's
 // transform is split into passes (Algorithm 1's stages grouped by digit
-// ranges) and every pass into tiles.  Level k of the batch is the list of all
-// tiles of pass k of every job that has one; each level is one persistent
-// launch whose workgroups take the level's tiles with a fixed stride (largest
-// jobs first), so a batch of any number of jobs is at most three launches and
-// no workgroup ever waits for another: the kernel boundary between levels
-// orders pass k before pass k+1 (on MI355X the L2 of each XCD is not
+// ranges) and every pass into tiles.  Two ways to run them:
+//
+//  * grouped (FDWT_PREC_F32, m >= 7): jobs of equal m form a group; pass k of
+//    a group is one launch of the static-shape pass kernel over all of the
+//    group's tiles, its columns read through tables of the jobs' pointers.
+//    The plan of a group (how large the first, contiguous pass is) is picked
+//    by fdwt_batch_autotune, which times every distinct plan on the device.
+//  * generic (FDWT_PREC_BF16X2, FDWT_PREC_F32_GENERIC, and jobs with m < 7):
+//    level k of the batch is the list of all tiles of pass k of every job;
+//    each level is one persistent launch whose workgroups take the level's
+//    tiles with a fixed stride (largest jobs first).
+//
+// In both no workgroup ever waits for another: the kernel boundary between
+// passes orders pass k before pass k+1 (on MI355X the L2 of each XCD is not
 // coherent with the others for ordinary device memory inside a kernel).
 //
 // Precision FDWT_PREC_BF16X2: in each job's first pass the stages of index
@@ -20,7 +28,11 @@
 #include "pass_core.h"
 
 #include <algorithm>
+#include <cmath>
 #include <cstring>
+#include <functional>
+#include <map>
+#include <mutex>
 
 namespace fdwt {
 
@@ -130,11 +142,20 @@ __global__ void __launch_bounds__(kBThreads) k_batch_fwd(const BJob* __restrict_
 struct fdwt_batch {
   int device = 0;
   int n_jobs = 0, prec = 0;
+  // generic path
   fdwt::BJob* d_jobs = nullptr;
   fdwt::BItem* d_items = nullptr;
   int level_begin[fdwt::kBMaxPass + 1] = {0};  // items of level k: [begin[k], begin[k+1])
   int n_levels = 0;
   int grid_per_level[fdwt::kBMaxPass] = {0};
+  // grouped path: one entry per distinct m
+  struct Group {
+    int m = 0, emax = 14, njobs = 0;
+    bool in_place = false;
+    void** d_in = nullptr;   // device array of the jobs' input pointers
+    void** d_out = nullptr;  // ... and output pointers
+  };
+  std::vector<Group> groups;
   double alg_bytes = 0.0;
 };
 
@@ -175,41 +196,43 @@ static int batch_plan_job(int m, BJob& J) {
 
 using namespace fdwt;
 
+namespace fdwt {
+int p2_plan_passes(int m, int emax);
+bool p2_plans_equal(int m, int e1, int e2);
+int fwt_p2_group_pass(int m, int emax, int level, const void* const* in_tab, void* const* out_tab, int njobs,
+                      hipStream_t st);
+
+// Plans chosen by the tuner, per m, reused by later batches in the process.
+static std::mutex g_tuned_mu;
+static std::map<int, int> g_tuned_emax;
+
+static int tuned_emax(int m) {
+  std::lock_guard<std::mutex> g(g_tuned_mu);
+  auto it = g_tuned_emax.find(m);
+  return it == g_tuned_emax.end() ? 14 : it->second;
+}
+
+static size_t generic_lds() { return (size_t)((1 << kBLogE) + (1 << kBLogE) / 32 + 1) * sizeof(float); }
+
+static int run_group(const fdwt_batch::Group& g, hipStream_t st) {
+  const int np = p2_plan_passes(g.m, g.emax);
+  for (int k = 0; k < np; ++k)
+    if (int rc = fwt_p2_group_pass(g.m, g.emax, k, (const void* const*)g.d_in, g.d_out, g.njobs, st)) return rc;
+  return FDWT_OK;
+}
+}  // namespace fdwt
+
 extern "C" {
 
 int fdwt_batch_create(int n_jobs, const fdwt_batch_job* jobs, int precision, fdwt_batch** out) {
   if (!out || !jobs || n_jobs < 1 || n_jobs > (1 << 20)) return fail(FDWT_EINVAL, "bad batch arguments");
   *out = nullptr;
-  if (precision != FDWT_PREC_F32 && precision != FDWT_PREC_BF16X2) return fail(FDWT_EINVAL, "unknown precision");
-  std::vector<BJob> hj(n_jobs);
-  std::vector<BItem> hi;
-  int maxpass = 0;
-  double alg = 0.0;
+  if (precision != FDWT_PREC_F32 && precision != FDWT_PREC_BF16X2 && precision != FDWT_PREC_F32_GENERIC)
+    return fail(FDWT_EINVAL, "unknown precision");
   for (int j = 0; j < n_jobs; ++j) {
-    const fdwt_batch_job& u = jobs[j];
-    if (u.m < 1 || u.m > kMaxLog2N) return fail(FDWT_EINVAL, "job m must be in 1..26");
-    if (!u.in_dev || !u.out_dev) return fail(FDWT_EINVAL, "NULL job buffer");
-    BJob& J = hj[j];
-    std::memset(&J, 0, sizeof(J));
-    if (batch_plan_job(u.m, J)) return fail(FDWT_EUNSUPPORTED, "job needs too many passes");
-    J.in = u.in_dev;
-    J.out = u.out_dev;
-    maxpass = std::max(maxpass, J.npass);
-    alg += 8.0 * (double)(int64_t(1) << u.m);
+    if (jobs[j].m < 1 || jobs[j].m > kMaxLog2N) return fail(FDWT_EINVAL, "job m must be in 1..26");
+    if (!jobs[j].in_dev || !jobs[j].out_dev) return fail(FDWT_EINVAL, "NULL job buffer");
   }
-  // Level k: every tile of pass k of every job (largest jobs first).
-  std::vector<int> order(n_jobs);
-  for (int j = 0; j < n_jobs; ++j) order[j] = j;
-  std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return hj[a].m > hj[b].m; });
-  int level_begin[kBMaxPass + 1] = {0};
-  for (int ps = 0; ps < maxpass; ++ps) {
-    level_begin[ps] = (int)hi.size();
-    for (int j : order)
-      if (ps < hj[j].npass)
-        for (int t = 0; t < hj[j].ntiles[ps]; ++t) hi.push_back({j, ps, t, 0});
-  }
-  level_begin[maxpass] = (int)hi.size();
-  if (hi.size() > (size_t)INT32_MAX) return fail(FDWT_EINVAL, "batch too large");
   auto* b = new fdwt_batch();
   if (hipGetDevice(&b->device) != hipSuccess) {
     delete b;
@@ -217,28 +240,81 @@ int fdwt_batch_create(int n_jobs, const fdwt_batch_job* jobs, int precision, fdw
   }
   b->n_jobs = n_jobs;
   b->prec = precision;
-  b->alg_bytes = alg;
-  b->n_levels = maxpass;
-  for (int k = 0; k <= maxpass; ++k) b->level_begin[k] = level_begin[k];
-  bool ok = hipMalloc(&b->d_jobs, hj.size() * sizeof(BJob)) == hipSuccess &&
-            hipMalloc(&b->d_items, hi.size() * sizeof(BItem)) == hipSuccess;
-  ok = ok && hipMemcpy(b->d_jobs, hj.data(), hj.size() * sizeof(BJob), hipMemcpyHostToDevice) == hipSuccess &&
-       hipMemcpy(b->d_items, hi.data(), hi.size() * sizeof(BItem), hipMemcpyHostToDevice) == hipSuccess;
-  if (!ok) {
+  auto bail = [&](int code, const char* msg) {
     (void)hipGetLastError();
     fdwt_batch_free(b);
-    return fail(FDWT_ENOMEM, "batch allocation failed");
+    return fail(code, msg);
+  };
+  // Grouped jobs (by m, largest first) and generic ones.
+  std::map<int, std::vector<int>, std::greater<int>> by_m;
+  std::vector<int> generic;
+  for (int j = 0; j < n_jobs; ++j) {
+    b->alg_bytes += 8.0 * (double)(int64_t(1) << jobs[j].m);
+    if (precision == FDWT_PREC_F32 && jobs[j].m >= 7) by_m[jobs[j].m].push_back(j);
+    else generic.push_back(j);
   }
-  const size_t lds = (size_t)((1 << kBLogE) + (1 << kBLogE) / 32 + 1) * sizeof(float);
-  int per_cu = 0, cus = 0;
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void*)k_batch_fwd, kBThreads, lds) != hipSuccess ||
-      hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, b->device) != hipSuccess) {
-    (void)hipGetLastError();
-    fdwt_batch_free(b);
-    return fail(FDWT_EDEVICE, "occupancy query failed");
+  for (auto& kv : by_m) {
+    fdwt_batch::Group g;
+    g.m = kv.first;
+    g.emax = tuned_emax(kv.first);
+    g.njobs = (int)kv.second.size();
+    std::vector<void*> hin, hout;
+    for (int j : kv.second) {
+      hin.push_back((void*)jobs[j].in_dev);
+      hout.push_back((void*)jobs[j].out_dev);
+      g.in_place |= jobs[j].in_dev == jobs[j].out_dev;
+    }
+    if (hipMalloc((void**)&g.d_in, hin.size() * sizeof(void*)) != hipSuccess ||
+        hipMalloc((void**)&g.d_out, hout.size() * sizeof(void*)) != hipSuccess) {
+      b->groups.push_back(g);
+      return bail(FDWT_ENOMEM, "batch allocation failed");
+    }
+    b->groups.push_back(g);
+    if (hipMemcpy(g.d_in, hin.data(), hin.size() * sizeof(void*), hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemcpy(g.d_out, hout.data(), hout.size() * sizeof(void*), hipMemcpyHostToDevice) != hipSuccess)
+      return bail(FDWT_EDEVICE, "batch upload failed");
   }
-  for (int k = 0; k < maxpass; ++k)
-    b->grid_per_level[k] = std::max(1, std::min(level_begin[k + 1] - level_begin[k], std::max(1, per_cu) * cus));
+  if (!generic.empty()) {
+    std::vector<BJob> hj(generic.size());
+    std::vector<BItem> hi;
+    int maxpass = 0;
+    for (size_t i = 0; i < generic.size(); ++i) {
+      const fdwt_batch_job& u = jobs[generic[i]];
+      BJob& J = hj[i];
+      std::memset(&J, 0, sizeof(J));
+      if (batch_plan_job(u.m, J)) return bail(FDWT_EUNSUPPORTED, "job needs too many passes");
+      J.in = u.in_dev;
+      J.out = u.out_dev;
+      maxpass = std::max(maxpass, J.npass);
+    }
+    // Level k: every tile of pass k of every job (largest jobs first).
+    std::vector<int> order(hj.size());
+    for (size_t j = 0; j < hj.size(); ++j) order[j] = (int)j;
+    std::stable_sort(order.begin(), order.end(), [&](int x, int y) { return hj[x].m > hj[y].m; });
+    for (int ps = 0; ps < maxpass; ++ps) {
+      b->level_begin[ps] = (int)hi.size();
+      for (int j : order)
+        if (ps < hj[j].npass)
+          for (int t = 0; t < hj[j].ntiles[ps]; ++t) hi.push_back({j, ps, t, 0});
+    }
+    b->level_begin[maxpass] = (int)hi.size();
+    b->n_levels = maxpass;
+    if (hi.size() > (size_t)INT32_MAX) return bail(FDWT_EINVAL, "batch too large");
+    if (hipMalloc(&b->d_jobs, hj.size() * sizeof(BJob)) != hipSuccess ||
+        hipMalloc(&b->d_items, hi.size() * sizeof(BItem)) != hipSuccess)
+      return bail(FDWT_ENOMEM, "batch allocation failed");
+    if (hipMemcpy(b->d_jobs, hj.data(), hj.size() * sizeof(BJob), hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemcpy(b->d_items, hi.data(), hi.size() * sizeof(BItem), hipMemcpyHostToDevice) != hipSuccess)
+      return bail(FDWT_EDEVICE, "batch upload failed");
+    int per_cu = 0, cus = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void*)k_batch_fwd, kBThreads, generic_lds()) !=
+            hipSuccess ||
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, b->device) != hipSuccess)
+      return bail(FDWT_EDEVICE, "occupancy query failed");
+    for (int k = 0; k < maxpass; ++k)
+      b->grid_per_level[k] =
+          std::max(1, std::min(b->level_begin[k + 1] - b->level_begin[k], std::max(1, per_cu) * cus));
+  }
   *out = b;
   return FDWT_OK;
 }
@@ -246,15 +322,78 @@ int fdwt_batch_create(int n_jobs, const fdwt_batch_job* jobs, int precision, fdw
 int fdwt_batch_run(fdwt_batch* b, void* stream) {
   if (!b) return fail(FDWT_EINVAL, "NULL batch");
   hipStream_t st = (hipStream_t)stream;
-  const size_t lds = (size_t)((1 << kBLogE) + (1 << kBLogE) / 32 + 1) * sizeof(float);
   hipEvent_t tb = timed_begin(st);
+  for (const auto& g : b->groups)
+    if (int rc = run_group(g, st)) return rc;
   for (int k = 0; k < b->n_levels; ++k) {
     const int n = b->level_begin[k + 1] - b->level_begin[k];
-    hipLaunchKernelGGL(k_batch_fwd, dim3(b->grid_per_level[k]), dim3(kBThreads), lds, st, b->d_jobs,
+    hipLaunchKernelGGL(k_batch_fwd, dim3(b->grid_per_level[k]), dim3(kBThreads), generic_lds(), st, b->d_jobs,
                        b->d_items + b->level_begin[k], n, b->prec);
     FDWT_HIP(hipGetLastError());
   }
   timed_end(tb, st, FDWT_TC_BATCH, b->alg_bytes);
+  return FDWT_OK;
+}
+
+int fdwt_batch_autotune(fdwt_batch* b, int reps, void* stream) {
+  if (!b) return fail(FDWT_EINVAL, "NULL batch");
+  if (reps < 1 || reps > 1000) return fail(FDWT_EINVAL, "reps must be in 1..1000");
+  hipStream_t st = (hipStream_t)stream;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  FDWT_HIP(hipEventCreate(&e0));
+  FDWT_HIP(hipEventCreate(&e1));
+  int rc = FDWT_OK;
+  for (auto& g : b->groups) {
+    if (g.in_place) continue;  // timing runs would overwrite the inputs
+    std::vector<int> cands;
+    for (int e = 14; e >= 10; --e) {
+      bool dup = false;
+      for (int c : cands) dup |= p2_plans_equal(g.m, c, e);
+      if (!dup) cands.push_back(e);
+    }
+    if (cands.size() < 2) continue;
+    float best = 0.0f;
+    int best_e = g.emax;
+    for (int e : cands) {
+      fdwt_batch::Group t = g;
+      t.emax = e;
+      std::vector<float> ms;
+      rc = run_group(t, st);  // warm-up
+      for (int r = 0; r < reps && !rc; ++r) {
+        if (hipEventRecord(e0, st) != hipSuccess) rc = fail(FDWT_EDEVICE, "event record failed");
+        if (!rc) rc = run_group(t, st);
+        if (!rc && hipEventRecord(e1, st) != hipSuccess) rc = fail(FDWT_EDEVICE, "event record failed");
+        float v = 0.0f;
+        if (!rc && (hipEventSynchronize(e1) != hipSuccess || hipEventElapsedTime(&v, e0, e1) != hipSuccess))
+          rc = fail(FDWT_EDEVICE, "event timing failed");
+        ms.push_back(v);
+      }
+      if (rc) break;
+      std::nth_element(ms.begin(), ms.begin() + ms.size() / 2, ms.end());
+      const float med = ms[ms.size() / 2];
+      if (best == 0.0f || med < best) {
+        best = med;
+        best_e = e;
+      }
+    }
+    if (rc) break;
+    g.emax = best_e;
+    std::lock_guard<std::mutex> lk(g_tuned_mu);
+    g_tuned_emax[g.m] = best_e;
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  return rc;
+}
+
+int fdwt_batch_describe(const fdwt_batch* b, int cap, int* m, int* emax, int* njobs, int* n_groups) {
+  if (!b || !n_groups) return fail(FDWT_EINVAL, "NULL argument");
+  *n_groups = (int)b->groups.size();
+  for (int i = 0; i < (int)b->groups.size() && i < cap; ++i) {
+    if (m) m[i] = b->groups[i].m;
+    if (emax) emax[i] = b->groups[i].emax;
+    if (njobs) njobs[i] = b->groups[i].njobs;
+  }
   return FDWT_OK;
 }
 
@@ -266,9 +405,15 @@ int fdwt_batch_check(fdwt_batch* b, void* stream) {
 
 void fdwt_batch_free(fdwt_batch* b) {
   if (!b) return;
-  if (b->d_jobs || b->d_items) (void)hipDeviceSynchronize();
+  bool any = b->d_jobs || b->d_items;
+  for (auto& g : b->groups) any |= g.d_in || g.d_out;
+  if (any) (void)hipDeviceSynchronize();
   if (b->d_jobs) (void)hipFree(b->d_jobs);
   if (b->d_items) (void)hipFree(b->d_items);
+  for (auto& g : b->groups) {
+    if (g.d_in) (void)hipFree(g.d_in);
+    if (g.d_out) (void)hipFree(g.d_out);
+  }
   delete b;
 }
 

@@ -14,6 +14,7 @@
 #include "pass_core.h"
 
 #include <algorithm>
+#include <cmath>
 #include <map>
 #include <type_traits>
 #include <mutex>
@@ -265,7 +266,8 @@ __global__ void __launch_bounds__((P2Shape<LOGE, WDIG>::THREADS))
   auto prefetch = [&](int l) {
     int col, tile;
     locate(l, col, tile);
-    const Tin* src = in + (int64_t)col * d.col_in + tile_base(tile) + goff0;
+    const Tin* colp = d.in_tab ? (const Tin*)d.in_tab[col] : in + (int64_t)col * d.col_in;
+    const Tin* src = colp + tile_base(tile) + goff0;
 #pragma unroll
     for (int k = 0; k < EPT; ++k) pre[k] = src[k * gstep];
   };
@@ -306,7 +308,7 @@ __global__ void __launch_bounds__((P2Shape<LOGE, WDIG>::THREADS))
       for (int k = 0; k < EPT; ++k) v[k] = lrowS[66 * k];
       reg_bfly<NS>(v);
       if constexpr (EPI == EPI_STORE) {
-        Tout* dst = out + (int64_t)col * d.col_out + base + goffS;
+        Tout* dst = (d.out_tab ? (Tout*)d.out_tab[col] : out + (int64_t)col * d.col_out) + base + goffS;
 #pragma unroll
         for (int k = 0; k < EPT; ++k) dst[k * gstepS] = cvt_out<T, Tout>(v[k], d.scale, d.scale64);
       } else {
@@ -350,7 +352,7 @@ __global__ void __launch_bounds__((P2Shape<LOGE, WDIG>::THREADS))
     // butterflies: 2-digit register groups keep it within 128 registers.
     P2Groups<LOGE, WDIG, 0, T, (EPI == EPI_REDUCE && sizeof(T) >= 8) ? 2 : 4>::run(lds, tid);
     if constexpr (EPI == EPI_STORE) {
-      Tout* dst = out + (int64_t)col * d.col_out + base + goff0;
+      Tout* dst = (d.out_tab ? (Tout*)d.out_tab[col] : out + (int64_t)col * d.col_out) + base + goff0;
 #pragma unroll
       for (int k = 0; k < EPT; ++k) dst[k * gstep] = cvt_out<T, Tout>(lrow[cpad(k * TH)], d.scale, d.scale64);
     } else {
@@ -580,8 +582,7 @@ struct P2Pass {
 // line with another tile, so the float64 passes, whose tiles of one column
 // are not neighbours in time, do not fetch lines twice), split evenly
 // (>= 2^7 elements per tile).
-static std::vector<P2Pass> plan_p2(int m, size_t bytes) {
-  const int emax = (bytes >= 8 && lds_budget(bytes) < 136 * 1024) ? 13 : 14;
+static std::vector<P2Pass> plan_p2_e(int m, int emax) {
   const int wd = 4;
   std::vector<P2Pass> out;
   if (m <= emax) {
@@ -596,6 +597,10 @@ static std::vector<P2Pass> plan_p2(int m, size_t bytes) {
   out.push_back({0, first, 0});
   for (int i = 0; i < nstr; ++i) out.push_back({first + i * rd, rd + wd, wd});
   return out;
+}
+
+static std::vector<P2Pass> plan_p2(int m, size_t bytes) {
+  return plan_p2_e(m, (bytes >= 8 && lds_budget(bytes) < 136 * 1024) ? 13 : 14);
 }
 
 template <class Tin, class T, class Tout, int WDIG, int EPI>
@@ -629,7 +634,8 @@ static int occupancy(const void* fn, int threads, size_t lds) {
 
 template <class Tin, class T, class Tout>
 static int launch_p2(const void* in, void* out, const P2Pass& g, int m, int batch, double scale,
-                     const ReduceArgs* red, hipStream_t st) {
+                     const ReduceArgs* red, hipStream_t st, const void* const* in_tab = nullptr,
+                     void* const* out_tab = nullptr) {
   constexpr bool wide = sizeof(T) >= 8;
   const void* fn = nullptr;
   if (red) {
@@ -665,6 +671,8 @@ static int launch_p2(const void* in, void* out, const P2Pass& g, int m, int batc
   } else {
     d.h0_col = -1;
   }
+  d.in_tab = in_tab;
+  d.out_tab = out_tab;
   const size_t lds = ((size_t)cpad(E) * sizeof(T) + 15) / 16 * 16 + 16 * sizeof(double);
   if (int rc = allow_lds(fn, lds)) return rc;
   int64_t G = (int64_t)occupancy(fn, threads, lds) * device_cus();
@@ -758,6 +766,31 @@ int fwt_reduce_f64(int p, int m, const double* in, void* tmp, int batch, const f
   ReduceArgs red{wts, partial, h0_out, h0_col};
   const Kind wk = p == 2 ? K_F64 : K_CF64;
   return run_passes(p, m, false, K_F64, in, wk, wk, tmp, tmp, batch, 1.0f, &red, tiles, st);
+}
+
+// Plans of p = 2 float transforms for the batch tuner: the first pass takes
+// up to 2^emax elements (emax in 7..14), then strided passes of rows of 16.
+int p2_plan_passes(int m, int emax) { return (int)plan_p2_e(m, emax).size(); }
+// Plans for two values of emax are the same pass list.
+bool p2_plans_equal(int m, int e1, int e2) {
+  const std::vector<P2Pass> a = plan_p2_e(m, e1), b = plan_p2_e(m, e2);
+  if (a.size() != b.size()) return false;
+  for (size_t i = 0; i < a.size(); ++i)
+    if (a[i].d0 != b[i].d0 || a[i].loge != b[i].loge || a[i].wdig != b[i].wdig) return false;
+  return true;
+}
+
+// Pass `level` of the plan (m, emax) for a group of njobs float jobs of 2^m
+// points each: column c reads in_tab[c] (level 0) or out_tab[c] and writes
+// out_tab[c]; the last pass scales by 2^-m (Eq. (eq_dwalshcoeff)).
+int fwt_p2_group_pass(int m, int emax, int level, const void* const* in_tab, void* const* out_tab, int njobs,
+                      hipStream_t st) {
+  const std::vector<P2Pass> passes = plan_p2_e(m, emax);
+  if (level < 0 || level >= (int)passes.size()) return fail(FDWT_EINVAL, "no such pass");
+  const bool last = level + 1 == (int)passes.size();
+  const double scale = last ? std::ldexp(1.0, -m) : 1.0;
+  const void* const* src = level == 0 ? in_tab : (const void* const*)out_tab;
+  return launch_p2<float, float, float>(nullptr, nullptr, passes[level], m, njobs, scale, nullptr, st, src, out_tab);
 }
 
 int64_t fwt_reduce_tiles(int p, int m, size_t elem_bytes) {

@@ -31,6 +31,11 @@ struct PassDesc {
   double* partial;
   double* h0_out;
   int32_t h0_col;
+  // Column pointer tables (store passes of static p = 2 shapes): when set,
+  // column c reads in_tab[c] and writes out_tab[c] instead of in/out plus
+  // c times the column stride (a group of equal-size jobs anywhere in memory).
+  const void* const* in_tab;
+  void* const* out_tab;
 };
 
 enum Epilogue { EPI_STORE = 0, EPI_REDUCE = 1 };

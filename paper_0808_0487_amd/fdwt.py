@@ -74,6 +74,8 @@ SIGNATURES = {
     "fdwt_batch_create": (_i, [_i, _vp, _i, ctypes.POINTER(_vp)]),
     "fdwt_batch_run": (_i, [_vp, _vp]),
     "fdwt_batch_check": (_i, [_vp, _vp]),
+    "fdwt_batch_autotune": (_i, [_vp, _i, _vp]),
+    "fdwt_batch_describe": (_i, [_vp, _i, _vp, _vp, _vp, ctypes.POINTER(_i)]),
     "fdwt_batch_free": (None, [_vp]),
     "fdwt_server_request_bytes": (_i, [ctypes.POINTER(RequestC), ctypes.c_size_t,
                                        ctypes.POINTER(ctypes.c_size_t), ctypes.POINTER(ctypes.c_size_t)]),
@@ -143,13 +145,13 @@ class BatchJobC(ctypes.Structure):
     _fields_ = [("m", ctypes.c_int), ("in_dev", ctypes.c_void_p), ("out_dev", ctypes.c_void_p)]
 
 
-PREC = {"f32": 0, "bf16x2": 1}
+PREC = {"f32": 0, "bf16x2": 1, "f32_generic": 2}
 
 
 class Batch:
-    """A ragged batch of p = 2 forward transforms (fdwt_batch_*): one
-    persistent launch per pass level over all jobs' tiles.
-    jobs: list of (m, in_tensor, out_tensor)."""
+    """A ragged batch of p = 2 forward transforms (fdwt_batch_*).
+    jobs: list of (m, in_tensor, out_tensor); precision 'f32' (grouped static
+    passes), 'f32_generic' or 'bf16x2' (persistent launch per pass level)."""
 
     def __init__(self, jobs, precision="f32"):
         arr = (BatchJobC * len(jobs))()
@@ -167,6 +169,18 @@ class Batch:
 
     def check(self, stream=None):
         _check(lib().fdwt_batch_check(self.h, _stream(stream)))
+
+    def autotune(self, reps=5, stream=None):
+        _check(lib().fdwt_batch_autotune(self.h, reps, _stream(stream)))
+
+    def describe(self):
+        """[(m, emax, jobs)] of the grouped path."""
+        n = ctypes.c_int()
+        _check(lib().fdwt_batch_describe(self.h, 0, None, None, None, ctypes.byref(n)))
+        m, e, j = (np.zeros(max(n.value, 1), dtype=np.int32) for _ in range(3))
+        _check(lib().fdwt_batch_describe(self.h, n.value, m.ctypes.data, e.ctypes.data, j.ctypes.data,
+                                         ctypes.byref(n)))
+        return [(int(m[i]), int(e[i]), int(j[i])) for i in range(n.value)]
 
     def close(self):
         if self.h:

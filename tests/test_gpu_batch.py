@@ -1,5 +1,6 @@
-"""Ragged batches of p = 2 transforms (one persistent launch per pass level),
-against the oracle, alone vs in the mix, and under HIP-graph capture."""
+"""Ragged batches of p = 2 transforms (grouped static passes, and the generic
+persistent launch per pass level with float32 or bfloat16-split low stages),
+against the oracle, alone vs in the mix, tuned, and under HIP-graph capture."""
 import numpy as np
 import pytest
 import torch
@@ -27,10 +28,10 @@ def check_against_oracle(jobs, tol, seed):
         assert err <= tol, (i, m, err)
 
 
-MS = [7, 9, 12, 13, 14, 15, 17, 20, 22, 8, 16, 19, 21, 13, 10]
+MS = [7, 9, 12, 13, 14, 15, 17, 20, 22, 8, 16, 19, 21, 13, 10, 3, 1, 6, 23]
 
 
-@pytest.mark.parametrize("prec,tol", [("f32", 1e-5), ("bf16x2", 2e-5)])
+@pytest.mark.parametrize("prec,tol", [("f32", 1e-5), ("f32_generic", 1e-5), ("bf16x2", 2e-5)])
 def test_ragged_batch_against_oracle(prec, tol):
     announce("batch", prec)
     jobs = make_jobs(MS, 500)
@@ -107,6 +108,26 @@ def test_graph_capture_replays_match_eager():
         for e, (_, _, y) in zip(eager, jobs):
             assert torch.equal(e, y), rep
     b.check()
+
+
+def test_autotune_keeps_results_exact():
+    """The tuner times every distinct plan per group and keeps one; results
+    after tuning still match the oracle, and the chosen plans are reported."""
+    announce("batch autotune")
+    ms = [12, 12, 15, 18, 18, 21, 22]
+    jobs = make_jobs(ms, 800)
+    b = fdwt.Batch(jobs, "f32")
+    b.autotune(reps=3)
+    for _, _, y in jobs:
+        y.fill_(0.0)
+    b.run()
+    b.check()
+    check_against_oracle(jobs, 1e-5, 800)
+    groups = b.describe()
+    assert sorted(g[0] for g in groups) == sorted(set(ms))
+    assert all(10 <= g[1] <= 14 for g in groups)
+    assert sum(g[2] for g in groups) == len(ms)
+    b.close()
 
 
 def test_batch_rejects_bad_jobs():
