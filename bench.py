@@ -49,6 +49,7 @@ def parse():
     ap.add_argument("--no-batch", action="store_true", help="skip the ragged-batch leg")
     ap.add_argument("--batch-jobs", type=int, default=512)
     ap.add_argument("--no-serve", action="store_true", help="skip the serving leg")
+    ap.add_argument("--no-interp", action="store_true", help="skip the p = 3 interpolation leg")
     ap.add_argument("--serve-window", type=float, default=0.2,
                     help="seconds of Poisson arrivals (at --serve-rate) replayed in the serving leg")
     ap.add_argument("--serve-rate", type=float, default=200.0)
@@ -61,7 +62,7 @@ def parse():
 
 def kernel_source_hash():
     h = hashlib.sha256()
-    for f in ["fwt.hip", "dev_math.h", "spline.hip"]:
+    for f in ["fwt.hip", "pass_core.h", "dev_math.h", "coords.h", "spline.hip"]:
         with open(os.path.join(ROOT, "paper_0808_0487_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
@@ -192,6 +193,47 @@ def batched_leg(torch, fdwt, inputs, n_jobs, reps=5):
             "tuned_plans_m_emax_jobs": plans, "autotune_s": t_tune,
             "batch_f32_graph": {"ms": t_graph, "points_per_s": total / (t_graph * 1e-3)},
             "speedup_batch_vs_plain": t_plain / t32}
+
+
+def interp_leg(torch, fdwt, inputs, reps=3):
+    """Prime base: p = 3, m = 14 (4,782,969 points), s = 10, seeded upper-
+    triangular generators, f = prod_j (1 + (x_j - 1/2)/j^2); complex float32
+    forward and inverse transforms, then the interpolant at 65536 uniform
+    random 20-digit query points.  Kernel alpha = 2, gamma_j = j^-2."""
+    p, m, s, nq = 3, 14, 10, 65536
+    C = inputs.upper_triangular_generators(p, m, s, seed=3)
+    net = fdwt.Net(p, m, s, C)
+    kern = fdwt.Kernel(2.0, inputs.kernel_weights(s))
+    a = inputs.family_params("product", s, alpha=2.0)
+    q = torch.from_numpy(inputs.queries(p, s, nq, 3).view(np.int32)).cuda()
+    stream = torch.cuda.current_stream()
+    f = net.sample("product", a)
+    ft = net.forward(f)
+    back = net.inverse(ft, real=True)
+    c, sf = net.walsh_interp(kern, f, q)
+    torch.cuda.synchronize()
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(4)]
+    t_fi, t_all = [], []
+    fdwt.timing_enable(True)
+    for _ in range(reps):
+        ev[0].record(stream)
+        net.forward(f, out=ft)
+        net.inverse(ft, out=back, real=True)
+        ev[1].record(stream)
+        net.walsh_interp(kern, f, q)
+        ev[2].record(stream)
+        torch.cuda.synchronize()
+        t_fi.append(ev[0].elapsed_time(ev[1]))
+        t_all.append(ev[1].elapsed_time(ev[2]))
+    tot, n, work = fdwt.timing_query("eval")
+    fdwt.timing_enable(False)
+    N = p ** m
+    err = float(torch.linalg.norm(back - f) / torch.linalg.norm(f))
+    net.close()
+    return {"workload": "p=3 m=14 (N=%d) s=10, product family a_j=j^-2, 65536 queries of 20 base-3 digits" % N,
+            "forward_inverse_ms": float(np.median(t_fi)), "points_per_s_fwd_inv": N / (np.median(t_fi) * 1e-3),
+            "interp_ms": float(np.median(t_all)), "eval_ms": tot / n,
+            "eval_coordinates_per_s": work / (tot * 1e-3), "round_trip_rel_err": err}
 
 
 def serving_leg(fdwt, inputs, window, rate, budget_gb, lanes):
@@ -358,6 +400,8 @@ def main():
     }
     if not args.no_batch:
         out["batched"] = batched_leg(torch, fdwt, inputs, args.batch_jobs)
+    if not args.no_interp:
+        out["interp_p3"] = interp_leg(torch, fdwt, inputs)
     torch.cuda.empty_cache()
     if not args.no_serve:
         out["serving"] = serving_leg(fdwt, inputs, args.serve_window, args.serve_rate, args.serve_budget_gb,
