@@ -108,6 +108,14 @@ int fdwt_sample(const fdwt_net* net, int family, const double* a_host, float* f_
 int fdwt_dwt_forward(const fdwt_net* net, int in_type, const void* in_dev,
                      int out_type, void* out_dev, void* stream);
 
+/* Forward transform of a test function sampled at the net on the device:
+ * fdwt_sample(family, a_host) followed by fdwt_dwt_forward (two launches;
+ * the samples never leave the device).  out_type is F32 (p = 2) or CF32
+ * (p odd); out_dev holds N elements of it.  p odd uses the net's workspace
+ * for the samples. */
+int fdwt_dwt_forward_family(const fdwt_net* net, int family, const double* a_host, int out_type,
+                            void* out_dev, void* stream);
+
 /* Inverse transform, Algorithm 2 (Section 3.3), the Lemma's sum:
  *     out[n] = sum_h in[h] omega_p^(+n_vec . h_vec)   (no normalisation).
  * Allowed: p = 2: F32 -> F32, I32 -> I32 (mod 2^32), F64 -> F64; p odd:

@@ -438,6 +438,33 @@ int fdwt_dwt_forward(const fdwt_net* h, int in_type, const void* in_dev, int out
   FDWT_GUARD_END
 }
 
+int fdwt_dwt_forward_family(const fdwt_net* h, int family, const double* a_host, int out_type, void* out_dev,
+                            void* stream) {
+  FDWT_GUARD_BEGIN
+  if (int rc = check_net(h)) return rc;
+  if (!a_host || !out_dev) return fail(FDWT_EINVAL, "NULL argument");
+  if (family != FDWT_FAMILY_PRODUCT && family != FDWT_FAMILY_EXP && family != FDWT_FAMILY_WANGFANG)
+    return fail(FDWT_EINVAL, "unknown family");
+  for (int j = 0; j < h->n.s; ++j)
+    if (!std::isfinite(a_host[j]) || (family == FDWT_FAMILY_WANGFANG && a_host[j] <= -1.0))
+      return fail(FDWT_EINVAL, "family parameter out of range");
+  Net& net = const_cast<Net&>(h->n);
+  if (out_type != (net.p == 2 ? FDWT_F32 : FDWT_CF32))
+    return fail(FDWT_EINVAL, "coefficients are F32 (p = 2) or CF32 (p odd)");
+  DeviceGuard g(net.device);
+  hipStream_t st = (hipStream_t)stream;
+  // p = 2 samples into the output and transforms in place; p odd samples
+  // into the workspace (the complex output is twice as wide).
+  float* f = (float*)out_dev;
+  if (net.p != 2) {
+    if (int rc = ensure_ws(net.sc, (size_t)net.N * sizeof(float), st)) return rc;
+    f = (float*)net.sc.ws;
+  }
+  if (int rc = launch_sample(net, family, a_host, f, st)) return rc;
+  return transform(net, false, FDWT_F32, f, out_type, out_dev, st);
+  FDWT_GUARD_END
+}
+
 int fdwt_dwt_inverse(const fdwt_net* h, int in_type, const void* in_dev, int out_type, void* out_dev,
                      void* stream) {
   FDWT_GUARD_BEGIN

@@ -66,6 +66,7 @@ SIGNATURES = {
     "fdwt_sample": (_i, [_vp, _i, _vp, _vp, _vp]),
     "fdwt_dwt_forward": (_i, [_vp, _i, _vp, _i, _vp, _vp]),
     "fdwt_dwt_inverse": (_i, [_vp, _i, _vp, _i, _vp, _vp]),
+    "fdwt_dwt_forward_family": (_i, [_vp, _i, _vp, _i, _vp, _vp]),
     "fdwt_query_depth": (_i, [_i]),
     "fdwt_spline_coef": (_i, [_vp, ctypes.POINTER(KernelC), _i, _vp, _vp, _vp]),
     "fdwt_spline_eval": (_i, [_vp, ctypes.POINTER(KernelC), _vp, _i64, _vp, _vp, _vp]),
@@ -276,6 +277,16 @@ class Net:
                 dt = torch.float32 if self.p == 2 else torch.complex64
             out = torch.empty(self.N, dtype=dt, device=x.device)
         _check(lib().fdwt_dwt_forward(self.h, _type_of(x), _ptr(x), _type_of(out), _ptr(out), _stream(stream)))
+        return out
+
+    def forward_family(self, family, a, out=None, stream=None):
+        """dwt_forward of f sampled on the device (fdwt_dwt_forward_family)."""
+        import torch
+        a = np.ascontiguousarray(a, dtype=np.float64)
+        if out is None:
+            out = torch.empty(self.N, dtype=torch.float32 if self.p == 2 else torch.complex64, device="cuda")
+        _check(lib().fdwt_dwt_forward_family(self.h, FAMILY[family], a.ctypes.data_as(ctypes.c_void_p),
+                                             _type_of(out), _ptr(out), _stream(stream)))
         return out
 
     def inverse(self, x, out=None, real=False, stream=None):

@@ -4,7 +4,7 @@ import numpy as np
 import pytest
 import torch
 
-from oracle import families, net as onet
+from oracle import families, net as onet, walsh
 from paper_0808_0487_amd import fdwt, inputs
 from tests.gpu_common import announce, nrel, sample_indices
 
@@ -83,3 +83,23 @@ def test_sample_full_size_exp_family_sampled():
     got = f[torch.from_numpy(idx).cuda()].cpu().numpy().astype(np.float64)
     fo = families.exponential(onet.net_points(p, m, C, idx), a)
     assert np.max(np.abs(got - fo) / np.abs(fo)) <= 1e-6
+
+
+@pytest.mark.parametrize("p,m,s,family", [(2, 12, 5, "exp"), (2, 18, 8, "product"), (3, 8, 4, "wangfang"),
+                                          (5, 6, 3, "product")])
+def test_forward_of_sampled_family_equals_two_calls(p, m, s, family):
+    """fdwt_dwt_forward_family equals fdwt_sample then fdwt_dwt_forward bit
+    for bit, and the oracle's transform of the oracle's samples to 1e-5."""
+    announce("forward family", p, m, s, family)
+    C = inputs.upper_triangular_generators(p, m, s, 21)
+    a = inputs.family_params(family, s, seed=4) if family != "wangfang" else inputs.family_params(family, s, a="k")
+    net = fdwt.Net(p, m, s, C)
+    fused = net.forward_family(family, a).cpu().numpy()
+    two = net.forward(net.sample(family, a)).cpu().numpy()
+    assert np.array_equal(fused, two)
+    fo = {"exp": families.exponential, "product": families.product, "wangfang": families.wangfang}[family](
+        onet.net_points(p, m, C), a)
+    hs = sample_indices(p ** m, 200, m)
+    ref = walsh.dwt_phase(p, m, fo, hs)
+    got = fused[hs]
+    assert nrel(got, ref.real if p == 2 else ref) <= 1e-5
