@@ -202,46 +202,52 @@ __global__ void __launch_bounds__(256) k_query_prep(const uint32_t* __restrict__
   }
 }
 
-// Lane holding the kernel factor for the XOR z of a query and a point
-// coordinate.  p = 2: the first differing bit t is the leading-zero count,
-// and z = 0 (v_ffbh_u32 returns all ones) lands in lane 63.  p odd: the
-// leading-zero count of the digit strings is 3t + 1..3t + 3, or 64 (lane 0)
-// when all digits agree.  The per-lane tables are laid out to match.
-template <int P>
-__device__ __forceinline__ int factor_lane_addr(typename std::conditional<P == 2, uint32_t, uint64_t>::type z) {
-  if constexpr (P == 2) {
-    int c;
-    asm("v_ffbh_u32 %0, %1" : "=v"(c) : "v"(z));
-    return c << 2;
-  } else {
-    return __clzll(z) << 2;
-  }
+// Leading-zero count with all ones for a zero argument (v_ffbh_u32).
+__device__ __forceinline__ int ffbh_raw(uint32_t z) {
+  int c;
+  asm("v_ffbh_u32 %0, %1" : "=v"(c) : "v"(z));
+  return c;
 }
 
 // Sf at queries as partial sums over point chunks (blockIdx.y): each thread
 // takes one query; the points of a chunk are staged in LDS kNS at a time and
-// read as 16-byte broadcasts; the factor 1 + gamma_j K'(.) of coordinate j
-// comes from a table spread over the lanes of the wave (tlane[j][lane], in
-// registers) through ds_bpermute, which has no bank conflicts.
+// read as 16-byte broadcasts (4 points); the factor 1 + gamma_j K'(.) of
+// coordinate j comes from a table spread over the lanes of the wave
+// (tlane[j][lane], in registers) through ds_bpermute, which has no bank
+// conflicts.  The table lane is the leading-zero count of the XOR of the
+// query's and the point's digit strings:
+//   p = 2: the first differing bit t (all equal: v_ffbh_u32 gives all ones,
+//          lane 63);
+//   p odd: 3t + 1..3t + 3 for first differing digit t, 64 (lane 0) when all
+//          D digits agree.  The count is taken from the high 32 bits of the
+//          strings; only when those agree (digits 0..9 equal, rare) does the
+//          lane compute it from the low word.
 template <int P, int SMAX>
 __global__ void __launch_bounds__(256) k_spline_eval(const void* __restrict__ Xp, const float* __restrict__ c,
                                                      int64_t N, int s, const void* __restrict__ qv, int64_t nq,
                                                      const float* __restrict__ tlane, int64_t ppc,
                                                      df* __restrict__ partial) {
-  using XT = typename std::conditional<P == 2, uint32_t, uint64_t>::type;
-  constexpr int V = 16 / sizeof(XT);  // points per LDS read
+  constexpr bool ODD = P != 2;
+  constexpr int V = 4;  // points per LDS read
   extern __shared__ __align__(16) unsigned char smem[];
-  XT* lx = reinterpret_cast<XT*>(smem);                                       // [s][kNS]
-  float* lc = reinterpret_cast<float*>(smem + (size_t)s * kNS * sizeof(XT));  // [kNS]
+  uint32_t* lxh = reinterpret_cast<uint32_t*>(smem);                     // [s][kNS] (p odd: high words)
+  uint32_t* lxl = lxh + (size_t)s * kNS;                                  // [s][kNS] p odd: low words
+  float* lc = reinterpret_cast<float*>(lxh + (size_t)(ODD ? 2 : 1) * s * kNS);  // [kNS]
   const int lane = threadIdx.x & 63;
   const int64_t qi = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const int64_t qq = qi < nq ? qi : nq - 1;
-  XT qr[SMAX];
+  // Query high words and table entries stay in registers; the low words
+  // (needed only on the rare path) are read from memory there.
+  uint32_t qh[SMAX];
   int tj[SMAX];
 #pragma unroll
   for (int j = 0; j < SMAX; ++j) {
     if (j < s) {
-      qr[j] = ((const XT*)qv)[(int64_t)j * nq + qq];
+      if constexpr (ODD) {
+        qh[j] = (uint32_t)(((const uint64_t*)qv)[(int64_t)j * nq + qq] >> 32);
+      } else {
+        qh[j] = ((const uint32_t*)qv)[(int64_t)j * nq + qq];
+      }
       tj[j] = __float_as_int(tlane[j * 64 + lane]);
     }
   }
@@ -253,7 +259,13 @@ __global__ void __launch_bounds__(256) k_spline_eval(const void* __restrict__ Xp
     for (int i = threadIdx.x; i < s * kNS; i += blockDim.x) {
       const int j = i / kNS, k = i % kNS;
       const int64_t n = n0 + k;
-      lx[i] = n < nend ? ((const XT*)Xp)[(int64_t)j * N + n] : (XT)0;
+      if constexpr (ODD) {
+        const uint64_t v = n < nend ? ((const uint64_t*)Xp)[(int64_t)j * N + n] : 0ull;
+        lxh[i] = (uint32_t)(v >> 32);
+        lxl[i] = (uint32_t)v;
+      } else {
+        lxh[i] = n < nend ? ((const uint32_t*)Xp)[(int64_t)j * N + n] : 0u;
+      }
     }
     for (int k = threadIdx.x; k < kNS; k += blockDim.x) lc[k] = (n0 + k < nend) ? c[n0 + k] : 0.0f;
     __syncthreads();
@@ -265,12 +277,24 @@ __global__ void __launch_bounds__(256) k_spline_eval(const void* __restrict__ Xp
 #pragma unroll
       for (int j = 0; j < SMAX; ++j) {
         if (j < s) {
-          XT xv[V];
-          *reinterpret_cast<uint4*>(xv) = *reinterpret_cast<const uint4*>(lx + j * kNS + k);
+          const uint4 xv = *reinterpret_cast<const uint4*>(lxh + j * kNS + k);
+          const uint32_t xs[V] = {xv.x, xv.y, xv.z, xv.w};
 #pragma unroll
           for (int u = 0; u < V; ++u) {
-            const int a = factor_lane_addr<P>(qr[j] ^ xv[u]);
-            pr[u] *= __int_as_float(__builtin_amdgcn_ds_bpermute(a, tj[j]));
+            const uint32_t zh = qh[j] ^ xs[u];
+            int cl = ffbh_raw(zh);
+            if constexpr (ODD) {
+              if (zh == 0u) {
+                // The empty asm keeps this load on the rare path (hoisting it
+                // out of the loop would cost a register pair per coordinate).
+                int64_t qo = qq;
+                asm volatile("" : "+v"(qo));
+                const uint32_t qlo = (uint32_t)((const uint64_t*)qv + (int64_t)j * nq)[qo];
+                const uint32_t zl = qlo ^ lxl[j * kNS + k + u];
+                cl = zl ? 32 + ffbh_raw(zl) : 64;
+              }
+            }
+            pr[u] *= __int_as_float(__builtin_amdgcn_ds_bpermute(cl << 2, tj[j]));
           }
         }
       }
@@ -535,7 +559,7 @@ int run_spline_eval(Net& net, Scratch& sc, const fdwt_kernel* kern, const void* 
   EvalWs w;
   eval_layout(net, nq, packed != nullptr, cv, w);
   // Factor 1 + gamma_j K'(t+1) of first differing digit t < D, and 1 + gamma_j
-  // when all D digits agree, placed in the lane factor_lane_addr selects.
+  // when all D digits agree, placed in the lanes k_spline_eval selects.
   std::vector<float> htl((size_t)s * 64, 1.0f);
   for (int j = 0; j < s; ++j) {
     float* row = htl.data() + (size_t)j * 64;
@@ -562,7 +586,7 @@ int run_spline_eval(Net& net, Scratch& sc, const fdwt_kernel* kern, const void* 
     FDWT_HIP(hipGetLastError());
     qv = w.qs;
   }
-  const size_t lds = (size_t)s * kNS * xb + kNS * 4;
+  const size_t lds = (size_t)s * kNS * xb + kNS * 4;  // p odd: high and low words of the strings
   hipEvent_t tb = timed_begin(st);
   if (p == 2) rc = launch_eval<2>(net, Xp, c, nq, qv, w.tl, w.partial, gy, ppc, lds, st);
   else if (p == 3) rc = launch_eval<3>(net, Xp, c, nq, qv, w.tl, w.partial, gy, ppc, lds, st);
