@@ -60,9 +60,21 @@ def parse():
     return ap.parse_args()
 
 
-def kernel_source_hash():
+# Source files of each kernel class (a class's committed traffic figure is
+# valid only while these files are unchanged).
+CLASS_SOURCES = {
+    "pass_f32": ["fwt.hip", "pass_core.h", "dev_math.h"],
+    "pass_cf32": ["fwt.hip", "pass_core.h", "dev_math.h"],
+    "pass_f64": ["fwt.hip", "pass_core.h", "dev_math.h"],
+    "kcols": ["spline.hip", "coords.h", "dev_math.h"],
+    "eval": ["spline.hip", "coords.h", "dev_math.h"],
+    "sample": ["net.hip", "coords.h", "dev_math.h"],
+}
+
+
+def kernel_source_hash(cls="pass_f64"):
     h = hashlib.sha256()
-    for f in ["fwt.hip", "pass_core.h", "dev_math.h", "coords.h", "spline.hip"]:
+    for f in CLASS_SOURCES.get(cls, CLASS_SOURCES["pass_f64"]):
         with open(os.path.join(ROOT, "paper_0808_0487_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
@@ -70,12 +82,12 @@ def kernel_source_hash():
 
 def committed_traffic(cls):
     """HBM bytes per launch of `cls` from the committed counter summary, or
-    None when absent or taken on different kernel sources."""
+    None when absent or taken on different sources of that class."""
     if not os.path.exists(TRAFFIC_FILE):
         return None
     text = open(TRAFFIC_FILE).read()
-    m = re.search(r"source_hash:\s*(\w+)", text)
-    if not m or m.group(1) != kernel_source_hash():
+    m = re.search(r"source_hash\[%s\]:\s*(\w+)" % cls, text)
+    if not m or m.group(1) != kernel_source_hash(cls):
         return None
     m = re.search(r"traffic_bytes_per_launch\[%s\]:\s*([0-9.eE+]+)" % cls, text)
     return float(m.group(1)) if m else None
@@ -417,7 +429,7 @@ def main():
                               "alg_GBs": fwd_alg, "frac_hbm_peak": fwd_alg / HBM_PEAK_GBS,
                               "pass_launches": fn / 30.0},
         "eff_dim": {"d_trc": res["d_trc"], "d_sup": res["d_sup"], "var_total": res["var_total"]},
-        "kernel_source_hash": kernel_source_hash(),
+        "kernel_source_hash": kernel_source_hash(dom),
         "wall_s": wall,
     }
     if not args.no_batch:
