@@ -386,14 +386,45 @@ def main():
     achieved = dc["work_per_launch"] / (dc["avg_launch_ms"] * 1e-3) / 1e9
     traffic = committed_traffic(dom)
 
-    # Plain forward float32 transform on its own (the two pass launches).
+    # Plain forward float32 transform on its own (the two pass launches):
+    # HIP events around each call, median of 50 after 10 warm-up calls, warm
+    # (back to back) and with a cold last-level cache (MALL, 256 MB: a 1 GiB
+    # buffer is written before each timed call).
+    def median_ms(flush):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        out_ms = []
+        for i in range(60):
+            if flush is not None:
+                flush.fill_(float(i))
+            e0.record(stream)
+            net.forward(f, out=ft)
+            e1.record(stream)
+            torch.cuda.synchronize()
+            if i >= 10:
+                out_ms.append(e0.elapsed_time(e1))
+        return float(np.median(out_ms))
+    fwd_ms = median_ms(None)
+    flush = torch.empty(1 << 28, dtype=torch.float32, device="cuda")
+    fwd_cold_ms = median_ms(flush)
+    # Device copy reference: 256 MiB each way.
+    csrc = torch.empty(1 << 26, dtype=torch.float32, device="cuda")
+    cdst = torch.empty_like(csrc)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    cms = []
+    for i in range(15):
+        e0.record(stream)
+        cdst.copy_(csrc)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        if i >= 5:
+            cms.append(e0.elapsed_time(e1))
+    copy_GBs = 2.0 * csrc.numel() * 4 / (float(np.median(cms)) * 1e-3) / 1e9
+    del flush, csrc, cdst
     fdwt.timing_enable(True)
-    for _ in range(30):
-        net.forward(f, out=ft)
+    net.forward(f, out=ft)
     torch.cuda.synchronize()
-    ftot, fn, fwork = fdwt.timing_query("pass_f32")
+    _, fn, _ = fdwt.timing_query("pass_f32")
     fdwt.timing_enable(False)
-    fwd_ms = ftot / 30.0
     fwd_alg = 8.0 * N / (fwd_ms * 1e-3) / 1e9
 
     if args.calib_copy:
@@ -427,7 +458,10 @@ def main():
         "classes": classes,
         "plain_forward_f32": {"ms": fwd_ms, "points_per_s": N / (fwd_ms * 1e-3),
                               "alg_GBs": fwd_alg, "frac_hbm_peak": fwd_alg / HBM_PEAK_GBS,
-                              "pass_launches": fn / 30.0},
+                              "pass_launches": fn, "moved_GBs": 8.0 * fn * N / (fwd_ms * 1e-3) / 1e9,
+                              "cold_mall_ms": fwd_cold_ms, "cold_mall_alg_GBs": 8.0 * N / (fwd_cold_ms * 1e-3) / 1e9,
+                              "timing": "HIP events per call, median of 50 after 10 warm-up calls"},
+        "device_copy_GBs": copy_GBs,
         "eff_dim": {"d_trc": res["d_trc"], "d_sup": res["d_sup"], "var_total": res["var_total"]},
         "kernel_source_hash": kernel_source_hash(dom),
         "wall_s": wall,
