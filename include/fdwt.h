@@ -194,6 +194,34 @@ typedef struct {
 int fdwt_eff_dim(const fdwt_net* net, const fdwt_kernel* kern, int ft_type,
                  const void* ft_dev, fdwt_effdim* out, void* stream);
 
+/* ------------------------------------------- kernel-parameter selection */
+
+/* Section 5.1, p = 2.  `net` has m + 1 digits (2N points) and its first N
+ * points must form an m-digit net (true when every C_j is upper
+ * triangular; otherwise FDWT_EINVAL); f2_dev holds f at all 2N points
+ * (float [2N], index order).  The spline with kernel (alpha, gamma_j =
+ * beta j^q) is fitted to the first half and the cost is
+ *     sum over n = N..2N-1 of (f(x_n) - Sf(x_n))^2
+ * (every point of the second half), computed with Walsh transforms: the
+ * second half is the first half shifted by x_N, so Sf there is a group
+ * convolution of the spline coefficients with K(. (+) x_N, 0).
+ * fdwt_split_cost returns the cost (and, if sf_dev is not NULL, Sf at the
+ * second half, float [N]); fdwt_kernel_tune minimises it by the Nelder-Mead
+ * simplex method in (log(alpha - 1), log beta, q) from start = {alpha, beta,
+ * q} with at most max_evals cost evaluations.  Both synchronise `stream`;
+ * p odd gives FDWT_EUNSUPPORTED.  Errors: FDWT_EINVAL for alpha <= 1,
+ * beta <= 0, a non-finite q or NULL pointers. */
+typedef struct {
+  double alpha, beta, q;   /* the selected parameters          */
+  double cost;             /* their cost                        */
+  int evaluations;         /* cost evaluations used             */
+} fdwt_kernel_fit;
+
+int fdwt_split_cost(const fdwt_net* net, const float* f2_dev, double alpha, double beta, double q, float* sf_dev,
+                    double* cost, void* stream);
+int fdwt_kernel_tune(const fdwt_net* net, const float* f2_dev, const double* start, int max_evals,
+                     fdwt_kernel_fit* out, void* stream);
+
 /* ------------------------------------------------------------- batches */
 
 /* A ragged batch of independent p = 2 forward transforms (float data, job j

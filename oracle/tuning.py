@@ -69,9 +69,12 @@ def from_params(alpha, beta, q):
 
 
 def tune(m2, C2, f2, start=(2.0, 1.0, -2.0), maxfev=200):
-    """Nelder-Mead over (log(alpha - 1), log beta, q) from `start`; returns
-    (alpha, beta, q, cost, evaluations)."""
-    res = minimize(lambda th: split_cost(m2, C2, f2, *to_params(th)), from_params(*start),
-                   method="Nelder-Mead", options={"maxfev": maxfev, "xatol": 1e-3, "fatol": 1e-12})
+    """Nelder-Mead over (log(alpha - 1), log beta, q) from `start` (initial
+    simplex: steps of 0.5 along each coordinate); returns (alpha, beta, q,
+    cost, evaluations)."""
+    th0 = from_params(*start)
+    simplex = np.vstack([th0] + [th0 + 0.5 * e for e in np.eye(3)])  # steps of 0.5 per coordinate
+    res = minimize(lambda th: split_cost(m2, C2, f2, *to_params(th)), th0, method="Nelder-Mead",
+                   options={"maxfev": maxfev, "xatol": 1e-4, "fatol": 1e-12, "initial_simplex": simplex})
     a, b, q = to_params(res.x)
     return a, b, q, float(res.fun), int(res.nfev)

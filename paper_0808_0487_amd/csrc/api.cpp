@@ -323,6 +323,7 @@ int fdwt_net_generate(int p, int m, int s, const uint8_t* C_host, fdwt_net** out
     delete h;
     return fail(FDWT_EDEVICE, "no HIP device");
   }
+  net.C.assign(C_host, C_host + (size_t)s * m * m);
   auto C = [&](int j, int r, int c) { return (int)C_host[((int64_t)j * m + r) * m + c]; };
   if (p == 2) {
     // Column c of C_j as an m-bit integer (row r -> bit m-1-r); per byte b of n,
@@ -529,6 +530,33 @@ int fdwt_walsh_interp(const fdwt_net* h, const fdwt_kernel* kern, const float* f
   if (!rc && nq > 0) rc = run_spline_eval(net, net.sc, kern, nullptr, c, nq, q_dev, sf_dev, st);
   (void)hipFreeAsync(ft, st);
   return rc;
+  FDWT_GUARD_END
+}
+
+int fdwt_split_cost(const fdwt_net* h, const float* f2_dev, double alpha, double beta, double q, float* sf_dev,
+                    double* cost, void* stream) {
+  FDWT_GUARD_BEGIN
+  if (int rc = check_net(h)) return rc;
+  if (!f2_dev || !cost) return fail(FDWT_EINVAL, "NULL argument");
+  if (!(alpha > 1.0) || !std::isfinite(alpha) || !(beta > 0.0) || !std::isfinite(beta) || !std::isfinite(q))
+    return fail(FDWT_EINVAL, "need alpha > 1, beta > 0 and finite q");
+  DeviceGuard g(h->n.device);
+  const double prm[3] = {alpha, beta, q};
+  return split_cost_call(h->n, f2_dev, prm, sf_dev, cost, (hipStream_t)stream);
+  FDWT_GUARD_END
+}
+
+int fdwt_kernel_tune(const fdwt_net* h, const float* f2_dev, const double* start, int max_evals,
+                     fdwt_kernel_fit* out, void* stream) {
+  FDWT_GUARD_BEGIN
+  if (int rc = check_net(h)) return rc;
+  if (!f2_dev || !start || !out) return fail(FDWT_EINVAL, "NULL argument");
+  if (!(start[0] > 1.0) || !std::isfinite(start[0]) || !(start[1] > 0.0) || !std::isfinite(start[1]) ||
+      !std::isfinite(start[2]))
+    return fail(FDWT_EINVAL, "need alpha > 1, beta > 0 and finite q at the start");
+  if (max_evals < 4 || max_evals > 100000) return fail(FDWT_EINVAL, "max_evals must be in 4..100000");
+  DeviceGuard g(h->n.device);
+  return kernel_tune_call(h->n, f2_dev, start, max_evals, out, (hipStream_t)stream);
   FDWT_GUARD_END
 }
 

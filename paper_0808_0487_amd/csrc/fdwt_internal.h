@@ -58,6 +58,7 @@ struct Net {
   int64_t N = 0;
   int device = 0;
   int nbytes = 0;           // p = 2: bytes of n used by the XOR tables
+  std::vector<uint8_t> C;   // the generators, [s][m][m] as given
   // p = 2: uint32 [s][nbytes][256], XOR of generator columns per byte of n.
   uint32_t* d_xtab = nullptr;
   // p odd: uint64 [s][m][p]: packed digits (4-bit fields, digit y_{r+1} at
@@ -134,6 +135,21 @@ int eff_dim_enqueue(Net& net, Scratch& sc, const fdwt_kernel* kern, const void* 
                     double* res_host, const double** res_dev, hipStream_t st);
 void eff_dim_finish(int s, const double* res, fdwt_effdim* out);
 int run_eff_dim(Net& net, Scratch& sc, const fdwt_kernel* kern, const void* ft, fdwt_effdim* out, hipStream_t st);
+
+// Section 5.1 (p = 2): Sf on the second half of a 2^(m+1)-point net from the
+// spline fitted on the first half (the m-digit net `tr`), as the inverse
+// transform of f~ G / K_u, and the cost sum (f - Sf)^2.  delta: the second
+// half's shift x_N, per coordinate as an (m+1)-digit integer (host array).
+// ft: forward transform of the first half's values; fval: second half's
+// values; sf_out (nullable) receives Sf there.  Synchronises st.
+int run_split_cost(Net& tr, Scratch& sc, const uint32_t* delta, const float* ft, const float* fval,
+                   const fdwt_kernel* kern, float* sf_out, double* cost, hipStream_t st);
+
+// tune.cpp (Section 5.1): cost of (alpha, beta, q) = prm, and the
+// Nelder-Mead selection from `start`, for a p = 2 net of m + 1 digits.
+int split_cost_call(const Net& n2, const float* f2, const double prm[3], float* sf, double* cost, hipStream_t st);
+int kernel_tune_call(const Net& n2, const float* f2, const double start[3], int max_evals, fdwt_kernel_fit* out,
+                     hipStream_t st);
 
 // Host tables of the kernel closed forms in double, for coordinates j and
 // first-differing-digit index i (0 = no differing digit).

@@ -315,6 +315,71 @@ __global__ void __launch_bounds__(256) k_eval_finish(const df* __restrict__ part
   }
 }
 
+// ------------------------------------------------ kernel-parameter cost
+// Section 5.1, p = 2.  g(u) = K(x_u (+) x_N, 0) over the first half (an
+// m-digit net, tables of `na`): coordinate j of x_u (+) x_N as an
+// (m+1)-digit integer is (X_j(u) << 1) ^ delta_j; the factor comes from its
+// first non-zero digit, tk2[j][t] = 1 + gamma_j K'(t+1) (t < m+1) and
+// tk2[j][m+1] = 1 + gamma_j (all digits zero).
+__global__ void __launch_bounds__(kChunk) k_kernel_shift_p2(NetArgs na, const uint32_t* __restrict__ delta,
+                                                            const double* __restrict__ tk2, int m2,
+                                                            double* __restrict__ out) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  const int s = na.s;
+  double* ltk = reinterpret_cast<double*>(smem);                       // [s][kTab]
+  uint32_t* ld = reinterpret_cast<uint32_t*>(ltk + s * kTab);           // [s]
+  uint32_t* lt0 = ld + ((s + 1) & ~1);
+  for (int i = threadIdx.x; i < s * kTab; i += blockDim.x) ltk[i] = tk2[i];
+  for (int i = threadIdx.x; i < s; i += blockDim.x) ld[i] = delta[i];
+  P2Coords pc{na.xtab, na.nbytes, s, lt0, lt0 + s * 256};
+  pc.stage_tables();
+  const int64_t N = na.N;
+  for (int64_t base = (int64_t)blockIdx.x * kChunk; base < N; base += (int64_t)gridDim.x * kChunk) {
+    __syncthreads();
+    pc.stage_group(base);
+    __syncthreads();
+    const int64_t n = base + threadIdx.x;
+    if (n < N) {
+      double K = 1.0;
+      for (int j = 0; j < s; ++j) {
+        const uint32_t z = (pc.X(j, n) << 1) ^ ld[j];
+        const int t = z ? (int)__clz(z) - (32 - m2) : m2;
+        K *= ltk[j * kTab + t];
+      }
+      out[n] = K;
+    }
+  }
+}
+
+// P(h) = f~(h) G(h) / K_u(h) in place of G (K_u > 0; clamped against rounding).
+__global__ void __launch_bounds__(256) k_split_combine(const float* __restrict__ ft, const double* __restrict__ ku,
+                                                       double* __restrict__ g, int64_t N) {
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t h = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; h < N; h += stride)
+    g[h] = (double)ft[h] * g[h] / fmax(ku[h], 1e-300);
+}
+
+// Block partials of sum_n (fval[n] - sf[n])^2 in float64; sf_out (nullable)
+// receives sf as float.
+__global__ void __launch_bounds__(256) k_sq_diff(const float* __restrict__ fval, const double* __restrict__ sf,
+                                                 int64_t N, double* __restrict__ partial, float* __restrict__ sf_out) {
+  __shared__ double red[256];
+  double a = 0.0;
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t n = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; n < N; n += stride) {
+    const double d = (double)fval[n] - sf[n];
+    a += d * d;
+    if (sf_out) sf_out[n] = (float)sf[n];
+  }
+  red[threadIdx.x] = a;
+  __syncthreads();
+  for (int off = 128; off > 0; off >>= 1) {
+    if (threadIdx.x < off) red[threadIdx.x] += red[threadIdx.x + off];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) partial[blockIdx.x] = red[0];
+}
+
 // =============================================================== host side
 static NetArgs net_args(const Net& net) {
   return NetArgs{net.d_xtab, net.d_ptab, net.nbytes, net.s, net.m, net.N};
@@ -727,6 +792,53 @@ int run_eff_dim(Net& net, Scratch& sc, const fdwt_kernel* kern, const void* ft, 
   FDWT_HIP(hipStreamSynchronize(st));
   FDWT_HIP(hipMemcpy(res.data(), res_dev, eff_dim_res_bytes(net), hipMemcpyDeviceToHost));
   eff_dim_finish(net.s, res.data(), out);
+  return FDWT_OK;
+}
+
+// ------------------------------------------------------- split cost
+int run_split_cost(Net& tr, Scratch& sc, const uint32_t* delta, const float* ft, const float* fval,
+                   const fdwt_kernel* kern, float* sf_out, double* cost, hipStream_t st) {
+  const int s = tr.s, m2 = tr.m + 1;
+  const int64_t N = tr.N;
+  Carve need(nullptr);
+  need.take(spectrum_bytes(tr));
+  need.take(spectrum_ws_bytes(tr));
+  need.take((size_t)s * kTab * sizeof(double));
+  need.take((size_t)s * 4);
+  need.take((size_t)N * 8);
+  need.take(kRedBlocks * sizeof(double));
+  need.take(sizeof(double));
+  if (int rc = ensure_ws(sc, need.off, st)) return rc;
+  Carve cv(sc.ws);
+  double* gk = (double*)cv.take(spectrum_bytes(tr));
+  void* sw = cv.take(spectrum_ws_bytes(tr));
+  double* tk2 = (double*)cv.take((size_t)s * kTab * sizeof(double));
+  uint32_t* dd = (uint32_t*)cv.take((size_t)s * 4);
+  double* g = (double*)cv.take((size_t)N * 8);
+  double* partial = (double*)cv.take(kRedBlocks * sizeof(double));
+  double* res = (double*)cv.take(sizeof(double));
+  int rc = spectrum_into(tr, sc, kern, sw, gk, st);  // K_u, unnormalised
+  if (rc) return rc;
+  std::vector<double> h2((size_t)s * kTab, 1.0);
+  for (int j = 0; j < s; ++j)
+    for (int t = 0; t <= m2; ++t)
+      h2[(size_t)j * kTab + t] = 1.0 + kern->gamma[j] * kprime(2, kern->alpha, t < m2 ? t + 1 : 0);
+  if ((rc = upload(sc, h2.data(), h2.size() * sizeof(double), tk2, st))) return rc;
+  if ((rc = upload(sc, delta, (size_t)s * 4, dd, st))) return rc;
+  const size_t lds = (size_t)s * kTab * 8 + (size_t)((s + 1) & ~1) * 4 + (size_t)s * 257 * 4;
+  if ((rc = allow_lds((const void*)k_kernel_shift_p2, lds))) return rc;
+  const unsigned grid = (unsigned)std::min<int64_t>((N + kChunk - 1) / kChunk, 2048);
+  hipLaunchKernelGGL(k_kernel_shift_p2, dim3(grid), dim3(kChunk), lds, st, net_args(tr), dd, tk2, m2, g);
+  FDWT_HIP(hipGetLastError());
+  if ((rc = fwt_run_tmp(2, tr.m, false, K_F64, g, K_F64, K_F64, g, nullptr, 1, 1.0, st))) return rc;
+  hipLaunchKernelGGL(k_split_combine, dim3(grid1(N)), dim3(256), 0, st, ft, gk, g, N);
+  FDWT_HIP(hipGetLastError());
+  if ((rc = fwt_run_tmp(2, tr.m, true, K_F64, g, K_F64, K_F64, g, nullptr, 1, 1.0, st))) return rc;
+  hipLaunchKernelGGL(k_sq_diff, dim3(kRedBlocks), dim3(256), 0, st, fval, g, N, partial, sf_out);
+  hipLaunchKernelGGL(k_sum_rows, dim3(1), dim3(256), 0, st, partial, kRedBlocks, res);
+  FDWT_HIP(hipGetLastError());
+  FDWT_HIP(hipStreamSynchronize(st));
+  FDWT_HIP(hipMemcpy(cost, res, sizeof(double), hipMemcpyDeviceToHost));
   return FDWT_OK;
 }
 

@@ -31,6 +31,11 @@ class EffDimC(ctypes.Structure):
                 ("var_qmc", ctypes.c_double), ("d_trc", ctypes.c_int), ("d_sup", ctypes.c_int)]
 
 
+class KernelFitC(ctypes.Structure):
+    _fields_ = [("alpha", ctypes.c_double), ("beta", ctypes.c_double), ("q", ctypes.c_double),
+                ("cost", ctypes.c_double), ("evaluations", ctypes.c_int)]
+
+
 class ServerConfigC(ctypes.Structure):
     _fields_ = [("hbm_budget", ctypes.c_size_t), ("lanes", ctypes.c_int), ("max_bypass", ctypes.c_int),
                 ("effdim_chunk_bytes", ctypes.c_size_t)]
@@ -72,6 +77,8 @@ SIGNATURES = {
     "fdwt_spline_eval": (_i, [_vp, ctypes.POINTER(KernelC), _vp, _i64, _vp, _vp, _vp]),
     "fdwt_walsh_interp": (_i, [_vp, ctypes.POINTER(KernelC), _vp, _vp, _i64, _vp, _vp, _vp]),
     "fdwt_eff_dim": (_i, [_vp, ctypes.POINTER(KernelC), _i, _vp, ctypes.POINTER(EffDimC), _vp]),
+    "fdwt_split_cost": (_i, [_vp, _vp, _d, _d, _d, _vp, ctypes.POINTER(_d)]),
+    "fdwt_kernel_tune": (_i, [_vp, _vp, _vp, _i, ctypes.POINTER(KernelFitC), _vp]),
     "fdwt_batch_create": (_i, [_i, _vp, _i, ctypes.POINTER(_vp)]),
     "fdwt_batch_run": (_i, [_vp, _vp]),
     "fdwt_batch_check": (_i, [_vp, _vp]),
@@ -329,6 +336,23 @@ class Net:
         _check(lib().fdwt_walsh_interp(self.h, kern.c, _ptr(f), _ptr(c_out), nq, _ptr(q) if nq else None,
                                        _ptr(sf_out) if nq else None, _stream(stream)))
         return c_out, sf_out
+
+    # ------------------------------------------ kernel-parameter selection
+    def split_cost(self, f2, alpha, beta, q, want_sf=False):
+        """Section 5.1 cost (and Sf at the second half) for a p = 2 net of
+        2N points; f2 float32 [2N] on the device."""
+        import torch
+        sf = torch.empty(self.N // 2, dtype=torch.float32, device=f2.device) if want_sf else None
+        c = ctypes.c_double()
+        _check(lib().fdwt_split_cost(self.h, _ptr(f2), alpha, beta, q, _ptr(sf) if want_sf else None,
+                                     ctypes.byref(c), _stream(None)))
+        return (c.value, sf) if want_sf else c.value
+
+    def kernel_tune(self, f2, start=(2.0, 1.0, -2.0), max_evals=200):
+        st = np.ascontiguousarray(start, dtype=np.float64)
+        out = KernelFitC()
+        _check(lib().fdwt_kernel_tune(self.h, _ptr(f2), st.ctypes.data, max_evals, ctypes.byref(out), _stream(None)))
+        return {"alpha": out.alpha, "beta": out.beta, "q": out.q, "cost": out.cost, "evaluations": out.evaluations}
 
     def eff_dim(self, kern, ft, stream=None):
         trc = np.zeros(self.s + 1)
