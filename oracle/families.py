@@ -4,8 +4,11 @@ see the package docstring.
   * product:  f(x) = prod_j (1 + a_j (x_j - 1/2))
   * exp:      f(x) = exp(-sum_j w_j x_j^2)
   * wangfang: f(x) = prod_j (|4 x_j - 2| + a_j)/(1 + a_j)   (Section 5.2)
+  * asian:    discounted payoff of an arithmetic-average Asian call under
+              geometric Brownian motion, standard construction (Section 5.3)
 """
 import numpy as np
+from scipy.special import ndtri
 
 
 def product(x, a):
@@ -23,6 +26,22 @@ def wangfang(x, a):
     return np.prod((np.abs(4.0 * np.asarray(x) - 2.0) + a) / (1.0 + a), axis=0)
 
 
+def asian(x, S0, K, sigma, r, T):
+    """Section 5.3: S_j = S_{j-1} exp((r - sigma^2/2) T/s + sigma sqrt(T/s) Z_j)
+    with Z_j = Phi^-1(x_j) (coordinate j drives step j), payoff
+    max(mean_j S_j - K, 0) discounted by exp(-rT).  x_j = 0 gives Z_j = -inf
+    (the path collapses to 0)."""
+    x = np.asarray(x, dtype=np.float64)
+    s = x.shape[0]
+    dt = T / s
+    with np.errstate(divide="ignore", over="ignore", invalid="ignore"):
+        Z = ndtri(x)
+        logS = np.log(S0) + np.cumsum((r - 0.5 * sigma ** 2) * dt + sigma * np.sqrt(dt) * Z, axis=0)
+        S = np.exp(logS)
+    S = np.where(np.isnan(S), 0.0, S)
+    return np.exp(-r * T) * np.maximum(S.mean(axis=0) - K, 0.0)
+
+
 def evaluate(kind, x, params):
     if kind == "product":
         return product(x, params)
@@ -30,4 +49,6 @@ def evaluate(kind, x, params):
         return exponential(x, params)
     if kind == "wangfang":
         return wangfang(x, params)
+    if kind == "asian":
+        return asian(x, *params)
     raise ValueError(kind)
