@@ -284,6 +284,37 @@ def section52_leg(torch, fdwt, inputs):
             "seconds": time.perf_counter() - t0, "rows": rows}
 
 
+def section53_leg(torch, fdwt, inputs):
+    """The Asian-call experiment of Section 5.3 (Tables 3 and 4): p = 2,
+    N = 2^14, S0 = K = 100, sigma = 0.2, r = 0.1, T = 1, s in {8, 16, 32},
+    standard construction (coordinate j drives time step j).  Per s: a seeded
+    upper-triangular net of 2^15 points (standing in for the paper's Sobol'
+    points), kernel parameters selected on it (Section 5.1), the spline on its
+    first 2^14 points, then eff_dim."""
+    prm = np.array([100.0, 100.0, 0.2, 0.1, 1.0])
+    rows = []
+    t0 = time.perf_counter()
+    for i, s in enumerate([8, 16, 32]):
+        m2 = 15
+        C2 = inputs.upper_triangular_generators(2, m2, s, seed=200 + i)
+        net2 = fdwt.Net(2, m2, s, C2)
+        f2 = net2.sample("asian", prm)
+        fit = net2.kernel_tune(f2, start=(2.0, 1.0, -1.0), max_evals=300)
+        net = fdwt.Net(2, m2 - 1, s, np.ascontiguousarray(C2[:, :m2 - 1, :m2 - 1]))
+        gam = fit["beta"] * np.arange(1, s + 1, dtype=np.float64) ** fit["q"]
+        f = f2[:2 ** (m2 - 1)].contiguous()
+        ed = net.eff_dim(fdwt.Kernel(fit["alpha"], gam), net.forward(f))
+        rows.append({"s": s, "spline_d_trc": ed["d_trc"], "spline_d_sup": ed["d_sup"], "var_qmc": ed["var_qmc"],
+                     "var_Sf": ed["var_total"], "ratio": ed["var_total"] / ed["var_qmc"],
+                     "price_qmc": float(f.double().mean()),
+                     "alpha": fit["alpha"], "beta": fit["beta"], "q": fit["q"], "cost_evaluations": fit["evaluations"]})
+        net.close()
+        net2.close()
+    return {"workload": "Section 5.3 Asian call, p=2 N=2^14 (+2^14 validation points), S0=K=100 sigma=0.2 r=0.1 T=1, "
+                        "standard construction, seeded upper-triangular nets, kernel by Nelder-Mead",
+            "seconds": time.perf_counter() - t0, "rows": rows}
+
+
 def serving_leg(fdwt, inputs, window, rate, budget_gb, lanes):
     """Serving workload: Poisson arrivals at `rate` per second over `window`
     seconds, requests drawn from a pool of 64 seeded nets (p in {2, 3, 5},
@@ -508,6 +539,7 @@ def main():
         out["interp_p3"] = interp_leg(torch, fdwt, inputs)
     if not args.no_table1:
         out["section52"] = section52_leg(torch, fdwt, inputs)
+        out["section53"] = section53_leg(torch, fdwt, inputs)
     torch.cuda.empty_cache()
     if not args.no_serve:
         out["serving"] = serving_leg(fdwt, inputs, args.serve_window, args.serve_rate, args.serve_budget_gb,

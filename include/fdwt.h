@@ -85,10 +85,22 @@ void fdwt_net_free(fdwt_net* net);
 #define FDWT_FAMILY_EXP      2   /* f = exp(-sum_j a_j x_j^2)                     */
 #define FDWT_FAMILY_WANGFANG 3   /* f = prod_j (|4 x_j - 2| + a_j)/(1 + a_j),
                                     the test function of Section 5.2              */
+#define FDWT_FAMILY_ASIAN    4   /* discounted payoff of the arithmetic-average
+                                    Asian call of Section 5.3: coordinate j drives
+                                    step j of the standard construction,
+                                    S_j = S_{j-1} exp((r - sigma^2/2) T/s
+                                          + sigma sqrt(T/s) Phi^-1(x_j)),
+                                    f = exp(-rT) max(A - K, 0), A the mean
+                                    of S_0..S_s (the prices at t_j = jT/s,
+                                    j = 0..s; Table 4's variances are those of
+                                    this mean);
+                                    a_host = {S0, K, sigma, r, T} (5 values,
+                                    whatever s), evaluated in double            */
 
 /* Sample a test function at the net: f_dev[n] = f(x_n), float [N], computed
  * on the device from the net (the points are not materialised).  a_host is
- * double [s] (read during the call).  Values are evaluated in float. */
+ * double [s] (read during the call; 5 model values for FDWT_FAMILY_ASIAN).
+ * Values are evaluated in float (the Asian payoff in double). */
 int fdwt_sample(const fdwt_net* net, int family, const double* a_host, float* f_dev, void* stream);
 
 /* ----------------------------------------------------------- transforms */
@@ -321,7 +333,7 @@ typedef struct {
   uint64_t net_key;          /* equal keys must mean equal (p, m, s, C)     */
   const uint8_t* C_host;     /* [s][m][m], as fdwt_net_generate             */
   int family;                /* FDWT_FAMILY_*                               */
-  const double* a_host;      /* [s] family parameters                       */
+  const double* a_host;      /* family parameters: [s], or 5 for ASIAN      */
   double alpha;              /* kernel smoothness, > 1                      */
   const double* gamma_host;  /* [s] kernel weights, > 0                     */
   int64_t nq;                /* interpolation: 1..2^24 queries              */

@@ -28,9 +28,12 @@ def wangfang(x, a):
 
 def asian(x, S0, K, sigma, r, T):
     """Section 5.3: S_j = S_{j-1} exp((r - sigma^2/2) T/s + sigma sqrt(T/s) Z_j)
-    with Z_j = Phi^-1(x_j) (coordinate j drives step j), payoff
-    max(mean_j S_j - K, 0) discounted by exp(-rT).  x_j = 0 gives Z_j = -inf
-    (the path collapses to 0)."""
+    with Z_j = Phi^-1(x_j) (coordinate j drives step j); the payoff is
+    max(A - K, 0) discounted by exp(-rT), A the mean of the s + 1 prices
+    S_0..S_s at t_j = jT/s, j = 0..s.  (The printed payoff averages S_1..S_s
+    over s; the section's own variances, Table 4, are those of the mean over
+    j = 0..s, which is the reading taken.)  x_j = 0 gives Z_j = -inf (the
+    path collapses to 0 from step j on)."""
     x = np.asarray(x, dtype=np.float64)
     s = x.shape[0]
     dt = T / s
@@ -39,7 +42,8 @@ def asian(x, S0, K, sigma, r, T):
         logS = np.log(S0) + np.cumsum((r - 0.5 * sigma ** 2) * dt + sigma * np.sqrt(dt) * Z, axis=0)
         S = np.exp(logS)
     S = np.where(np.isnan(S), 0.0, S)
-    return np.exp(-r * T) * np.maximum(S.mean(axis=0) - K, 0.0)
+    A = (S0 + S.sum(axis=0)) / (s + 1)
+    return np.exp(-r * T) * np.maximum(A - K, 0.0)
 
 
 def evaluate(kind, x, params):

@@ -206,6 +206,22 @@ static int check_kernel(const Net& net, const fdwt_kernel* k) {
   return FDWT_OK;
 }
 
+static int check_family(const Net& net, int family, const double* a) {
+  if (family == FDWT_FAMILY_ASIAN) {
+    for (int i = 0; i < 5; ++i)
+      if (!std::isfinite(a[i])) return fail(FDWT_EINVAL, "family parameter out of range");
+    if (!(a[0] > 0.0) || a[1] < 0.0 || !(a[2] > 0.0) || !(a[4] > 0.0))
+      return fail(FDWT_EINVAL, "Asian parameters need S0 > 0, K >= 0, sigma > 0, T > 0");
+    return FDWT_OK;
+  }
+  if (family != FDWT_FAMILY_PRODUCT && family != FDWT_FAMILY_EXP && family != FDWT_FAMILY_WANGFANG)
+    return fail(FDWT_EINVAL, "unknown family");
+  for (int j = 0; j < net.s; ++j)
+    if (!std::isfinite(a[j]) || (family == FDWT_FAMILY_WANGFANG && a[j] <= -1.0))
+      return fail(FDWT_EINVAL, "family parameter out of range");
+  return FDWT_OK;
+}
+
 static Kind to_kind(int t) {
   switch (t) {
     case FDWT_F32: return K_F32;
@@ -419,11 +435,7 @@ int fdwt_sample(const fdwt_net* h, int family, const double* a_host, float* f_de
   FDWT_GUARD_BEGIN
   if (int rc = check_net(h)) return rc;
   if (!a_host || !f_dev) return fail(FDWT_EINVAL, "NULL argument");
-  if (family != FDWT_FAMILY_PRODUCT && family != FDWT_FAMILY_EXP && family != FDWT_FAMILY_WANGFANG)
-    return fail(FDWT_EINVAL, "unknown family");
-  for (int j = 0; j < h->n.s; ++j)
-    if (!std::isfinite(a_host[j]) || (family == FDWT_FAMILY_WANGFANG && a_host[j] <= -1.0))
-      return fail(FDWT_EINVAL, "family parameter out of range");
+  if (int rc = check_family(h->n, family, a_host)) return rc;
   DeviceGuard g(h->n.device);
   return launch_sample(h->n, family, a_host, f_dev, (hipStream_t)stream);
   FDWT_GUARD_END
@@ -444,11 +456,7 @@ int fdwt_dwt_forward_family(const fdwt_net* h, int family, const double* a_host,
   FDWT_GUARD_BEGIN
   if (int rc = check_net(h)) return rc;
   if (!a_host || !out_dev) return fail(FDWT_EINVAL, "NULL argument");
-  if (family != FDWT_FAMILY_PRODUCT && family != FDWT_FAMILY_EXP && family != FDWT_FAMILY_WANGFANG)
-    return fail(FDWT_EINVAL, "unknown family");
-  for (int j = 0; j < h->n.s; ++j)
-    if (!std::isfinite(a_host[j]) || (family == FDWT_FAMILY_WANGFANG && a_host[j] <= -1.0))
-      return fail(FDWT_EINVAL, "family parameter out of range");
+  if (int rc = check_family(h->n, family, a_host)) return rc;
   Net& net = const_cast<Net&>(h->n);
   if (out_type != (net.p == 2 ? FDWT_F32 : FDWT_CF32))
     return fail(FDWT_EINVAL, "coefficients are F32 (p = 2) or CF32 (p odd)");

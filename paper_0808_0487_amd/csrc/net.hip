@@ -7,6 +7,8 @@
 #include "coords.h"
 #include "dev_math.h"
 
+#include <cmath>
+
 namespace fdwt {
 
 // ------------------------------------------------------------- kernels
@@ -60,26 +62,67 @@ __global__ void __launch_bounds__(kChunk) k_coords_odd(const uint64_t* ptab, int
   }
 }
 
-// Test-function families (float arithmetic).
+// Test-function families.  The first three work in float on x = X p^-m;
+// the Asian payoff (Section 5.3) works in double on the exact quotient.
 struct FamilyArgs {
   int s;
   float a[kMaxS];
   float inv1a[kMaxS];  // 1 / (1 + a_j), Section 5.2 function
+  // Asian call: log S0, K, drift (r - sigma^2/2) T/s, sigma sqrt(T/s),
+  // discount exp(-rT), 1/(s + 1) (the mean runs over S_0..S_s).
+  double g[6];
+};
+
+// Standard normal quantile: the rational approximation 26.2.23 of
+// Abramowitz and Stegun (absolute error below 4.5e-4) on the smaller tail,
+// refined by three Newton steps on Phi(x) = erfc(-x/sqrt 2)/2 (quadratic
+// convergence); u = 0 and u = 1 map to -inf and +inf.
+__device__ __forceinline__ double inv_normal(double u) {
+  if (u <= 0.0) return -INFINITY;
+  if (u >= 1.0) return INFINITY;
+  const double pl = u < 0.5 ? u : 1.0 - u;  // exact for u = X p^-m
+  const double t = sqrt(-2.0 * log(pl));
+  double x = -(t - (2.515517 + t * (0.802853 + t * 0.010328)) / (1.0 + t * (1.432788 + t * (0.189269 + t * 0.001308))));
+  const double sqrt2pi = 2.5066282746310002;
+  for (int k = 0; k < 3; ++k) {
+    const double e = 0.5 * erfc(-x * 0.70710678118654752) - pl;  // Phi(x) - pl, accurate in the tail
+    x -= e * sqrt2pi * exp(0.5 * x * x);
+  }
+  return u < 0.5 ? x : -x;
+}
+
+template <int FAM>
+struct FamState {
+  using T = float;
+};
+template <>
+struct FamState<FDWT_FAMILY_ASIAN> {
+  using T = double2;  // (log S_j, sum of S_1..S_j)
 };
 
 template <int FAM>
-__device__ __forceinline__ float fam_init() {
-  return FAM == FDWT_FAMILY_EXP ? 0.0f : 1.0f;
+__device__ __forceinline__ typename FamState<FAM>::T fam_init(const FamilyArgs& fa) {
+  if constexpr (FAM == FDWT_FAMILY_ASIAN) return make_double2(fa.g[0], exp(fa.g[0]));  // S_0 in the mean
+  else return FAM == FDWT_FAMILY_EXP ? 0.0f : 1.0f;
+}
+// One coordinate: X its integer value, inv_f / inv_d the factor p^-m.
+template <int FAM>
+__device__ __forceinline__ void fam_step(typename FamState<FAM>::T& acc, const FamilyArgs& fa, float a, float inv1a,
+                                         uint32_t X, float inv_f, double inv_d) {
+  if constexpr (FAM == FDWT_FAMILY_ASIAN) {
+    acc.x += fa.g[2] + fa.g[3] * inv_normal((double)X * inv_d);
+    acc.y += exp(acc.x);
+  } else {
+    const float x = (float)X * inv_f;
+    if constexpr (FAM == FDWT_FAMILY_PRODUCT) acc = acc * (1.0f + a * (x - 0.5f));
+    else if constexpr (FAM == FDWT_FAMILY_EXP) acc = acc + a * x * x;
+    else acc = acc * ((fabsf(4.0f * x - 2.0f) + a) * inv1a);
+  }
 }
 template <int FAM>
-__device__ __forceinline__ float fam_step(float acc, float a, float inv1a, float x) {
-  if constexpr (FAM == FDWT_FAMILY_PRODUCT) return acc * (1.0f + a * (x - 0.5f));
-  else if constexpr (FAM == FDWT_FAMILY_EXP) return acc + a * x * x;
-  else return acc * ((fabsf(4.0f * x - 2.0f) + a) * inv1a);
-}
-template <int FAM>
-__device__ __forceinline__ float fam_final(float acc) {
-  if constexpr (FAM == FDWT_FAMILY_EXP) return expf(-acc);
+__device__ __forceinline__ float fam_final(typename FamState<FAM>::T acc, const FamilyArgs& fa) {
+  if constexpr (FAM == FDWT_FAMILY_ASIAN) return (float)(fa.g[4] * fmax(acc.y * fa.g[5] - fa.g[1], 0.0));
+  else if constexpr (FAM == FDWT_FAMILY_EXP) return expf(-acc);
   else return acc;
 }
 
@@ -102,15 +145,15 @@ __global__ void __launch_bounds__(kChunk) k_sample_p2(const uint32_t* xtab, int 
     pc.stage_group(base);
     __syncthreads();
     const int64_t n = base + threadIdx.x;
-    float acc = fam_init<FAM>();
-    for (int j = 0; j < s; ++j) acc = fam_step<FAM>(acc, la[j], li[j], (float)pc.X(j, n) * inv);
-    if (n < N) f[n] = fam_final<FAM>(acc);
+    auto acc = fam_init<FAM>(fa);
+    for (int j = 0; j < s; ++j) fam_step<FAM>(acc, fa, la[j], li[j], pc.X(j, n), inv, (double)inv);
+    if (n < N) f[n] = fam_final<FAM>(acc, fa);
   }
 }
 
 template <int P, int FAM>
 __global__ void __launch_bounds__(kChunk) k_sample_odd(const uint64_t* ptab, FamilyArgs fa, int m, int64_t N,
-                                                       float inv_pm, float* f) {
+                                                       float inv_pm, double inv_pm_d, float* f) {
   extern __shared__ __align__(16) uint64_t lds_odd[];
   const int s = fa.s;
   OddCoords<P> oc{ptab, s, m, lds_odd, lds_odd + s * OddCoords<P>::PK};
@@ -129,12 +172,10 @@ __global__ void __launch_bounds__(kChunk) k_sample_odd(const uint64_t* ptab, Fam
     if (n < N) {
       int r, k;
       oc.split(n, r, k);
-      float acc = fam_init<FAM>();
-      for (int j = 0; j < s; ++j) {
-        const uint32_t X = canon_odd<P>(oc.X(j, r, k), m);
-        acc = fam_step<FAM>(acc, la[j], li[j], (float)X * inv_pm);
-      }
-      f[n] = fam_final<FAM>(acc);
+      auto acc = fam_init<FAM>(fa);
+      for (int j = 0; j < s; ++j)
+        fam_step<FAM>(acc, fa, la[j], li[j], canon_odd<P>(oc.X(j, r, k), m), inv_pm, inv_pm_d);
+      f[n] = fam_final<FAM>(acc, fa);
     }
   }
 }
@@ -186,12 +227,12 @@ static int sample_fam(const Net& net, const FamilyArgs& fa, float* f, unsigned g
     const size_t lds = OddCoords<3>::lds_bytes(net.s) + 2 * kMaxS * 4;
     if (int rc = allow_lds((const void*)k_sample_odd<3, FAM>, lds)) return rc;
     hipLaunchKernelGGL((k_sample_odd<3, FAM>), dim3(g), dim3(kChunk), lds, st, net.d_ptab, fa, net.m, net.N,
-                       inv_pm(net), f);
+                       inv_pm(net), 1.0 / (double)net.N, f);
   } else {
     const size_t lds = OddCoords<5>::lds_bytes(net.s) + 2 * kMaxS * 4;
     if (int rc = allow_lds((const void*)k_sample_odd<5, FAM>, lds)) return rc;
     hipLaunchKernelGGL((k_sample_odd<5, FAM>), dim3(g), dim3(kChunk), lds, st, net.d_ptab, fa, net.m, net.N,
-                       inv_pm(net), f);
+                       inv_pm(net), 1.0 / (double)net.N, f);
   }
   return FDWT_OK;
 }
@@ -199,15 +240,27 @@ static int sample_fam(const Net& net, const FamilyArgs& fa, float* f, unsigned g
 int launch_sample(const Net& net, int family, const double* a, float* f, hipStream_t st) {
   FamilyArgs fa;
   fa.s = net.s;
-  for (int j = 0; j < net.s; ++j) {
-    fa.a[j] = (float)a[j];
-    fa.inv1a[j] = (float)(1.0 / (1.0 + a[j]));
+  if (family == FDWT_FAMILY_ASIAN) {
+    // a = (S0, K, sigma, r, T)
+    const double dt = a[4] / net.s;
+    fa.g[0] = std::log(a[0]);
+    fa.g[1] = a[1];
+    fa.g[2] = (a[3] - 0.5 * a[2] * a[2]) * dt;
+    fa.g[3] = a[2] * std::sqrt(dt);
+    fa.g[4] = std::exp(-a[3] * a[4]);
+    fa.g[5] = 1.0 / (net.s + 1);
+  } else {
+    for (int j = 0; j < net.s; ++j) {
+      fa.a[j] = (float)a[j];
+      fa.inv1a[j] = (float)(1.0 / (1.0 + a[j]));
+    }
   }
   const unsigned g = grid_for(net.N, 256);
   hipEvent_t tb = timed_begin(st);
   int rc;
   if (family == FDWT_FAMILY_PRODUCT) rc = sample_fam<FDWT_FAMILY_PRODUCT>(net, fa, f, g, st);
   else if (family == FDWT_FAMILY_EXP) rc = sample_fam<FDWT_FAMILY_EXP>(net, fa, f, g, st);
+  else if (family == FDWT_FAMILY_ASIAN) rc = sample_fam<FDWT_FAMILY_ASIAN>(net, fa, f, g, st);
   else rc = sample_fam<FDWT_FAMILY_WANGFANG>(net, fa, f, g, st);
   if (rc) return rc;
   FDWT_HIP(hipGetLastError());

@@ -105,7 +105,8 @@ int check_request(const fdwt_request* q) {
   if (!q->C_host || !q->a_host || !q->gamma_host) return fail(FDWT_EINVAL, "NULL request array");
   for (int64_t i = 0; i < (int64_t)q->s * q->m * q->m; ++i)
     if (q->C_host[i] >= q->p) return fail(FDWT_EINVAL, "generator entry >= p");
-  if (q->family != FDWT_FAMILY_PRODUCT && q->family != FDWT_FAMILY_EXP && q->family != FDWT_FAMILY_WANGFANG)
+  if (q->family != FDWT_FAMILY_PRODUCT && q->family != FDWT_FAMILY_EXP && q->family != FDWT_FAMILY_WANGFANG &&
+      q->family != FDWT_FAMILY_ASIAN)
     return fail(FDWT_EINVAL, "unknown family");
   if (!(q->alpha > 1.0) || !std::isfinite(q->alpha)) return fail(FDWT_EINVAL, "alpha must be > 1");
   for (int j = 0; j < q->s; ++j)
@@ -127,7 +128,7 @@ Request copy_request(const fdwt_request* q) {
   r.family = q->family;
   r.net_key = q->net_key;
   r.C.assign(q->C_host, q->C_host + (size_t)q->s * q->m * q->m);
-  r.a.assign(q->a_host, q->a_host + q->s);
+  r.a.assign(q->a_host, q->a_host + (q->family == FDWT_FAMILY_ASIAN ? 5 : q->s));
   r.gamma.assign(q->gamma_host, q->gamma_host + q->s);
   r.alpha = q->alpha;
   r.nq = q->kind == FDWT_JOB_INTERP ? q->nq : 0;

@@ -15,7 +15,7 @@ LIB_PATH = os.path.join(HERE, "libfdwt.so")
 
 OK, EINVAL, ENOMEM, EDEVICE, EBUDGET, EUNSUPPORTED = 0, -1, -2, -3, -4, -5
 F32, I32, CF32, F64, CF64 = 1, 2, 3, 4, 5
-FAMILY = {"product": 1, "exp": 2, "wangfang": 3}
+FAMILY = {"product": 1, "exp": 2, "wangfang": 3, "asian": 4}
 
 # Every function the header declares, with (restype, argtypes).
 _vp, _i, _i64, _d = ctypes.c_void_p, ctypes.c_int, ctypes.c_int64, ctypes.c_double
@@ -379,8 +379,9 @@ class Request:
         self.gamma = np.ascontiguousarray(gamma, dtype=np.float64)
         self.q = None if queries is None else np.ascontiguousarray(queries, dtype=np.uint32)
         self.net_key, self.family, self.alpha = int(net_key), family, float(alpha)
-        if self.C.shape != (s, m, m) or self.a.shape != (s,) or self.gamma.shape != (s,):
-            raise ValueError("C (s, m, m), a (s,) and gamma (s,) expected")
+        na = 5 if family == "asian" else s
+        if self.C.shape != (s, m, m) or self.a.shape != (na,) or self.gamma.shape != (s,):
+            raise ValueError("C (s, m, m), a (s,) or (5,) for 'asian', and gamma (s,) expected")
         if kind == "interp" and (self.q is None or self.q.ndim != 2 or self.q.shape[0] != s):
             raise ValueError("interp requests need queries of shape (s, nq)")
 

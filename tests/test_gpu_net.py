@@ -103,3 +103,17 @@ def test_forward_of_sampled_family_equals_two_calls(p, m, s, family):
     ref = walsh.dwt_phase(p, m, fo, hs)
     got = fused[hs]
     assert nrel(got, ref.real if p == 2 else ref) <= 1e-5
+
+
+@pytest.mark.parametrize("p,m,s", [(2, 14, 8), (2, 10, 32), (3, 8, 5), (5, 5, 3)])
+def test_asian_payoff_against_oracle(p, m, s):
+    """Section 5.3 payoff sampled on the device (double, inverse normal by
+    A&S 26.2.23 + Newton) against the oracle (scipy ndtri) at every point."""
+    announce("asian", p, m, s)
+    C = inputs.upper_triangular_generators(p, m, s, 31)
+    prm = np.array([100.0, 100.0, 0.2, 0.1, 1.0])
+    net = fdwt.Net(p, m, s, C)
+    got = net.sample("asian", prm).cpu().numpy().astype(np.float64)
+    ref = families.asian(onet.net_points(p, m, C), *prm)
+    assert nrel(got, ref) <= 2e-7
+    assert got[0] == 0.0  # the point 0 collapses the path

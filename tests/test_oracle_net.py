@@ -98,30 +98,33 @@ def test_every_one_dimensional_binary_net_t_value():
             assert t == 0
 
 
-def test_asian_payoff_one_step_is_black_scholes():
-    """With s = 1 the Asian call is a European call: the integral of the
-    oracle's payoff over [0, 1] (midpoint rule, 2^18 cells) equals the
+def test_asian_payoff_one_step_is_half_a_black_scholes_call():
+    """With s = 1 the payoff is exp(-rT) max((S0 + S1)/2 - K, 0), half a
+    European call on S1 with strike 2K - S0: the integral of the oracle's
+    payoff over [0, 1] (midpoint rule, 2^18 cells) equals half the
     Black-Scholes price."""
     from math import erf, exp, log, sqrt
     from oracle import families
-    S0, K, sigma, r, T = 100.0, 100.0, 0.2, 0.1, 1.0
+    S0, K, sigma, r, T = 100.0, 95.0, 0.2, 0.1, 1.0
     M = 1 << 18
     x = ((np.arange(M) + 0.5) / M)[None, :]
     price = float(np.mean(families.asian(x, S0, K, sigma, r, T)))
     Phi = lambda z: 0.5 * (1.0 + erf(z / sqrt(2.0)))
-    d1 = (log(S0 / K) + (r + 0.5 * sigma ** 2) * T) / (sigma * sqrt(T))
-    bs = S0 * Phi(d1) - K * exp(-r * T) * Phi(d1 - sigma * sqrt(T))
-    assert abs(price - bs) <= 2e-4 * bs
+    K2 = 2 * K - S0
+    d1 = (log(S0 / K2) + (r + 0.5 * sigma ** 2) * T) / (sigma * sqrt(T))
+    bs = S0 * Phi(d1) - K2 * exp(-r * T) * Phi(d1 - sigma * sqrt(T))
+    assert abs(price - 0.5 * bs) <= 2e-4 * bs
 
 
 def test_asian_payoff_limits():
-    """No volatility: a deterministic path, payoff (mean of S0 e^{r t_j} - K)+
-    discounted; a point with a zero coordinate has payoff 0 (path collapses)."""
+    """No volatility: a deterministic path, payoff (mean over j = 0..s of
+    S0 e^{r t_j} - K)+ discounted; a zero coordinate collapses the rest of
+    the path."""
     from oracle import families
     s, S0, K, r, T = 4, 100.0, 95.0, 0.05, 1.0
     x = np.full((s, 1), 0.3)
     v = families.asian(x, S0, K, 1e-12, r, T)[0]
-    t = np.arange(1, s + 1) * T / s
+    t = np.arange(0, s + 1) * T / s
     assert abs(v - np.exp(-r * T) * (np.mean(S0 * np.exp(r * t)) - K)) <= 1e-8
-    x[1, 0] = 0.0
-    assert families.asian(x, S0, K, 0.2, r, T)[0] == 0.0
+    x[0, 0] = 0.0
+    assert families.asian(x, S0, K, 0.2, r, T)[0] == 0.0  # only S0 remains: (S0/(s+1) - K)+ = 0
