@@ -34,6 +34,8 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+# Non-packed VALU lane operations per second: 256 CUs x 4 SIMD x 16 lanes x 2.4 GHz.
+VALU_LANE_OPS = 256 * 4 * 16 * 2.4e9
 CLASSES = ["pass_f32", "pass_cf32", "pass_f64", "sample", "kcols", "eval"]
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_c2_step.md")
 
@@ -81,14 +83,18 @@ def kernel_source_hash(cls="pass_f64"):
     return h.hexdigest()[:16]
 
 
-def committed_traffic(cls):
+def committed_traffic(cls, alg_per_launch):
     """HBM bytes per launch of `cls` from the committed counter summary, or
-    None when absent or taken on different sources of that class."""
+    None when absent, taken on different sources of that class, or taken on a
+    different launch mix (algorithmic bytes per launch differing by > 0.5%)."""
     if not os.path.exists(TRAFFIC_FILE):
         return None
     text = open(TRAFFIC_FILE).read()
     m = re.search(r"source_hash\[%s\]:\s*(\w+)" % cls, text)
     if not m or m.group(1) != kernel_source_hash(cls):
+        return None
+    m = re.search(r"alg_bytes_per_launch\[%s\]:\s*([0-9.eE+]+)" % cls, text)
+    if not m or abs(float(m.group(1)) - alg_per_launch) > 5e-3 * alg_per_launch:
         return None
     m = re.search(r"traffic_bytes_per_launch\[%s\]:\s*([0-9.eE+]+)" % cls, text)
     return float(m.group(1)) if m else None
@@ -243,7 +249,11 @@ def interp_leg(torch, fdwt, inputs, reps=3):
     N = p ** m
     err = float(torch.linalg.norm(back - f) / torch.linalg.norm(f))
     net.close()
+    rate = work / (tot * 1e-3)
     return {"workload": "p=3 m=14 (N=%d) s=10, product family a_j=j^-2, 65536 queries of 20 base-3 digits" % N,
+            "eval_roofline": {"bound": "alu", "achieved": rate, "peak": VALU_LANE_OPS / 5.0,
+                              "unit": "coordinate evaluations/s", "frac": rate / (VALU_LANE_OPS / 5.0),
+                              "ops_per_evaluation": "5 VALU (xor, compare, ffbh, shift, multiply) + 1 ds_bpermute"},
             "forward_inverse_ms": float(np.median(t_fi)), "points_per_s_fwd_inv": N / (np.median(t_fi) * 1e-3),
             "interp_ms": float(np.median(t_all)), "eval_ms": tot / n,
             "eval_coordinates_per_s": work / (tot * 1e-3), "round_trip_rel_err": err}
@@ -421,6 +431,9 @@ def main():
     stream = torch.cuda.current_stream()
 
     def step():
+        # Every step computes the kernel spectrum afresh (once: spline_coef
+        # and eff_dim share it through the handle's cache).
+        net.drop_spectrum()
         net.sample("exp", a, out=f)
         net.forward(f, out=ft)
         net.forward(fi, out=gi)
@@ -447,11 +460,14 @@ def main():
         if n:
             classes[cl] = {"ms_per_step": tot / args.steps, "launches_per_step": n / args.steps,
                            "avg_launch_ms": tot / n, "work_per_launch": work / n}
+            if cl != "eval":
+                gbs = work / (tot * 1e-3) / 1e9
+                classes[cl].update({"alg_GBs": gbs, "frac_hbm_peak": gbs / HBM_PEAK_GBS})
     fdwt.timing_enable(False)
     dom = max(classes, key=lambda k: classes[k]["ms_per_step"])
     dc = classes[dom]
     achieved = dc["work_per_launch"] / (dc["avg_launch_ms"] * 1e-3) / 1e9
-    traffic = committed_traffic(dom)
+    traffic = committed_traffic(dom, dc["work_per_launch"])
 
     # Plain forward float32 transform on its own (the two pass launches):
     # HIP events around each call, median of 50 after 10 warm-up calls, warm

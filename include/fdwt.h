@@ -79,6 +79,16 @@ int fdwt_net_points(const fdwt_net* net, float* x_dev, void* stream);
 
 void fdwt_net_free(fdwt_net* net);
 
+/* The handle caches the kernel spectrum K~ (float64, N values, complex for
+ * p odd) of the last kernel (alpha, gamma) used by fdwt_spline_coef,
+ * fdwt_walsh_interp or fdwt_eff_dim: the spectrum depends on the net and the
+ * kernel only, so calls with the same kernel reuse it (a call on another
+ * stream waits for it on the device).  fdwt_net_drop_spectrum forgets it
+ * (the next call recomputes it into the same memory, which the handle keeps
+ * until fdwt_net_free).  Calls on one handle must not overlap in time (they
+ * share its workspace and cache). */
+int fdwt_net_drop_spectrum(fdwt_net* net);
+
 /* ------------------------------------------------------------ sampling */
 
 #define FDWT_FAMILY_PRODUCT  1   /* f = prod_j (1 + a_j (x_j - 1/2))              */

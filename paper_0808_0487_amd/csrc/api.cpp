@@ -407,10 +407,17 @@ void fdwt_net_free(fdwt_net* h) {
   Net& n = h->n;
   DeviceGuard g(n.device);
   scratch_release(n.sc);
+  release_spectrum(n);
   if (n.d_xtab || n.d_ptab) (void)hipDeviceSynchronize();
   if (n.d_xtab) (void)hipFree(n.d_xtab);
   if (n.d_ptab) (void)hipFree(n.d_ptab);
   delete h;
+}
+
+int fdwt_net_drop_spectrum(fdwt_net* h) {
+  if (int rc = check_net(h)) return rc;
+  drop_spectrum(h->n);
+  return FDWT_OK;
 }
 
 int fdwt_net_digits(const fdwt_net* h, uint32_t* X_dev, void* stream) {
@@ -494,7 +501,9 @@ int fdwt_spline_coef(const fdwt_net* h, const fdwt_kernel* kern, int ft_type, co
     return fail(FDWT_EINVAL, "coefficients must be F32 (p = 2) or CF32 (p odd)");
   DeviceGuard g(h->n.device);
   Net& net = const_cast<Net&>(h->n);
-  return run_spline_coef(net, net.sc, kern, nullptr, ft_dev, c_dev, (hipStream_t)stream);
+  const void* gk = nullptr;
+  if (int rc = cached_spectrum(net, kern, &gk, (hipStream_t)stream)) return rc;
+  return run_spline_coef(net, net.sc, kern, gk, ft_dev, c_dev, (hipStream_t)stream);
   FDWT_GUARD_END
 }
 
@@ -534,7 +543,9 @@ int fdwt_walsh_interp(const fdwt_net* h, const fdwt_kernel* kern, const float* f
   }
   if (!c) c = (float*)((char*)ft + ftb);
   int rc = transform(net, false, FDWT_F32, f_dev, net.p == 2 ? FDWT_F32 : FDWT_CF32, ft, st);
-  if (!rc) rc = run_spline_coef(net, net.sc, kern, nullptr, ft, c, st);
+  const void* gk = nullptr;
+  if (!rc) rc = cached_spectrum(net, kern, &gk, st);
+  if (!rc) rc = run_spline_coef(net, net.sc, kern, gk, ft, c, st);
   if (!rc && nq > 0) rc = run_spline_eval(net, net.sc, kern, nullptr, c, nq, q_dev, sf_dev, st);
   (void)hipFreeAsync(ft, st);
   return rc;

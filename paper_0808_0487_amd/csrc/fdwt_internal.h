@@ -66,6 +66,13 @@ struct Net {
   uint64_t* d_ptab = nullptr;
   // Workspace and staging of the handle's own calls (grow-only).
   Scratch sc;
+  // Cached kernel spectrum (Section 3.2's K~, unnormalised float64) of the
+  // kernel whose (alpha, gamma) bytes are spec_key; spec_ready is recorded on
+  // the stream that computed it.
+  void* spec = nullptr;
+  size_t spec_bytes = 0;
+  std::vector<double> spec_key;
+  hipEvent_t spec_ready = nullptr;
 };
 
 }  // namespace fdwt
@@ -120,6 +127,11 @@ size_t kernel_tables_bytes(const Net& net);  // staged kernel tables (K' and R' 
 size_t spectrum_bytes(const Net& net);     // kernel spectrum: N doubles (p = 2), N complex doubles
 size_t spectrum_ws_bytes(const Net& net);
 int run_spectrum(Net& net, Scratch& sc, const fdwt_kernel* kern, void* gk, hipStream_t st);
+// The net's cached spectrum for kern, computed on st if absent or for another
+// kernel; st waits for it.  *gk receives the device pointer.
+int cached_spectrum(Net& net, const fdwt_kernel* kern, const void** gk, hipStream_t st);
+void drop_spectrum(Net& net);     // forget the cached spectrum (memory kept)
+void release_spectrum(Net& net);  // free it
 size_t spline_coef_ws_bytes(const Net& net, bool have_spectrum);
 int run_spline_coef(Net& net, Scratch& sc, const fdwt_kernel* kern, const void* gk, const void* ft, float* c,
                     hipStream_t st);

@@ -506,6 +506,52 @@ int run_spectrum(Net& net, Scratch& sc, const fdwt_kernel* kern, void* gk, hipSt
   return spectrum_into(net, sc, kern, sc.ws, gk, st);
 }
 
+int cached_spectrum(Net& net, const fdwt_kernel* kern, const void** gk, hipStream_t st) {
+  std::vector<double> key(1 + net.s);
+  key[0] = kern->alpha;
+  for (int j = 0; j < net.s; ++j) key[1 + j] = kern->gamma[j];
+  const bool hit = net.spec && key.size() == net.spec_key.size() &&
+                   std::memcmp(key.data(), net.spec_key.data(), key.size() * sizeof(double)) == 0;
+  if (!hit) {
+    const size_t need = spectrum_bytes(net);
+    if (net.spec && net.spec_bytes < need) {
+      FDWT_HIP(hipStreamSynchronize(st));
+      FDWT_HIP(hipFree(net.spec));
+      net.spec = nullptr;
+    }
+    if (!net.spec) {
+      if (hipMalloc(&net.spec, need) != hipSuccess) {
+        (void)hipGetLastError();
+        return fail(FDWT_ENOMEM, "kernel spectrum allocation failed");
+      }
+      net.spec_bytes = need;
+    }
+    if (!net.spec_ready) FDWT_HIP(hipEventCreateWithFlags(&net.spec_ready, hipEventDisableTiming));
+    net.spec_key.clear();  // invalid until computed
+    if (int rc = run_spectrum(net, net.sc, kern, net.spec, st)) return rc;
+    FDWT_HIP(hipEventRecord(net.spec_ready, st));
+    net.spec_key = key;
+  } else {
+    FDWT_HIP(hipStreamWaitEvent(st, net.spec_ready, 0));
+  }
+  *gk = net.spec;
+  return FDWT_OK;
+}
+
+void drop_spectrum(Net& net) { net.spec_key.clear(); }
+
+void release_spectrum(Net& net) {
+  if (net.spec) {
+    (void)hipDeviceSynchronize();
+    (void)hipFree(net.spec);
+  }
+  if (net.spec_ready) (void)hipEventDestroy(net.spec_ready);
+  net.spec = nullptr;
+  net.spec_bytes = 0;
+  net.spec_ready = nullptr;
+  net.spec_key.clear();
+}
+
 // ------------------------------------------------- spline coefficients
 struct CoefWs {
   void* gk;  // spectrum (when not given)
@@ -786,7 +832,10 @@ void eff_dim_finish(int s, const double* r, fdwt_effdim* out) {
 int run_eff_dim(Net& net, Scratch& sc, const fdwt_kernel* kern, const void* ft, fdwt_effdim* out, hipStream_t st) {
   const int ch = eff_dim_chunk(net, (size_t)12 << 30);
   const double* res_dev = nullptr;
-  int rc = eff_dim_enqueue(net, sc, kern, nullptr, ft, ch, nullptr, &res_dev, st);
+  const void* gk = nullptr;
+  int rc = cached_spectrum(net, kern, &gk, st);
+  if (rc) return rc;
+  rc = eff_dim_enqueue(net, sc, kern, gk, ft, ch, nullptr, &res_dev, st);
   if (rc) return rc;
   std::vector<double> res(2 * net.s + 2);
   FDWT_HIP(hipStreamSynchronize(st));

@@ -68,6 +68,7 @@ SIGNATURES = {
     "fdwt_net_digits": (_i, [_vp, _vp, _vp]),
     "fdwt_net_points": (_i, [_vp, _vp, _vp]),
     "fdwt_net_free": (None, [_vp]),
+    "fdwt_net_drop_spectrum": (_i, [_vp]),
     "fdwt_sample": (_i, [_vp, _i, _vp, _vp, _vp]),
     "fdwt_dwt_forward": (_i, [_vp, _i, _vp, _i, _vp, _vp]),
     "fdwt_dwt_inverse": (_i, [_vp, _i, _vp, _i, _vp, _vp]),
@@ -268,6 +269,10 @@ class Net:
         _check(lib().fdwt_sample(self.h, FAMILY[family], a.ctypes.data_as(ctypes.c_void_p), _ptr(out),
                                  _stream(stream)))
         return out
+
+    def drop_spectrum(self):
+        """Release the cached kernel spectrum (fdwt_net_drop_spectrum)."""
+        _check(lib().fdwt_net_drop_spectrum(self.h))
 
     # --------------------------------------------------------- transforms
     def forward(self, x, out=None, stream=None):

@@ -141,3 +141,26 @@ def test_prime_three_full_size_interpolation():
     sf = sf.cpu().numpy()
     assert nrel(sf[-len(idx):], fo[idx]) <= 1e-5
     assert np.all(np.isfinite(sf))
+
+
+def test_spectrum_cache_follows_the_kernel():
+    """The handle's cached spectrum is keyed by (alpha, gamma): switching
+    kernels recomputes it, switching back reproduces the first result bit for
+    bit, and a dropped cache gives the same coefficients again."""
+    announce("spectrum cache")
+    p, m, s, seed = 2, 12, 5, 41
+    C, X, gam, fo, net, kern, f = setup_case(p, m, s, seed)
+    kb = fdwt.Kernel(3.0, gam * 0.5)
+    ft = net.forward(f)
+    c1 = net.spline_coef(kern, ft).clone()
+    c2 = net.spline_coef(kb, ft).clone()
+    c3 = net.spline_coef(kern, ft).clone()
+    assert torch.equal(c1, c3) and not torch.equal(c1, c2)
+    fresh = fdwt.Net(p, m, s, C)
+    assert torch.equal(fresh.spline_coef(kb, fresh.forward(f)), c2)
+    net.drop_spectrum()
+    assert torch.equal(net.spline_coef(kern, ft), c1)
+    e1 = net.eff_dim(kern, ft)
+    net.drop_spectrum()
+    e2 = net.eff_dim(kern, ft)
+    assert np.array_equal(e1["var_trc"], e2["var_trc"]) and np.array_equal(e1["var_sup"], e2["var_sup"])
