@@ -6,7 +6,7 @@
  * Walsh Transform with an Application to Function Interpolation".
  *
  * Conventions used by every call
- *   - p in {2, 3, 5}; m >= 1; N = p^m <= 2^26 points; 1 <= s <= 64.
+ *   - p in {2, 3, 5, 7}; m >= 1; N = p^m <= 2^26 points; 1 <= s <= 64.
  *   - Point index n = n_0 + n_1 p + ... + n_{m-1} p^{m-1} (digit vector
  *     n_vec least significant first).  Coefficient index h = h_0 + h_1 p + ...
  *     where h_vec = C . k is the label of the coset of wavenumber k
@@ -62,7 +62,7 @@ typedef struct fdwt_net fdwt_net;
  * owns device tables and a workspace; free it with fdwt_net_free.  The
  * current HIP device at this call is the device of every later call.
  * Errors: FDWT_EINVAL (p not prime, m < 1, p^m > 2^26, s outside 1..64,
- * entry >= p, NULL), FDWT_EUNSUPPORTED (prime p other than 2, 3, 5),
+ * entry >= p, NULL), FDWT_EUNSUPPORTED (prime p other than 2, 3, 5, 7),
  * FDWT_ENOMEM, FDWT_EDEVICE. */
 int fdwt_net_generate(int p, int m, int s, const uint8_t* C_host, fdwt_net** out);
 
@@ -160,7 +160,7 @@ typedef struct {
 } fdwt_kernel;
 
 /* Query depth D: queries are D-digit base-p integers Q, q = Q p^-D, with
- * D = 32 (p = 2), 20 (p = 3), 13 (p = 5). */
+ * D = 32 (p = 2), 20 (p = 3), 13 (p = 5), 11 (p = 7). */
 int fdwt_query_depth(int p);
 
 /* Spline coefficients (Section 3.2, Eq. (splinecoef), then Algorithm 2):

@@ -86,7 +86,7 @@ void timed_end(hipEvent_t begin, hipStream_t st, int cls, double work) {
   g_recs.push_back({begin, e, cls, work});
 }
 
-int query_depth(int p) { return p == 2 ? 32 : (p == 3 ? 20 : (p == 5 ? 13 : 0)); }
+int query_depth(int p) { return p == 2 ? 32 : (p == 3 ? 20 : (p == 5 ? 13 : (p == 7 ? 11 : 0))); }
 
 // K'(z,0) and R'(z,0) of Section 4 for z whose first non-zero base-p digit is
 // digit i (i = 0: z = 0).
@@ -323,7 +323,7 @@ int fdwt_net_generate(int p, int m, int s, const uint8_t* C_host, fdwt_net** out
   if (!out || !C_host) return fail(FDWT_EINVAL, "NULL argument");
   *out = nullptr;
   if (!is_prime(p)) return fail(FDWT_EINVAL, "p must be prime");
-  if (p != 2 && p != 3 && p != 5) return fail(FDWT_EUNSUPPORTED, "only p = 2, 3, 5 are supported");
+  if (p != 2 && p != 3 && p != 5 && p != 7) return fail(FDWT_EUNSUPPORTED, "only p = 2, 3, 5, 7 are supported");
   if (m < 1) return fail(FDWT_EINVAL, "m must be >= 1");
   if (s < 1 || s > kMaxS) return fail(FDWT_EINVAL, "s must be in 1..64");
   if (ipow(p, m) > (int64_t(1) << kMaxLog2N)) return fail(FDWT_EINVAL, "p^m must be <= 2^26");

@@ -64,7 +64,7 @@ __device__ __forceinline__ uint64_t addmod_packed(uint64_t a, uint64_t b) {
 template <int P>
 struct OddCoords {
   static constexpr int K = P == 3 ? 4 : 2;               // low digits per table entry
-  static constexpr int PK = P == 3 ? 81 : 25;            // P^K
+  static constexpr int PK = P == 3 ? 81 : P * P;         // P^K
   static constexpr int NH = kChunk / PK + 2;             // high parts per group (at most)
   static constexpr size_t lds_bytes(int s) { return (size_t)s * (PK + NH) * 8; }
   const uint64_t* ptab;  // [s][m][P] (global)

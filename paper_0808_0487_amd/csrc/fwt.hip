@@ -399,6 +399,7 @@ static size_t lds_budget(size_t bytes) {
 static int kreg_for(int p, Kind work) {
   if (p == 2) return 4;
   if (p == 3) return 2;
+  if (p == 7) return 1;
   return work == K_CF32 ? 2 : 1;
 }
 
@@ -462,7 +463,7 @@ struct ReduceArgs {
 template <int P, bool INV, class Tin, class T, class Tout>
 static int launch_pass(const void* in, void* out, const PassGeom& g, int m, int batch, double scale,
                        int64_t col_in, int64_t col_out, Kind work, const ReduceArgs* red, hipStream_t st) {
-  constexpr int KMAX = (P == 2) ? 4 : ((P == 3 || sizeof(T) <= 8) ? 2 : 1);
+  constexpr int KMAX = (P == 2) ? 4 : (P == 7 ? 1 : ((P == 3 || sizeof(T) <= 8) ? 2 : 1));
   PassDesc d{};
   d.col_in = col_in;
   d.col_out = col_out;
@@ -567,8 +568,11 @@ static int pass_any(int p, bool inv, Kind ik, Kind wk, Kind ok, const void* in, 
     case 5:
       return inv ? pass_dispatch<5, true>(ik, wk, ok, in, out, g, m, batch, scale, ci, co, red, st)
                  : pass_dispatch<5, false>(ik, wk, ok, in, out, g, m, batch, scale, ci, co, red, st);
+    case 7:
+      return inv ? pass_dispatch<7, true>(ik, wk, ok, in, out, g, m, batch, scale, ci, co, red, st)
+                 : pass_dispatch<7, false>(ik, wk, ok, in, out, g, m, batch, scale, ci, co, red, st);
   }
-  return fail(FDWT_EUNSUPPORTED, "p must be 2, 3 or 5");
+  return fail(FDWT_EUNSUPPORTED, "p must be 2, 3, 5 or 7");
 }
 
 // ---------------------------------------------- p = 2 static-shape passes

@@ -202,10 +202,15 @@ static int coords(const Net& net, void* out, hipStream_t st) {
     if (int rc = allow_lds((const void*)k_coords_odd<3, MODE>, lds)) return rc;
     hipLaunchKernelGGL((k_coords_odd<3, MODE>), dim3(g), dim3(kChunk), lds, st, net.d_ptab, net.s, net.m,
                        net.N, inv_pm(net), out);
-  } else {
+  } else if (net.p == 5) {
     const size_t lds = OddCoords<5>::lds_bytes(net.s);
     if (int rc = allow_lds((const void*)k_coords_odd<5, MODE>, lds)) return rc;
     hipLaunchKernelGGL((k_coords_odd<5, MODE>), dim3(g), dim3(kChunk), lds, st, net.d_ptab, net.s, net.m,
+                       net.N, inv_pm(net), out);
+  } else {
+    const size_t lds = OddCoords<7>::lds_bytes(net.s);
+    if (int rc = allow_lds((const void*)k_coords_odd<7, MODE>, lds)) return rc;
+    hipLaunchKernelGGL((k_coords_odd<7, MODE>), dim3(g), dim3(kChunk), lds, st, net.d_ptab, net.s, net.m,
                        net.N, inv_pm(net), out);
   }
   FDWT_HIP(hipGetLastError());
@@ -228,10 +233,15 @@ static int sample_fam(const Net& net, const FamilyArgs& fa, float* f, unsigned g
     if (int rc = allow_lds((const void*)k_sample_odd<3, FAM>, lds)) return rc;
     hipLaunchKernelGGL((k_sample_odd<3, FAM>), dim3(g), dim3(kChunk), lds, st, net.d_ptab, fa, net.m, net.N,
                        inv_pm(net), 1.0 / (double)net.N, f);
-  } else {
+  } else if (net.p == 5) {
     const size_t lds = OddCoords<5>::lds_bytes(net.s) + 2 * kMaxS * 4;
     if (int rc = allow_lds((const void*)k_sample_odd<5, FAM>, lds)) return rc;
     hipLaunchKernelGGL((k_sample_odd<5, FAM>), dim3(g), dim3(kChunk), lds, st, net.d_ptab, fa, net.m, net.N,
+                       inv_pm(net), 1.0 / (double)net.N, f);
+  } else {
+    const size_t lds = OddCoords<7>::lds_bytes(net.s) + 2 * kMaxS * 4;
+    if (int rc = allow_lds((const void*)k_sample_odd<7, FAM>, lds)) return rc;
+    hipLaunchKernelGGL((k_sample_odd<7, FAM>), dim3(g), dim3(kChunk), lds, st, net.d_ptab, fa, net.m, net.N,
                        inv_pm(net), 1.0 / (double)net.N, f);
   }
   return FDWT_OK;

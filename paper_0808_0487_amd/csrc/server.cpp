@@ -99,7 +99,8 @@ Sizes request_sizes(const Request& r, size_t chunk_bytes) {
 int check_request(const fdwt_request* q) {
   if (!q) return fail(FDWT_EINVAL, "NULL request");
   if (q->kind != FDWT_JOB_INTERP && q->kind != FDWT_JOB_EFFDIM) return fail(FDWT_EINVAL, "unknown job kind");
-  if (q->p != 2 && q->p != 3 && q->p != 5) return fail(FDWT_EUNSUPPORTED, "only p = 2, 3, 5 are supported");
+  if (q->p != 2 && q->p != 3 && q->p != 5 && q->p != 7)
+    return fail(FDWT_EUNSUPPORTED, "only p = 2, 3, 5, 7 are supported");
   if (q->m < 1 || ipow(q->p, q->m) > (int64_t(1) << kMaxLog2N)) return fail(FDWT_EINVAL, "need 1 <= m, p^m <= 2^26");
   if (q->s < 1 || q->s > kMaxS) return fail(FDWT_EINVAL, "s must be in 1..64");
   if (!q->C_host || !q->a_host || !q->gamma_host) return fail(FDWT_EINVAL, "NULL request array");

@@ -448,7 +448,8 @@ static int launch_kernel_cols(const Net& net, const double* tk, const double* tr
                               hipStream_t st) {
   if (net.p == 2) return kcols_p<2>(net, tk, tr, c0, c1, out, st);
   if (net.p == 3) return kcols_p<3>(net, tk, tr, c0, c1, out, st);
-  return kcols_p<5>(net, tk, tr, c0, c1, out, st);
+  if (net.p == 5) return kcols_p<5>(net, tk, tr, c0, c1, out, st);
+  return kcols_p<7>(net, tk, tr, c0, c1, out, st);
 }
 
 static unsigned grid1(int64_t n) { return (unsigned)std::min<int64_t>((n + 255) / 256, 4096); }
@@ -586,8 +587,7 @@ int run_spline_coef(Net& net, Scratch& sc, const fdwt_kernel* kern, const void* 
   }
   void* ct = net.p == 2 ? (void*)c : (void*)w.ct;
   if (net.p == 2) hipLaunchKernelGGL(k_spec_div<2>, dim3(grid1(N)), dim3(256), 0, st, ft, GK, N, ct);
-  else if (net.p == 3) hipLaunchKernelGGL(k_spec_div<3>, dim3(grid1(N)), dim3(256), 0, st, ft, GK, N, ct);
-  else hipLaunchKernelGGL(k_spec_div<5>, dim3(grid1(N)), dim3(256), 0, st, ft, GK, N, ct);
+  else hipLaunchKernelGGL(k_spec_div<3>, dim3(grid1(N)), dim3(256), 0, st, ft, GK, N, ct);  // any odd p
   FDWT_HIP(hipGetLastError());
   // Algorithm 2 (no normalisation); p odd returns the real part.
   if (net.p == 2) return fwt_run_tmp(2, net.m, true, K_F32, ct, K_F32, K_F32, c, nullptr, 1, 1.0, st);
@@ -693,15 +693,15 @@ int run_spline_eval(Net& net, Scratch& sc, const fdwt_kernel* kern, const void* 
   const void* qv = q;
   if (p != 2) {
     if (p == 3) hipLaunchKernelGGL(k_query_prep<3>, dim3(grid1((int64_t)s * nq)), dim3(256), 0, st, q, nq, s, D, w.qs);
-    else hipLaunchKernelGGL(k_query_prep<5>, dim3(grid1((int64_t)s * nq)), dim3(256), 0, st, q, nq, s, D, w.qs);
+    else if (p == 5) hipLaunchKernelGGL(k_query_prep<5>, dim3(grid1((int64_t)s * nq)), dim3(256), 0, st, q, nq, s, D, w.qs);
+    else hipLaunchKernelGGL(k_query_prep<7>, dim3(grid1((int64_t)s * nq)), dim3(256), 0, st, q, nq, s, D, w.qs);
     FDWT_HIP(hipGetLastError());
     qv = w.qs;
   }
   const size_t lds = (size_t)s * kNS * xb + kNS * 4;  // p odd: high and low words of the strings
   hipEvent_t tb = timed_begin(st);
   if (p == 2) rc = launch_eval<2>(net, Xp, c, nq, qv, w.tl, w.partial, gy, ppc, lds, st);
-  else if (p == 3) rc = launch_eval<3>(net, Xp, c, nq, qv, w.tl, w.partial, gy, ppc, lds, st);
-  else rc = launch_eval<5>(net, Xp, c, nq, qv, w.tl, w.partial, gy, ppc, lds, st);
+  else rc = launch_eval<3>(net, Xp, c, nq, qv, w.tl, w.partial, gy, ppc, lds, st);  // any odd p: digit strings
   if (rc) return rc;
   timed_end(tb, st, FDWT_TC_EVAL, (double)nq * (double)N * s);
   hipLaunchKernelGGL(k_eval_finish, dim3(grid1(nq)), dim3(256), 0, st, w.partial, gy, nq, sf);
@@ -782,8 +782,7 @@ int eff_dim_enqueue(Net& net, Scratch& sc, const fdwt_kernel* kern, const void* 
   double* h0 = w.res + ncols + 1;  // h = 0 share of the total
   const double pm = (double)N;
   if (p == 2) hipLaunchKernelGGL(k_effdim_weights<2>, dim3(kRedBlocks), dim3(256), 0, st, ft, GK, N, pm, w.wts, w.qmc_partial);
-  else if (p == 3) hipLaunchKernelGGL(k_effdim_weights<3>, dim3(kRedBlocks), dim3(256), 0, st, ft, GK, N, pm, w.wts, w.qmc_partial);
-  else hipLaunchKernelGGL(k_effdim_weights<5>, dim3(kRedBlocks), dim3(256), 0, st, ft, GK, N, pm, w.wts, w.qmc_partial);
+  else hipLaunchKernelGGL(k_effdim_weights<3>, dim3(kRedBlocks), dim3(256), 0, st, ft, GK, N, pm, w.wts, w.qmc_partial);  // any odd p
   FDWT_HIP(hipGetLastError());
   for (int c0 = 0; c0 < ncols; c0 += ch) {
     const int c1 = std::min(ncols, c0 + ch);

@@ -12,14 +12,14 @@ no published dataset is involved):
   * test functions: the product family prod_j (1 + a_j (x_j - 1/2)), the
     exponential family exp(-sum_j w_j x_j^2) and the multiplicative function
     of the paper's Section 5.2;
-  * queries: uniform D-digit base-p integers per coordinate (D = 32, 20, 13
-    for p = 2, 3, 5).
+  * queries: uniform D-digit base-p integers per coordinate (D = 32, 20, 13,
+    11 for p = 2, 3, 5, 7).
 """
 import math
 
 import numpy as np
 
-QUERY_DEPTH = {2: 32, 3: 20, 5: 13}
+QUERY_DEPTH = {2: 32, 3: 20, 5: 13, 7: 11}
 
 
 def rng(seed):

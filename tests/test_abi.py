@@ -48,7 +48,7 @@ def test_invalid_arguments_rejected_before_device_work():
     C = np.zeros((1, 3, 3), dtype=np.uint8)
     ptr = C.ctypes.data_as(ctypes.c_void_p)
     assert L.fdwt_net_generate(4, 3, 1, ptr, ctypes.byref(h)) == fdwt.EINVAL
-    assert L.fdwt_net_generate(7, 3, 1, ptr, ctypes.byref(h)) == fdwt.EUNSUPPORTED
+    assert L.fdwt_net_generate(11, 3, 1, ptr, ctypes.byref(h)) == fdwt.EUNSUPPORTED
     assert L.fdwt_net_generate(2, 0, 1, ptr, ctypes.byref(h)) == fdwt.EINVAL
     assert L.fdwt_net_generate(2, 27, 1, ptr, ctypes.byref(h)) == fdwt.EINVAL
     assert L.fdwt_net_generate(2, 3, 65, ptr, ctypes.byref(h)) == fdwt.EINVAL

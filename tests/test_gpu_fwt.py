@@ -76,7 +76,8 @@ def test_p2_int32_bit_exact(m):
 
 
 @pytest.mark.parametrize("p,m", [(3, 1), (3, 2), (3, 7), (3, 8), (3, 9), (3, 12), (3, 15),
-                                 (5, 1), (5, 2), (5, 5), (5, 6), (5, 8), (5, 10)])
+                                 (5, 1), (5, 2), (5, 5), (5, 6), (5, 8), (5, 10),
+                                 (7, 1), (7, 2), (7, 4), (7, 5), (7, 7), (7, 9)])
 def test_odd_p_complex_sizes(p, m):
     announce("odd p forward/inverse", p, m)
     N = p ** m

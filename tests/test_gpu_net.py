@@ -14,7 +14,8 @@ pytestmark = pytest.mark.gpu
 @pytest.mark.parametrize("p,m,s,seed", [(2, 1, 1, 1), (2, 7, 3, 2), (2, 10, 4, 1), (2, 13, 8, 3),
                                         (2, 17, 5, 4), (2, 12, 64, 11), (3, 1, 2, 5), (3, 6, 4, 6),
                                         (3, 9, 3, 7), (3, 5, 64, 12), (5, 1, 1, 8), (5, 4, 3, 9),
-                                        (5, 7, 2, 10)])
+                                        (5, 7, 2, 10), (7, 1, 2, 15), (7, 4, 3, 16), (7, 8, 5, 17),
+                                        (7, 5, 64, 18)])
 def test_net_digits_bit_exact(p, m, s, seed):
     announce("net_digits", p, m, s, seed)
     C = inputs.upper_triangular_generators(p, m, s, seed)
@@ -105,7 +106,7 @@ def test_forward_of_sampled_family_equals_two_calls(p, m, s, family):
     assert nrel(got, ref.real if p == 2 else ref) <= 1e-5
 
 
-@pytest.mark.parametrize("p,m,s", [(2, 14, 8), (2, 10, 32), (3, 8, 5), (5, 5, 3)])
+@pytest.mark.parametrize("p,m,s", [(2, 14, 8), (2, 10, 32), (3, 8, 5), (5, 5, 3), (7, 4, 6)])
 def test_asian_payoff_against_oracle(p, m, s):
     """Section 5.3 payoff sampled on the device (double, inverse normal by
     A&S 26.2.23 + Newton) against the oracle (scipy ndtri) at every point."""

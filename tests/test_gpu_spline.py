@@ -10,7 +10,8 @@ from tests.gpu_common import announce, nrel, sample_indices
 
 pytestmark = pytest.mark.gpu
 
-CASES = [(2, 8, 4, 1), (2, 10, 4, 2), (2, 11, 6, 3), (3, 5, 3, 4), (3, 6, 4, 5), (5, 3, 3, 6), (5, 4, 2, 7)]
+CASES = [(2, 8, 4, 1), (2, 10, 4, 2), (2, 11, 6, 3), (3, 5, 3, 4), (3, 6, 4, 5), (5, 3, 3, 6), (5, 4, 2, 7),
+         (7, 3, 3, 13), (7, 4, 2, 14)]
 # wider s exercises every register length of the symmetric-polynomial state
 WIDE = [(2, 7, 12, 8), (2, 6, 30, 9), (2, 5, 64, 10), (3, 4, 20, 11), (5, 3, 40, 12)]
 

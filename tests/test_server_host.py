@@ -42,7 +42,7 @@ def test_effdim_chunk_bounds_job_memory():
 
 def test_request_validation_on_host():
     r = req("interp", 2, 8, 3)
-    r.p = 7
+    r.p = 11
     with pytest.raises(fdwt.FdwtError) as e:
         fdwt.request_bytes(r)
     assert e.value.code == fdwt.EUNSUPPORTED
