@@ -17,8 +17,9 @@
  *     are host memory owned by the caller.  Coordinate-major layouts are
  *     [s][N] (all N values of coordinate 1, then coordinate 2, ...).
  *   - stream is a hipStream_t (NULL = the null stream).  Calls enqueue work
- *     on it and return without waiting, except fdwt_eff_dim, which returns
- *     its scalars to the host and therefore synchronises the stream.
+ *     on it and return without waiting, except those that return host
+ *     results (fdwt_eff_dim, fdwt_split_cost, fdwt_kernel_tune,
+ *     fdwt_batch_check, fdwt_batch_autotune), which synchronise the stream.
  *   - Calls made with one net handle must be ordered on one stream (or
  *     synchronised by the caller): the handle owns a workspace they share.
  *   - Errors: every int-returning call returns FDWT_OK (0) or a negative
@@ -40,7 +41,7 @@ extern "C" {
 #define FDWT_ENOMEM       -2   /* device or host allocation failed            */
 #define FDWT_EDEVICE      -3   /* a HIP runtime call failed                   */
 #define FDWT_EBUDGET      -4   /* request exceeds a configured memory budget  */
-#define FDWT_EUNSUPPORTED -5   /* valid math, not supported here (e.g. p = 7) */
+#define FDWT_EUNSUPPORTED -5   /* valid math, not supported here (e.g. p = 11)*/
 
 /* Element types of transform inputs and outputs. */
 #define FDWT_F32  1   /* float                                               */

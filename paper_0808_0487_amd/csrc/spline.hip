@@ -26,6 +26,7 @@
 
 #include <algorithm>
 #include <cmath>
+#include <cstdlib>
 #include <cstring>
 
 namespace fdwt {
@@ -828,8 +829,19 @@ void eff_dim_finish(int s, const double* r, fdwt_effdim* out) {
     }
 }
 
+// Column budget of the one-call eff_dim (FDWT_EFFDIM_CHUNK_MB overrides the
+// 12 GiB default; results do not depend on it).
+static size_t effdim_budget() {
+  static const size_t b = [] {
+    const char* e = getenv("FDWT_EFFDIM_CHUNK_MB");
+    const long v = e ? atol(e) : 12 * 1024;
+    return (size_t)std::max(1L, v) << 20;
+  }();
+  return b;
+}
+
 int run_eff_dim(Net& net, Scratch& sc, const fdwt_kernel* kern, const void* ft, fdwt_effdim* out, hipStream_t st) {
-  const int ch = eff_dim_chunk(net, (size_t)12 << 30);
+  const int ch = eff_dim_chunk(net, effdim_budget());
   const double* res_dev = nullptr;
   const void* gk = nullptr;
   int rc = cached_spectrum(net, kern, &gk, st);
