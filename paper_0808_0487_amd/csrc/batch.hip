@@ -16,8 +16,9 @@
 //    tiles with a fixed stride (largest jobs first).
 //
 // In both no workgroup ever waits for another: the kernel boundary between
-// passes orders pass k before pass k+1 (on MI355X the L2 of each XCD is not
-// coherent with the others for ordinary device memory inside a kernel).
+// passes orders pass k before pass k+1 (the L2 caches of MI355X's XCDs are
+// not kept coherent with each other inside a kernel for ordinary device
+// memory, so cross-workgroup hand-offs within one launch are avoided).
 //
 // Precision FDWT_PREC_BF16X2: in each job's first pass the stages of index
 // digits 0..3 (16-point Walsh-Hadamard blocks) run on the matrix cores as
