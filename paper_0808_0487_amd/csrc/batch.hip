@@ -108,7 +108,7 @@ __global__ void __launch_bounds__(kBThreads) k_batch_fwd(const BJob* __restrict_
     d.kreg = 4;
     const int lo = I.tile % d.nlo, hi = I.tile / d.nlo;
     const int64_t base = (int64_t)lo * d.w + (int64_t)hi * d.shi;
-    const float* src = (ps == 0 ? J.in : J.out) + base;
+    const gptr<const float> src = to_global((ps == 0 ? J.in : J.out) + base);
     for (int e = threadIdx.x; e < d.E; e += blockDim.x) {
       const int c = e & (d.w - 1), i = e >> d.wdig;
       blds[pad(e)] = src[c + (int64_t)i * d.sd0];
@@ -129,7 +129,7 @@ __global__ void __launch_bounds__(kBThreads) k_batch_fwd(const BJob* __restrict_
       __syncthreads();
     }
     const float sc = (ps == J.npass - 1) ? J.scale : 1.0f;
-    float* dst = J.out + base;
+    const gptr<float> dst = to_global(J.out + base);
     for (int e = threadIdx.x; e < d.E; e += blockDim.x) {
       const int c = e & (d.w - 1), i = e >> d.wdig;
       dst[c + (int64_t)i * d.sd0] = blds[pad(e)] * sc;

@@ -93,7 +93,7 @@ __global__ void __launch_bounds__(1024) fwt_pass(const Tin* __restrict__ in, Tou
       lds[pad(e)] = cvt_in<Tin, T>(pre[k]);
     }
     lds_barrier();
-    if (lb + G < nb) prefetch(lb + G);
+    prefetch(lb + G < nb ? lb + G : lb);  // unconditional: exact wait counts
     for (int q = 0; q < d.r; q += d.kreg) {
       const int kk = min(d.kreg, d.r - q);
       if constexpr (KMAX >= 4) {
@@ -267,7 +267,7 @@ __global__ void __launch_bounds__((P2Shape<LOGE, WDIG>::THREADS))
     int col, tile;
     locate(l, col, tile);
     const Tin* colp = d.in_tab ? (const Tin*)d.in_tab[col] : in + (int64_t)col * d.col_in;
-    const Tin* src = colp + tile_base(tile) + goff0;
+    const gptr<const Tin> src = to_global(colp + tile_base(tile) + goff0);
 #pragma unroll
     for (int k = 0; k < EPT; ++k) pre[k] = src[k * gstep];
   };
@@ -302,13 +302,14 @@ __global__ void __launch_bounds__((P2Shape<LOGE, WDIG>::THREADS))
 #pragma unroll
         for (int k = 0; k < EPT; ++k) wcur[k] = wt[k * gstepS];
       }
-      if (lb + G < nb) prefetch(lb + G);
+      prefetch(lb + G < nb ? lb + G : lb);  // unconditional: exact wait counts
       P2Groups<LOGE, WDIG, 0, T, (EPI == EPI_REDUCE && sizeof(T) >= 8) ? 2 : 4, RDL>::run(lds, tid);
 #pragma unroll
       for (int k = 0; k < EPT; ++k) v[k] = lrowS[66 * k];
       reg_bfly<NS>(v);
       if constexpr (EPI == EPI_STORE) {
-        Tout* dst = (d.out_tab ? (Tout*)d.out_tab[col] : out + (int64_t)col * d.col_out) + base + goffS;
+        const gptr<Tout> dst =
+            to_global((d.out_tab ? (Tout*)d.out_tab[col] : out + (int64_t)col * d.col_out) + base + goffS);
 #pragma unroll
         for (int k = 0; k < EPT; ++k) dst[k * gstepS] = cvt_out<T, Tout>(v[k], d.scale, d.scale64);
       } else {
@@ -347,12 +348,16 @@ __global__ void __launch_bounds__((P2Shape<LOGE, WDIG>::THREADS))
 #pragma unroll
       for (int k = 0; k < EPT; ++k) wcur[k] = wt[k * gstep];
     }
-    if (lb + G < nb) prefetch(lb + G);
+    // Unconditional (the last round re-reads its own block): with no branch
+    // around the loads the compiler's wait counts stay exact, so waiting for
+    // this tile's weights does not wait for the next tile's elements.
+    prefetch(lb + G < nb ? lb + G : lb);
     // The grouped-sum variant keeps this tile's weights live across the
     // butterflies: 2-digit register groups keep it within 128 registers.
     P2Groups<LOGE, WDIG, 0, T, (EPI == EPI_REDUCE && sizeof(T) >= 8) ? 2 : 4>::run(lds, tid);
     if constexpr (EPI == EPI_STORE) {
-      Tout* dst = (d.out_tab ? (Tout*)d.out_tab[col] : out + (int64_t)col * d.col_out) + base + goff0;
+      const gptr<Tout> dst =
+          to_global((d.out_tab ? (Tout*)d.out_tab[col] : out + (int64_t)col * d.col_out) + base + goff0);
 #pragma unroll
       for (int k = 0; k < EPT; ++k) dst[k * gstep] = cvt_out<T, Tout>(lrow[cpad(k * TH)], d.scale, d.scale64);
     } else {

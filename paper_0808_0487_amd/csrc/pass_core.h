@@ -40,6 +40,18 @@ struct PassDesc {
 
 enum Epilogue { EPI_STORE = 0, EPI_REDUCE = 1 };
 
+// Pointers in the global address space.  A pointer read from memory (a
+// column table) is generic to the compiler, and accesses through it become
+// flat instructions, which the LDS wait counter also tracks: every wait for
+// LDS would then wait for the tile prefetch and the stores in flight as well.
+// Accesses through a gptr are global instructions.
+template <class T>
+using gptr = T __attribute__((address_space(1)))*;
+template <class T>
+__device__ __forceinline__ gptr<T> to_global(T* p) {
+  return (gptr<T>)p;
+}
+
 // ------------------------------------------------------------ conversions
 template <class Tin, class T>
 __device__ __forceinline__ T cvt_in(Tin v);
