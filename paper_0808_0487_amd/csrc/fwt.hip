@@ -236,7 +236,6 @@ __global__ void __launch_bounds__((P2Shape<LOGE, WDIG>::THREADS))
   constexpr int EPT = S::EPT, TH = S::THREADS;
   extern __shared__ __align__(16) unsigned char smem_raw[];
   T* lds = reinterpret_cast<T*>(smem_raw);
-  double* red = reinterpret_cast<double*>(smem_raw + ((cpad(S::E) * sizeof(T) + 15) & ~(size_t)15));
   const int G = gridDim.x;
   const int nb = d.ntiles * d.batch;
   const int hw = blockIdx.x;
@@ -322,13 +321,7 @@ __global__ void __launch_bounds__((P2Shape<LOGE, WDIG>::THREADS))
           if (col == d.h0_col && base + goffS + (int64_t)k * gstepS == 0) *d.h0_out = term;
         }
         for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off);
-        if (lane == 0) red[wv] = acc;
-        lds_barrier();
-        if (tid == 0) {
-          double t = 0.0;
-          for (int w = 0; w < TH / 64; ++w) t += red[w];
-          d.partial[(int64_t)col * d.ntiles + tile] = t;
-        }
+        if (lane == 0) d.partial[((int64_t)col * d.ntiles + tile) * (TH / 64) + wv] = acc;
       }
       lds_barrier();
     }
@@ -371,13 +364,7 @@ __global__ void __launch_bounds__((P2Shape<LOGE, WDIG>::THREADS))
         if (col == d.h0_col && base + goff0 + (int64_t)k * gstep == 0) *d.h0_out = term;
       }
       for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off);
-      if ((tid & 63) == 0) red[tid >> 6] = acc;
-      lds_barrier();
-      if (tid == 0) {
-        double t = 0.0;
-        for (int w = 0; w < TH / 64; ++w) t += red[w];
-        d.partial[(int64_t)col * d.ntiles + tile] = t;
-      }
+      if ((tid & 63) == 0) d.partial[((int64_t)col * d.ntiles + tile) * (TH / 64) + (tid >> 6)] = acc;
     }
     lds_barrier();
   }
@@ -460,7 +447,7 @@ static int device_cus() {
 // Optional grouped-sum epilogue of the last pass.
 struct ReduceArgs {
   const float2* wts;
-  double* partial;  // [batch][ntiles of the last pass]
+  double* partial;  // [batch][fwt_reduce_parts]
   double* h0_out;
   int h0_col;
 };
@@ -641,6 +628,13 @@ static int occupancy(const void* fn, int threads, size_t lds) {
   return n;
 }
 
+// Partial sums per column written by a reducing static pass: one per wave of
+// every tile.
+static int64_t p2_reduce_parts(int m, const P2Pass& g) {
+  const int threads = std::max(64, std::min(1024, (1 << g.loge) / 16));
+  return ((int64_t(1) << m) >> g.loge) * (threads / 64);
+}
+
 template <class Tin, class T, class Tout>
 static int launch_p2(const void* in, void* out, const P2Pass& g, int m, int batch, double scale,
                      const ReduceArgs* red, hipStream_t st, const void* const* in_tab = nullptr,
@@ -682,7 +676,7 @@ static int launch_p2(const void* in, void* out, const P2Pass& g, int m, int batc
   }
   d.in_tab = in_tab;
   d.out_tab = out_tab;
-  const size_t lds = ((size_t)cpad(E) * sizeof(T) + 15) / 16 * 16 + 16 * sizeof(double);
+  const size_t lds = ((size_t)cpad(E) * sizeof(T) + 15) / 16 * 16;
   if (int rc = allow_lds(fn, lds)) return rc;
   int64_t G = (int64_t)occupancy(fn, threads, lds) * device_cus();
   if (G >= nb) G = nb;
@@ -712,10 +706,10 @@ static bool p2_static_ok(int p, int m, Kind ik, Kind wk, Kind ok) {
 }
 
 static int run_p2(int m, Kind k, const void* in, void* out, void* tmp, int batch, double scale,
-                  const ReduceArgs* red, int64_t* last_tiles, hipStream_t st) {
+                  const ReduceArgs* red, int64_t* last_parts, hipStream_t st) {
   const std::vector<P2Pass> passes = plan_p2(m, kind_bytes(k));
   const size_t np = passes.size();
-  if (last_tiles) *last_tiles = (int64_t(1) << m) >> passes.back().loge;
+  if (last_parts) *last_parts = p2_reduce_parts(m, passes.back());
   if (np == 1) return p2_pass(k, in, out, passes[0], m, batch, scale, red, st);
   void* mid = red ? tmp : out;
   if (!mid) return fail(FDWT_EINVAL, "transform needs a workspace for its intermediate passes");
@@ -727,15 +721,15 @@ static int run_p2(int m, Kind k, const void* in, void* out, void* tmp, int batch
 
 static int run_passes(int p, int m, bool inverse, Kind in_kind, const void* in, Kind work_kind,
                       Kind out_kind, void* out, void* tmp, int batch, double scale, const ReduceArgs* red,
-                      int64_t* last_tiles, hipStream_t st) {
+                      int64_t* last_parts, hipStream_t st) {
   if (p2_static_ok(p, m, in_kind, work_kind, out_kind))
-    return run_p2(m, work_kind, in, out, tmp, batch, scale, red, last_tiles, st);
+    return run_p2(m, work_kind, in, out, tmp, batch, scale, red, last_parts, st);
   const int64_t N = ipow(p, m);
   std::vector<PassGeom> passes = plan(p, m, kind_bytes(work_kind), work_kind);
   const size_t np = passes.size();
-  if (last_tiles) {
+  if (last_parts) {
     const PassGeom& g = passes.back();
-    *last_tiles = N / (ipow(p, g.r) * ipow(p, g.wdig));
+    *last_parts = N / (ipow(p, g.r) * ipow(p, g.wdig));
   }
   if (np == 1)
     return pass_any(p, inverse, in_kind, work_kind, out_kind, in, out, passes[0], m, batch, scale, N, N,
@@ -769,12 +763,12 @@ int fwt_run(int p, int m, bool inverse, Kind in_kind, const void* in, Kind work_
 // Unnormalised forward transform of `batch` real float64 columns with the
 // grouped-sum epilogue in its last pass (no output stored).  tmp holds the
 // intermediate passes (batch columns of the working type); partial receives
-// [batch][tiles] sums, tiles returned in *tiles.
+// [batch][parts] partial sums, parts (fwt_reduce_parts) returned in *parts.
 int fwt_reduce_f64(int p, int m, const double* in, void* tmp, int batch, const float2* wts,
-                   double* partial, double* h0_out, int h0_col, int64_t* tiles, hipStream_t st) {
+                   double* partial, double* h0_out, int h0_col, int64_t* parts, hipStream_t st) {
   ReduceArgs red{wts, partial, h0_out, h0_col};
   const Kind wk = p == 2 ? K_F64 : K_CF64;
-  return run_passes(p, m, false, K_F64, in, wk, wk, tmp, tmp, batch, 1.0f, &red, tiles, st);
+  return run_passes(p, m, false, K_F64, in, wk, wk, tmp, tmp, batch, 1.0f, &red, parts, st);
 }
 
 // Plans of p = 2 float transforms for the batch tuner: the first pass takes
@@ -802,8 +796,8 @@ int fwt_p2_group_pass(int m, int emax, int level, const void* const* in_tab, voi
   return launch_p2<float, float, float>(nullptr, nullptr, passes[level], m, njobs, scale, nullptr, st, src, out_tab);
 }
 
-int64_t fwt_reduce_tiles(int p, int m, size_t elem_bytes) {
-  if (p == 2 && m >= 7) return (int64_t(1) << m) >> plan_p2(m, elem_bytes).back().loge;
+int64_t fwt_reduce_parts(int p, int m, size_t elem_bytes) {
+  if (p == 2 && m >= 7) return p2_reduce_parts(m, plan_p2(m, elem_bytes).back());
   std::vector<PassGeom> passes = plan(p, m, elem_bytes, elem_bytes >= 16 ? K_CF64 : K_F64);
   const PassGeom& g = passes.back();
   return ipow(p, m) / (ipow(p, g.r) * ipow(p, g.wdig));

@@ -25,8 +25,9 @@ struct PassDesc {
   double scale64;   // the same factor for double-based outputs
   // Grouped-sum epilogue (EPI_REDUCE): instead of storing, accumulate
   // sum_h wts[h].x * clamp(value(h) * wts[h].y, 0, 1) per column into
-  // partial[col * ntiles + tile]; the value at h = 0 of column h0_col goes to
-  // *h0_out as well.
+  // partial sums: partial[col * ntiles + tile] (generic pass) or one per wave,
+  // partial[(col * ntiles + tile) * waves + wave] (static p = 2 pass); the
+  // value at h = 0 of column h0_col goes to *h0_out as well.
   const float2* wts;
   double* partial;
   double* h0_out;

@@ -456,8 +456,8 @@ static int launch_kernel_cols(const Net& net, const double* tk, const double* tr
 static unsigned grid1(int64_t n) { return (unsigned)std::min<int64_t>((n + 255) / 256, 4096); }
 
 int fwt_reduce_f64(int p, int m, const double* in, void* tmp, int batch, const float2* wts, double* partial,
-                   double* h0_out, int h0_col, int64_t* tiles, hipStream_t st);
-int64_t fwt_reduce_tiles(int p, int m, size_t elem_bytes);
+                   double* h0_out, int h0_col, int64_t* parts, hipStream_t st);
+int64_t fwt_reduce_parts(int p, int m, size_t elem_bytes);
 
 // ------------------------------------------------------ kernel spectrum
 // Unnormalised float64 spectrum of the kernel data K(x_n, 0): p = 2, N
@@ -736,15 +736,15 @@ struct EffWs {
 static void eff_layout(const Net& net, bool have_gk, int ch, Carve& cv, EffWs& w) {
   const int ncols = 2 * net.s;
   const size_t wb = (net.p == 2) ? sizeof(double) : sizeof(double2);
-  const int64_t tiles = fwt_reduce_tiles(net.p, net.m, wb);
+  const int64_t parts = fwt_reduce_parts(net.p, net.m, wb);
   w.gk = have_gk ? nullptr : cv.take(spectrum_bytes(net));
   w.sw = have_gk ? nullptr : cv.take(spectrum_ws_bytes(net));
   w.tab = (double*)cv.take((size_t)2 * net.s * kTab * sizeof(double));
   w.wts = (float2*)cv.take((size_t)net.N * sizeof(float2));
   w.A = (double*)cv.take((size_t)ch * net.N * 8);
   w.B = cv.take((size_t)ch * net.N * wb);
-  w.partial = (double*)cv.take((size_t)ncols * tiles * sizeof(double) + kRedBlocks * sizeof(double));
-  w.qmc_partial = w.partial ? w.partial + (size_t)ncols * tiles : nullptr;
+  w.partial = (double*)cv.take((size_t)ncols * parts * sizeof(double) + kRedBlocks * sizeof(double));
+  w.qmc_partial = w.partial ? w.partial + (size_t)ncols * parts : nullptr;
   w.res = (double*)cv.take(eff_dim_res_bytes(net));
 }
 size_t eff_dim_ws_bytes(const Net& net, bool have_spectrum, int chunk) {
@@ -765,7 +765,7 @@ int eff_dim_enqueue(Net& net, Scratch& sc, const fdwt_kernel* kern, const void* 
   const int64_t N = net.N;
   const size_t wb = (p == 2) ? sizeof(double) : sizeof(double2);
   const int ncols = 2 * s;  // U_1..U_s, Q_1..Q_s (generator columns 1..2s)
-  const int64_t tiles = fwt_reduce_tiles(p, net.m, wb);
+  const int64_t parts = fwt_reduce_parts(p, net.m, wb);  // partial sums per column
   int rc = ensure_ws(sc, eff_dim_ws_bytes(net, gk_given != nullptr, ch), st);
   if (rc) return rc;
   Carve cv(sc.ws);
@@ -791,10 +791,10 @@ int eff_dim_enqueue(Net& net, Scratch& sc, const fdwt_kernel* kern, const void* 
     if (rc) return rc;
     const int h0_col = (s - 1 >= c0 && s - 1 < c1) ? s - 1 - c0 : -1;  // U_s
     int64_t t = 0;
-    rc = fwt_reduce_f64(p, net.m, w.A, w.B, c1 - c0, w.wts, w.partial + (size_t)c0 * tiles, h0, h0_col, &t, st);
+    rc = fwt_reduce_f64(p, net.m, w.A, w.B, c1 - c0, w.wts, w.partial + (size_t)c0 * parts, h0, h0_col, &t, st);
     if (rc) return rc;
   }
-  hipLaunchKernelGGL(k_sum_rows, dim3(ncols), dim3(256), 0, st, w.partial, (int)tiles, w.res);
+  hipLaunchKernelGGL(k_sum_rows, dim3(ncols), dim3(256), 0, st, w.partial, (int)parts, w.res);
   hipLaunchKernelGGL(k_sum_rows, dim3(1), dim3(256), 0, st, w.qmc_partial, kRedBlocks, w.res + ncols);
   FDWT_HIP(hipGetLastError());
   if (res_dev) *res_dev = w.res;
