@@ -458,6 +458,12 @@ static unsigned grid1(int64_t n) { return (unsigned)std::min<int64_t>((n + 255) 
 int fwt_reduce_f64(int p, int m, const double* in, void* tmp, int batch, const float2* wts, double* partial,
                    double* h0_out, int h0_col, int64_t* parts, hipStream_t st);
 int64_t fwt_reduce_parts(int p, int m, size_t elem_bytes);
+bool fwt_p2_split_ok(int m);
+int fwt_p2_f64_first(int m, const double* in, double* out, int batch, hipStream_t st);
+int fwt_p2_f64_reduce_rest(int m, double* data, int batch, const float2* wts, double* partial, double* h0_out,
+                           int h0_col, hipStream_t st);
+int fwt_p2_trunc_first(int m, int s, const uint32_t* xtab, int nbytes, const double* rtab, int ktab, double* out,
+                       hipStream_t st);
 
 // ------------------------------------------------------ kernel spectrum
 // Unnormalised float64 spectrum of the kernel data K(x_n, 0): p = 2, N
@@ -785,14 +791,26 @@ int eff_dim_enqueue(Net& net, Scratch& sc, const fdwt_kernel* kern, const void* 
   if (p == 2) hipLaunchKernelGGL(k_effdim_weights<2>, dim3(kRedBlocks), dim3(256), 0, st, ft, GK, N, pm, w.wts, w.qmc_partial);
   else hipLaunchKernelGGL(k_effdim_weights<3>, dim3(kRedBlocks), dim3(256), 0, st, ft, GK, N, pm, w.wts, w.qmc_partial);  // any odd p
   FDWT_HIP(hipGetLastError());
-  for (int c0 = 0; c0 < ncols; c0 += ch) {
-    const int c1 = std::min(ncols, c0 + ch);
-    rc = launch_kernel_cols(net, w.tab, w.tab + (size_t)s * kTab, c0 + 1, c1 + 1, w.A, st);
-    if (rc) return rc;
-    const int h0_col = (s - 1 >= c0 && s - 1 < c1) ? s - 1 - c0 : -1;  // U_s
-    int64_t t = 0;
-    rc = fwt_reduce_f64(p, net.m, w.A, w.B, c1 - c0, w.wts, w.partial + (size_t)c0 * parts, h0, h0_col, &t, st);
-    if (rc) return rc;
+  if (p == 2 && ch == ncols && fwt_p2_split_ok(net.m)) {
+    // All columns at once: the U_d columns are generated inside the first
+    // pass of their transforms (B columns 0..s-1); only the Q_j columns go
+    // through memory (kernel data in A, first pass into B columns s..2s-1).
+    double* B = (double*)w.B;
+    const double* tr = w.tab + (size_t)s * kTab;
+    if ((rc = launch_kernel_cols(net, w.tab, tr, s + 1, ncols + 1, w.A, st))) return rc;
+    if ((rc = fwt_p2_trunc_first(net.m, s, net.d_xtab, net.nbytes, tr, kTab, B, st))) return rc;
+    if ((rc = fwt_p2_f64_first(net.m, w.A, B + (size_t)s * N, s, st))) return rc;
+    if ((rc = fwt_p2_f64_reduce_rest(net.m, B, ncols, w.wts, w.partial, h0, s - 1, st))) return rc;
+  } else {
+    for (int c0 = 0; c0 < ncols; c0 += ch) {
+      const int c1 = std::min(ncols, c0 + ch);
+      rc = launch_kernel_cols(net, w.tab, w.tab + (size_t)s * kTab, c0 + 1, c1 + 1, w.A, st);
+      if (rc) return rc;
+      const int h0_col = (s - 1 >= c0 && s - 1 < c1) ? s - 1 - c0 : -1;  // U_s
+      int64_t t = 0;
+      rc = fwt_reduce_f64(p, net.m, w.A, w.B, c1 - c0, w.wts, w.partial + (size_t)c0 * parts, h0, h0_col, &t, st);
+      if (rc) return rc;
+    }
   }
   hipLaunchKernelGGL(k_sum_rows, dim3(ncols), dim3(256), 0, st, w.partial, (int)parts, w.res);
   hipLaunchKernelGGL(k_sum_rows, dim3(1), dim3(256), 0, st, w.qmc_partial, kRedBlocks, w.res + ncols);

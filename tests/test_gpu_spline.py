@@ -6,6 +6,7 @@ import torch
 
 from oracle import anova, families, kernel, net as onet
 from paper_0808_0487_amd import fdwt, inputs
+from tests._libdwt import lib_dwt
 from tests.gpu_common import announce, nrel, sample_indices
 
 pytestmark = pytest.mark.gpu
@@ -120,6 +121,45 @@ def test_effdim_invariants_at_scale(p, m, s):
     assert res["var_total"] - res["var_total_h0"] <= res["var_qmc"] * (1 + 1e-6)
     _, _, total = anova.product_anova(anova.product_family_component_variance(a))
     assert 0.5 * total <= res["var_total"] <= 1.5 * total
+
+
+@pytest.mark.parametrize("m,s,seed", [(15, 6, 21), (16, 10, 22), (17, 20, 23), (15, 64, 24)])
+def test_effdim_two_pass_sizes_against_spectral_route(m, s, seed):
+    """p = 2 nets with two-pass transforms (m >= 15; tiles of 2^12, 2^13 and
+    2^14 in the first pass, where the truncation columns are generated inside
+    that pass): var_trc and var_sup against Eq. (sig2sfu) summed over u,
+    sigma^2 = sum_h |f~(h)|^2 rho(h) with rho = g~(h) / K~(h)^2 clamped into
+    [0, 1], all in float64 from the oracle's kernel values and the FFT over
+    the digit tensor (the route the CPU pins tie to the direct double sums)."""
+    announce("eff_dim two-pass", 2, m, s, seed)
+    p, N = 2, 2 ** m
+    C = inputs.upper_triangular_generators(p, m, s, seed)
+    X = onet.net_int(p, m, C)
+    gam = inputs.kernel_weights(s)
+    f32 = families.product(X / float(N), inputs.family_params("product", s, scale=1.0, alpha=2.0)).astype(np.float32)
+    net = fdwt.Net(p, m, s, C)
+    res = net.eff_dim(fdwt.Kernel(2.0, gam), net.forward(torch.from_numpy(f32).cuda()))
+    fsq = np.abs(lib_dwt(p, m, f32.astype(np.float64))) ** 2
+    Kt = lib_dwt(p, m, kernel.kernel_K(p, 2.0, gam, m, X, np.zeros((s, 1), dtype=np.int64))).real
+    r = [gam[j] ** 2 * kernel.rprime_closed(p, 2.0, kernel.first_diff_digit(p, m, X[j], 0)) for j in range(s)]
+
+    def var(g):
+        return float(np.sum(fsq * np.clip(lib_dwt(p, m, g).real / Kt ** 2, 0.0, 1.0)))
+
+    trc, sup = np.zeros(s + 1), np.zeros(s + 1)
+    prod = np.ones(N)
+    for d in range(1, s + 1):
+        prod = prod * (1.0 + r[d - 1])
+        trc[d] = var(prod - 1.0)
+    e = anova.esp(r)
+    for d in range(1, s + 1):
+        sup[d] = sup[d - 1] + var(e[d])
+    assert np.allclose(res["var_trc"], trc, rtol=1e-5, atol=1e-7 * trc[s])
+    assert np.allclose(res["var_sup"], sup, rtol=1e-5, atol=1e-7 * trc[s])
+    assert res["var_total_h0"] == pytest.approx(fsq[0] * np.clip((prod[:] - 1.0).mean() / Kt[0] ** 2, 0, 1),
+                                                rel=1e-5)
+    dt, ds = anova.effective_dims(trc, sup)
+    assert (res["d_trc"], res["d_sup"]) == (dt, ds)
 
 
 def test_prime_three_full_size_interpolation():
