@@ -170,13 +170,15 @@ __global__ void __launch_bounds__(256) k_effdim_weights(const void* __restrict__
 }
 
 // Sum nblk partials per row in a fixed order: out[row] = sum_b in[row*nblk + b].
-__global__ void __launch_bounds__(256) k_sum_rows(const double* __restrict__ in, int nblk, double* __restrict__ out) {
-  __shared__ double red[256];
+constexpr int kSumThreads = 1024;
+__global__ void __launch_bounds__(kSumThreads) k_sum_rows(const double* __restrict__ in, int nblk,
+                                                          double* __restrict__ out) {
+  __shared__ double red[kSumThreads];
   double a = 0.0;
-  for (int b = threadIdx.x; b < nblk; b += blockDim.x) a += in[(int64_t)blockIdx.x * nblk + b];
+  for (int b = threadIdx.x; b < nblk; b += kSumThreads) a += in[(int64_t)blockIdx.x * nblk + b];
   red[threadIdx.x] = a;
   __syncthreads();
-  for (int off = 128; off > 0; off >>= 1) {
+  for (int off = kSumThreads / 2; off > 0; off >>= 1) {
     if (threadIdx.x < off) red[threadIdx.x] += red[threadIdx.x + off];
     __syncthreads();
   }
@@ -812,8 +814,8 @@ int eff_dim_enqueue(Net& net, Scratch& sc, const fdwt_kernel* kern, const void* 
       if (rc) return rc;
     }
   }
-  hipLaunchKernelGGL(k_sum_rows, dim3(ncols), dim3(256), 0, st, w.partial, (int)parts, w.res);
-  hipLaunchKernelGGL(k_sum_rows, dim3(1), dim3(256), 0, st, w.qmc_partial, kRedBlocks, w.res + ncols);
+  hipLaunchKernelGGL(k_sum_rows, dim3(ncols), dim3(kSumThreads), 0, st, w.partial, (int)parts, w.res);
+  hipLaunchKernelGGL(k_sum_rows, dim3(1), dim3(kSumThreads), 0, st, w.qmc_partial, kRedBlocks, w.res + ncols);
   FDWT_HIP(hipGetLastError());
   if (res_dev) *res_dev = w.res;
   if (res_host) FDWT_HIP(hipMemcpyAsync(res_host, w.res, eff_dim_res_bytes(net), hipMemcpyDeviceToHost, st));
@@ -913,7 +915,7 @@ int run_split_cost(Net& tr, Scratch& sc, const uint32_t* delta, const float* ft,
   FDWT_HIP(hipGetLastError());
   if ((rc = fwt_run_tmp(2, tr.m, true, K_F64, g, K_F64, K_F64, g, nullptr, 1, 1.0, st))) return rc;
   hipLaunchKernelGGL(k_sq_diff, dim3(kRedBlocks), dim3(256), 0, st, fval, g, N, partial, sf_out);
-  hipLaunchKernelGGL(k_sum_rows, dim3(1), dim3(256), 0, st, partial, kRedBlocks, res);
+  hipLaunchKernelGGL(k_sum_rows, dim3(1), dim3(kSumThreads), 0, st, partial, kRedBlocks, res);
   FDWT_HIP(hipGetLastError());
   FDWT_HIP(hipStreamSynchronize(st));
   FDWT_HIP(hipMemcpy(cost, res, sizeof(double), hipMemcpyDeviceToHost));
