@@ -370,25 +370,28 @@ __global__ void __launch_bounds__((P2Shape<LOGE, WDIG>::THREADS))
   }
 }
 
-// First (contiguous) pass of the float64 transforms of the truncation columns
-// U_d = prod_{j<=d} (1 + a_j) - 1, d = 1..s (Section 4), with the column values
-// generated in registers instead of read from memory.  a_j = gamma_j^2 R'(x_{n,j})
-// depends only on the first non-zero digit of x_{n,j}: rtab[j][t] (t = the
-// leading-zero count of X_j(n) in m bits; t = m for X = 0).  Each workgroup
-// takes whole tiles and runs j = 1..s in order; a thread keeps U for its 16
-// points (n = tile E + tid + k TH) in registers from one column to the next,
-// U_j = U_{j-1} + a_j (1 + U_{j-1}).  X_j(n) is the XOR of the generator
-// columns of the set bits of n (Definition of a digital net, p = 2); the
-// columns and the R' tables are staged in LDS, so the loop's only memory
-// accesses are its stores.
-struct TruncGen {
+// First (contiguous) pass of float64 transforms whose input columns are
+// generated in registers instead of read from memory (p = 2, Section 4):
+//  * truncation columns (KCOL false): U_d = prod_{j<=d} (1 + a_j) - 1,
+//    d = 1..s, with a_j = gamma_j^2 R'(x_{n,j}) = tab[j][t];
+//  * kernel column (KCOL true): K(x_n, 0) = prod_j tab[j][t] with
+//    tab[j][t] = 1 + gamma_j K'(x_{n,j}, 0).
+// t is the index of the first non-zero digit of x_{n,j} (the leading-zero
+// count of X_j(n) in m bits; t = m for X = 0).  Each workgroup takes whole
+// tiles and runs j = 1..s in order; a thread keeps the running value for its
+// 16 points (n = tile E + tid + k TH) in registers (for U: U_j = U_{j-1} +
+// a_j (1 + U_{j-1}), one column stored per j).  X_j(n) is the XOR of the
+// generator columns of the set bits of n (Definition of a digital net,
+// p = 2); the columns and the tables are staged in LDS, so the loop's only
+// memory accesses are its stores.
+struct ColGen {
   const uint32_t* xtab;  // [s][nbytes][256]: X_j of byte value v at byte b
-  const double* rtab;    // [s][ktab]
+  const double* tab;     // [s][ktab]
   int nbytes, s, m, ktab;
 };
 
-template <int LOGE>
-__global__ void __launch_bounds__((P2Shape<LOGE, 0>::THREADS)) fwt_p2_trunc(TruncGen g, double* out, PassDesc d) {
+template <int LOGE, bool KCOL>
+__global__ void __launch_bounds__((P2Shape<LOGE, 0>::THREADS)) fwt_p2_gen(ColGen g, double* out, PassDesc d) {
   using S = P2Shape<LOGE, 0>;
   constexpr int EPT = S::EPT, TH = S::THREADS, TB = LOGE - 4;  // tid has TB bits
   static_assert(LOGE >= 10 && EPT == 16, "16 elements per thread");
@@ -399,7 +402,7 @@ __global__ void __launch_bounds__((P2Shape<LOGE, 0>::THREADS)) fwt_p2_trunc(Trun
   double* rl = lds + ((cpad(S::E) + 1) & ~1);                    // [s][m + 1]
   uint32_t* cl = reinterpret_cast<uint32_t*>(rl + s * (m + 1));   // [s][m]: generator columns
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
-  for (int i = tid; i < s * (m + 1); i += TH) rl[i] = g.rtab[(i / (m + 1)) * g.ktab + i % (m + 1)];
+  for (int i = tid; i < s * (m + 1); i += TH) rl[i] = g.tab[(i / (m + 1)) * g.ktab + i % (m + 1)];
   for (int i = tid; i < s * m; i += TH) {
     const int j = i / m, c = i % m;
     cl[i] = g.xtab[((size_t)j * g.nbytes + (c >> 3)) * 256 + (1 << (c & 7))];
@@ -411,11 +414,30 @@ __global__ void __launch_bounds__((P2Shape<LOGE, 0>::THREADS)) fwt_p2_trunc(Trun
   double* lrowS = lds + cpad(lane + 1024 * wv);
   const uint32_t goffS = (uint32_t)(lane + 1024 * wv);
   const int sh = 32 - m;
+  // Pass over one generated column of the tile: the same stage groups as
+  // fwt_p2's first pass, then a coalesced store.
+  auto transform_store = [&](const double (&u)[EPT], int col) {
+    double v[EPT];
+#pragma unroll
+    for (int k = 0; k < EPT; ++k) v[k] = u[k];
+    reg_bfly<4>(v);
+#pragma unroll
+    for (int k = 0; k < EPT; ++k) lrow[cpad(k * TH)] = v[k];
+    lds_barrier();
+    P2Groups<LOGE, 0, 0, double, 4, 6>::run(lds, tid);
+#pragma unroll
+    for (int k = 0; k < EPT; ++k) v[k] = lrowS[66 * k];
+    reg_bfly<NS>(v);
+    const gptr<double> dst = to_global(out + (int64_t)col * d.col_out + ((int64_t)lb << LOGE) + goffS);
+#pragma unroll
+    for (int k = 0; k < EPT; ++k) dst[k * 64] = v[k];
+    lds_barrier();
+  };
   for (; lb < d.ntiles; lb += G) {
     const uint32_t n0 = (uint32_t)lb << LOGE;
     double u[EPT];
 #pragma unroll
-    for (int k = 0; k < EPT; ++k) u[k] = 0.0;
+    for (int k = 0; k < EPT; ++k) u[k] = KCOL ? 1.0 : 0.0;
     for (int j = 0; j < s; ++j) {
       const uint32_t* cj = cl + j * m;
       uint32_t xt = 0;  // X_j(tid) ^ X_j(n0)
@@ -432,26 +454,14 @@ __global__ void __launch_bounds__((P2Shape<LOGE, 0>::THREADS)) fwt_p2_trunc(Trun
         for (int k = 0; k < (1 << b); ++k) kx[k + (1 << b)] = kx[k] ^ cb;
       }
       const double* rj = rl + j * (m + 1);
-      double v[EPT];
 #pragma unroll
       for (int k = 0; k < EPT; ++k) {
         const double a = rj[(int)__clz(xt ^ kx[k]) - sh];
-        u[k] = fma(a, 1.0 + u[k], u[k]);
-        v[k] = u[k];
+        u[k] = KCOL ? u[k] * a : fma(a, 1.0 + u[k], u[k]);
       }
-      reg_bfly<4>(v);
-#pragma unroll
-      for (int k = 0; k < EPT; ++k) lrow[cpad(k * TH)] = v[k];
-      lds_barrier();
-      P2Groups<LOGE, 0, 0, double, 4, 6>::run(lds, tid);
-#pragma unroll
-      for (int k = 0; k < EPT; ++k) v[k] = lrowS[66 * k];
-      reg_bfly<NS>(v);
-      const gptr<double> dst = to_global(out + (int64_t)j * d.col_out + ((int64_t)lb << LOGE) + goffS);
-#pragma unroll
-      for (int k = 0; k < EPT; ++k) dst[k * 64] = v[k];
-      lds_barrier();
+      if constexpr (!KCOL) transform_store(u, j);
     }
+    if constexpr (KCOL) transform_store(u, 0);
   }
 }
 
@@ -884,7 +894,7 @@ int fwt_p2_group_pass(int m, int emax, int level, const void* const* in_tab, voi
 
 // The p = 2 float64 transform of a batch of columns split after its first
 // pass, for callers that produce part of the first pass's output with
-// fwt_p2_trunc_first: whether the plan for m has that shape (two or more
+// fwt_p2_gen_first: whether the plan for m has that shape (two or more
 // passes, the first contiguous with 2^12..2^14-element tiles), the first pass
 // alone (in -> out), and the remaining passes in place with the grouped-sum
 // epilogue in the last (partial as for fwt_reduce_f64).
@@ -910,22 +920,27 @@ int fwt_p2_f64_reduce_rest(int m, double* data, int batch, const float2* wts, do
   return p2_pass(K_F64, data, data, v.back(), m, batch, 1.0, &red, st);
 }
 
-// First pass of the transforms of the s truncation columns, generated in the
-// kernel (fwt_p2_trunc): out receives s columns of 2^m doubles.
-int fwt_p2_trunc_first(int m, int s, const uint32_t* xtab, int nbytes, const double* rtab, int ktab, double* out,
-                       hipStream_t st) {
+// First pass of the transforms of generated columns (fwt_p2_gen): the s
+// truncation columns U_d from the R' table (kcol false: out receives s
+// columns), or the kernel column K from the K' table (kcol true: one column).
+int fwt_p2_gen_first(int m, int s, const uint32_t* xtab, int nbytes, const double* tab, int ktab, bool kcol,
+                     double* out, hipStream_t st) {
   if (!fwt_p2_split_ok(m) || s < 1 || s > 64 || ktab <= m) return fail(FDWT_EINVAL, "bad generated-column pass");
   const P2Pass g = plan_p2(m, 8)[0];
-  const void* fn = g.loge == 14 ? (const void*)fwt_p2_trunc<14>
-                   : g.loge == 13 ? (const void*)fwt_p2_trunc<13> : (const void*)fwt_p2_trunc<12>;
+  const void* fn = nullptr;
+  if (kcol) fn = g.loge == 14 ? (const void*)fwt_p2_gen<14, true>
+                 : g.loge == 13 ? (const void*)fwt_p2_gen<13, true> : (const void*)fwt_p2_gen<12, true>;
+  else fn = g.loge == 14 ? (const void*)fwt_p2_gen<14, false>
+            : g.loge == 13 ? (const void*)fwt_p2_gen<13, false> : (const void*)fwt_p2_gen<12, false>;
   const int64_t N = int64_t(1) << m;
   const int E = 1 << g.loge;
   const int threads = E / 16;
+  const int ncol = kcol ? 1 : s;
   PassDesc d{};
   d.col_in = N;
   d.col_out = N;
   d.ntiles = (int)(N / E);
-  d.batch = s;
+  d.batch = ncol;
   d.h0_col = -1;
   const size_t lds = (size_t)((cpad(E) + 1) & ~1) * sizeof(double) + (size_t)s * (m + 1) * sizeof(double) +
                      (size_t)s * m * sizeof(uint32_t);
@@ -934,12 +949,22 @@ int fwt_p2_trunc_first(int m, int s, const uint32_t* xtab, int nbytes, const dou
   if (G >= d.ntiles) G = d.ntiles;
   if (G >= 64) G -= G % 8;
   d.xcd = (G % 8 == 0 && G >= 64) ? 1 : 0;
-  TruncGen tg{xtab, rtab, nbytes, s, m, ktab};
-  void* args[] = {(void*)&tg, (void*)&out, (void*)&d};
+  ColGen cg{xtab, tab, nbytes, s, m, ktab};
+  void* args[] = {(void*)&cg, (void*)&out, (void*)&d};
   hipEvent_t tb = timed_begin(st);
   FDWT_HIP(hipLaunchKernel(fn, dim3((unsigned)G), dim3(threads), args, lds, st));
-  timed_end(tb, st, FDWT_TC_PASS_F64, (double)N * s * sizeof(double));
+  timed_end(tb, st, FDWT_TC_PASS_F64, (double)N * ncol * sizeof(double));
   return FDWT_OK;
+}
+
+// The passes after the first of an unnormalised p = 2 float64 transform, in
+// place (the first pass's output already in data).
+int fwt_p2_f64_rest(int m, double* data, int batch, hipStream_t st) {
+  if (!fwt_p2_split_ok(m)) return fail(FDWT_EINVAL, "no split plan for this m");
+  const std::vector<P2Pass> v = plan_p2(m, 8);
+  int rc = FDWT_OK;
+  for (size_t i = 1; !rc && i < v.size(); ++i) rc = p2_pass(K_F64, data, data, v[i], m, batch, 1.0, nullptr, st);
+  return rc;
 }
 
 int64_t fwt_reduce_parts(int p, int m, size_t elem_bytes) {

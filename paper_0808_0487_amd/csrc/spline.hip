@@ -464,8 +464,9 @@ bool fwt_p2_split_ok(int m);
 int fwt_p2_f64_first(int m, const double* in, double* out, int batch, hipStream_t st);
 int fwt_p2_f64_reduce_rest(int m, double* data, int batch, const float2* wts, double* partial, double* h0_out,
                            int h0_col, hipStream_t st);
-int fwt_p2_trunc_first(int m, int s, const uint32_t* xtab, int nbytes, const double* rtab, int ktab, double* out,
-                       hipStream_t st);
+int fwt_p2_gen_first(int m, int s, const uint32_t* xtab, int nbytes, const double* tab, int ktab, bool kcol,
+                     double* out, hipStream_t st);
+int fwt_p2_f64_rest(int m, double* data, int batch, hipStream_t st);
 
 // ------------------------------------------------------ kernel spectrum
 // Unnormalised float64 spectrum of the kernel data K(x_n, 0): p = 2, N
@@ -502,6 +503,11 @@ static int spectrum_into(Net& net, Scratch& sc, const fdwt_kernel* kern, void* w
     rc = upload(sc, htab.data(), htab.size() * sizeof(double), w.tab, st);
     if (rc) return rc;
     tab = w.tab;
+  }
+  if (net.p == 2 && fwt_p2_split_ok(net.m)) {
+    // K generated inside the first pass of its transform (no column in memory).
+    if ((rc = fwt_p2_gen_first(net.m, net.s, net.d_xtab, net.nbytes, tab, kTab, true, (double*)gk, st))) return rc;
+    return fwt_p2_f64_rest(net.m, (double*)gk, 1, st);
   }
   double* A = net.p == 2 ? (double*)gk : w.A;
   rc = launch_kernel_cols(net, tab, tab + (size_t)net.s * kTab, 0, 1, A, st);
@@ -800,7 +806,7 @@ int eff_dim_enqueue(Net& net, Scratch& sc, const fdwt_kernel* kern, const void* 
     double* B = (double*)w.B;
     const double* tr = w.tab + (size_t)s * kTab;
     if ((rc = launch_kernel_cols(net, w.tab, tr, s + 1, ncols + 1, w.A, st))) return rc;
-    if ((rc = fwt_p2_trunc_first(net.m, s, net.d_xtab, net.nbytes, tr, kTab, B, st))) return rc;
+    if ((rc = fwt_p2_gen_first(net.m, s, net.d_xtab, net.nbytes, tr, kTab, false, B, st))) return rc;
     if ((rc = fwt_p2_f64_first(net.m, w.A, B + (size_t)s * N, s, st))) return rc;
     if ((rc = fwt_p2_f64_reduce_rest(net.m, B, ncols, w.wts, w.partial, h0, s - 1, st))) return rc;
   } else {

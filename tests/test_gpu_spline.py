@@ -83,10 +83,12 @@ def test_effective_dimension_variances(p, m, s, seed):
     assert res["var_total"] - res["var_total_h0"] <= res["var_qmc"] * (1 + 1e-6)
 
 
-def test_kernel_section_closed_form():
+@pytest.mark.parametrize("m,s", [(9, 5), (24, 2)])
+def test_kernel_section_closed_form(m, s):
     """f = K(., x_v): every variance has the closed form of the kernel
-    section (Section 4 product structure)."""
-    p, m, s = 2, 9, 5
+    section (Section 4 product structure).  m = 24 is the full-size plan
+    (generated truncation columns, half-width grouped-sum pass)."""
+    p = 2
     announce("kernel section", p, m, s)
     C = inputs.upper_triangular_generators(p, m, s, 9)
     X = onet.net_int(p, m, C)
