@@ -388,6 +388,7 @@ struct ColGen {
   const uint32_t* xtab;  // [s][nbytes][256]: X_j of byte value v at byte b
   const double* tab;     // [s][ktab]
   int nbytes, s, m, ktab;
+  int d0, d1;            // truncation columns U_{d0+1}..U_{d1} are stored (out column d - 1 - d0)
 };
 
 template <int LOGE, bool KCOL>
@@ -438,7 +439,8 @@ __global__ void __launch_bounds__((P2Shape<LOGE, 0>::THREADS)) fwt_p2_gen(ColGen
     double u[EPT];
 #pragma unroll
     for (int k = 0; k < EPT; ++k) u[k] = KCOL ? 1.0 : 0.0;
-    for (int j = 0; j < s; ++j) {
+    const int jend = KCOL ? s : g.d1;
+    for (int j = 0; j < jend; ++j) {
       const uint32_t* cj = cl + j * m;
       uint32_t xt = 0;  // X_j(tid) ^ X_j(n0)
 #pragma unroll
@@ -459,7 +461,9 @@ __global__ void __launch_bounds__((P2Shape<LOGE, 0>::THREADS)) fwt_p2_gen(ColGen
         const double a = rj[(int)__clz(xt ^ kx[k]) - sh];
         u[k] = KCOL ? u[k] * a : fma(a, 1.0 + u[k], u[k]);
       }
-      if constexpr (!KCOL) transform_store(u, j);
+      if constexpr (!KCOL) {
+        if (j >= g.d0) transform_store(u, j - g.d0);
+      }
     }
     if constexpr (KCOL) transform_store(u, 0);
   }
@@ -920,12 +924,14 @@ int fwt_p2_f64_reduce_rest(int m, double* data, int batch, const float2* wts, do
   return p2_pass(K_F64, data, data, v.back(), m, batch, 1.0, &red, st);
 }
 
-// First pass of the transforms of generated columns (fwt_p2_gen): the s
-// truncation columns U_d from the R' table (kcol false: out receives s
-// columns), or the kernel column K from the K' table (kcol true: one column).
+// First pass of the transforms of generated columns (fwt_p2_gen): the
+// truncation columns U_{d0+1}..U_{d1} from the R' table (kcol false: out
+// receives d1 - d0 columns), or the kernel column K from the K' table (kcol
+// true: one column; d0, d1 unused).
 int fwt_p2_gen_first(int m, int s, const uint32_t* xtab, int nbytes, const double* tab, int ktab, bool kcol,
-                     double* out, hipStream_t st) {
+                     int d0, int d1, double* out, hipStream_t st) {
   if (!fwt_p2_split_ok(m) || s < 1 || s > 64 || ktab <= m) return fail(FDWT_EINVAL, "bad generated-column pass");
+  if (!kcol && (d0 < 0 || d1 > s || d0 >= d1)) return fail(FDWT_EINVAL, "bad generated-column range");
   const P2Pass g = plan_p2(m, 8)[0];
   const void* fn = nullptr;
   if (kcol) fn = g.loge == 14 ? (const void*)fwt_p2_gen<14, true>
@@ -935,7 +941,7 @@ int fwt_p2_gen_first(int m, int s, const uint32_t* xtab, int nbytes, const doubl
   const int64_t N = int64_t(1) << m;
   const int E = 1 << g.loge;
   const int threads = E / 16;
-  const int ncol = kcol ? 1 : s;
+  const int ncol = kcol ? 1 : d1 - d0;
   PassDesc d{};
   d.col_in = N;
   d.col_out = N;
@@ -949,7 +955,7 @@ int fwt_p2_gen_first(int m, int s, const uint32_t* xtab, int nbytes, const doubl
   if (G >= d.ntiles) G = d.ntiles;
   if (G >= 64) G -= G % 8;
   d.xcd = (G % 8 == 0 && G >= 64) ? 1 : 0;
-  ColGen cg{xtab, tab, nbytes, s, m, ktab};
+  ColGen cg{xtab, tab, nbytes, s, m, ktab, kcol ? 0 : d0, kcol ? s : d1};
   void* args[] = {(void*)&cg, (void*)&out, (void*)&d};
   hipEvent_t tb = timed_begin(st);
   FDWT_HIP(hipLaunchKernel(fn, dim3((unsigned)G), dim3(threads), args, lds, st));

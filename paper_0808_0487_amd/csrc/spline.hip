@@ -465,7 +465,7 @@ int fwt_p2_f64_first(int m, const double* in, double* out, int batch, hipStream_
 int fwt_p2_f64_reduce_rest(int m, double* data, int batch, const float2* wts, double* partial, double* h0_out,
                            int h0_col, hipStream_t st);
 int fwt_p2_gen_first(int m, int s, const uint32_t* xtab, int nbytes, const double* tab, int ktab, bool kcol,
-                     double* out, hipStream_t st);
+                     int d0, int d1, double* out, hipStream_t st);
 int fwt_p2_f64_rest(int m, double* data, int batch, hipStream_t st);
 
 // ------------------------------------------------------ kernel spectrum
@@ -506,7 +506,8 @@ static int spectrum_into(Net& net, Scratch& sc, const fdwt_kernel* kern, void* w
   }
   if (net.p == 2 && fwt_p2_split_ok(net.m)) {
     // K generated inside the first pass of its transform (no column in memory).
-    if ((rc = fwt_p2_gen_first(net.m, net.s, net.d_xtab, net.nbytes, tab, kTab, true, (double*)gk, st))) return rc;
+    if ((rc = fwt_p2_gen_first(net.m, net.s, net.d_xtab, net.nbytes, tab, kTab, true, 0, 0, (double*)gk, st)))
+      return rc;
     return fwt_p2_f64_rest(net.m, (double*)gk, 1, st);
   }
   double* A = net.p == 2 ? (double*)gk : w.A;
@@ -799,26 +800,32 @@ int eff_dim_enqueue(Net& net, Scratch& sc, const fdwt_kernel* kern, const void* 
   if (p == 2) hipLaunchKernelGGL(k_effdim_weights<2>, dim3(kRedBlocks), dim3(256), 0, st, ft, GK, N, pm, w.wts, w.qmc_partial);
   else hipLaunchKernelGGL(k_effdim_weights<3>, dim3(kRedBlocks), dim3(256), 0, st, ft, GK, N, pm, w.wts, w.qmc_partial);  // any odd p
   FDWT_HIP(hipGetLastError());
-  if (p == 2 && ch == ncols && fwt_p2_split_ok(net.m)) {
-    // All columns at once: the U_d columns are generated inside the first
-    // pass of their transforms (B columns 0..s-1); only the Q_j columns go
-    // through memory (kernel data in A, first pass into B columns s..2s-1).
-    double* B = (double*)w.B;
-    const double* tr = w.tab + (size_t)s * kTab;
-    if ((rc = launch_kernel_cols(net, w.tab, tr, s + 1, ncols + 1, w.A, st))) return rc;
-    if ((rc = fwt_p2_gen_first(net.m, s, net.d_xtab, net.nbytes, tr, kTab, false, B, st))) return rc;
-    if ((rc = fwt_p2_f64_first(net.m, w.A, B + (size_t)s * N, s, st))) return rc;
-    if ((rc = fwt_p2_f64_reduce_rest(net.m, B, ncols, w.wts, w.partial, h0, s - 1, st))) return rc;
-  } else {
-    for (int c0 = 0; c0 < ncols; c0 += ch) {
-      const int c1 = std::min(ncols, c0 + ch);
-      rc = launch_kernel_cols(net, w.tab, w.tab + (size_t)s * kTab, c0 + 1, c1 + 1, w.A, st);
+  const int h0c = s - 1;  // U_s: its h = 0 term is the h = 0 share of the total
+  const double* tr = w.tab + (size_t)s * kTab;
+  for (int c0 = 0; c0 < ncols; c0 += ch) {
+    const int c1 = std::min(ncols, c0 + ch);
+    const int h0_col = (h0c >= c0 && h0c < c1) ? h0c - c0 : -1;
+    if (p == 2 && fwt_p2_split_ok(net.m)) {
+      // Chunk columns [c0, c1): the U_d among them are generated inside the
+      // first pass of their transforms (B columns 0..nu-1); only the Q_j go
+      // through memory (kernel data in A, first pass into B after the U_d).
+      double* B = (double*)w.B;
+      const int u1 = std::min(c1, s), nu = std::max(0, u1 - c0);
+      if (nu > 0 && (rc = fwt_p2_gen_first(net.m, s, net.d_xtab, net.nbytes, tr, kTab, false, c0, u1, B, st)))
+        return rc;
+      const int q0 = std::max(c0, s);
+      if (q0 < c1) {
+        if ((rc = launch_kernel_cols(net, w.tab, tr, q0 + 1, c1 + 1, w.A, st))) return rc;
+        if ((rc = fwt_p2_f64_first(net.m, w.A, B + (size_t)nu * N, c1 - q0, st))) return rc;
+      }
+      rc = fwt_p2_f64_reduce_rest(net.m, B, c1 - c0, w.wts, w.partial + (size_t)c0 * parts, h0, h0_col, st);
+    } else {
+      rc = launch_kernel_cols(net, w.tab, tr, c0 + 1, c1 + 1, w.A, st);
       if (rc) return rc;
-      const int h0_col = (s - 1 >= c0 && s - 1 < c1) ? s - 1 - c0 : -1;  // U_s
       int64_t t = 0;
       rc = fwt_reduce_f64(p, net.m, w.A, w.B, c1 - c0, w.wts, w.partial + (size_t)c0 * parts, h0, h0_col, &t, st);
-      if (rc) return rc;
     }
+    if (rc) return rc;
   }
   hipLaunchKernelGGL(k_sum_rows, dim3(ncols), dim3(kSumThreads), 0, st, w.partial, (int)parts, w.res);
   hipLaunchKernelGGL(k_sum_rows, dim3(1), dim3(kSumThreads), 0, st, w.qmc_partial, kRedBlocks, w.res + ncols);

@@ -115,6 +115,27 @@ def test_alone_and_in_the_mix_bit_identical():
     sv.close()
 
 
+def test_chunked_effdim_bit_identical():
+    """eff_dim in column chunks (the server's effdim_chunk_bytes: here 5 of the
+    2s = 12 columns at a time, so one chunk holds U_6 and Q_1..Q_4) equals the
+    one-call path, which takes all columns at once, bit for bit: every
+    column's transform and partial sums are the same in any grouping.  p = 2,
+    m = 16 uses the generated truncation-column pass."""
+    announce("server chunked eff_dim")
+    p, m, s = 2, 16, 6
+    reqs = [make_request("eff_dim", p, m, s, 300 + i, fam) for i, fam in enumerate(("product", "exp"))]
+    per_col = (p ** m) * 16
+    sv = fdwt.Server(256 * MiB, lanes=2, effdim_chunk_bytes=5 * per_col)
+    served = run_all(sv, reqs)
+    sv.close()
+    for r, (_, res) in zip(reqs, served):
+        net = fdwt.Net(r.p, r.m, r.s, r.C)
+        f = net.sample(r.family, r.a)
+        ref = net.eff_dim(fdwt.Kernel(r.alpha, r.gamma), net.forward(f))
+        assert same_result(res, ref), r.family
+        net.close()
+
+
 def test_budget_admission_and_eviction():
     """A budget that holds about two jobs with their caches: everything
     still completes (jobs wait for memory, resident entries are evicted and
