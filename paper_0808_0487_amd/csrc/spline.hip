@@ -214,35 +214,38 @@ __device__ __forceinline__ int ffbh_raw(uint32_t z) {
 
 // Sf at queries as partial sums over point chunks (blockIdx.y): each thread
 // takes one query; the points of a chunk are staged in LDS kNS at a time and
-// read as 16-byte broadcasts (4 points); the factor 1 + gamma_j K'(.) of
-// coordinate j comes from a table spread over the lanes of the wave
-// (tlane[j][lane], in registers) through ds_bpermute, which has no bank
-// conflicts.  The table lane is the leading-zero count of the XOR of the
-// query's and the point's digit strings:
-//   p = 2: the first differing bit t (all equal: v_ffbh_u32 gives all ones,
-//          lane 63);
-//   p odd: 3t + 1..3t + 3 for first differing digit t, 64 (lane 0) when all
-//          D digits agree.  The count is taken from the high 32 bits of the
-//          strings; only when those agree (digits 0..9 equal, rare) does the
-//          lane compute it from the low word.
+// read as 16-byte broadcasts (4 points).  The factor 1 + gamma_j K'(.) of
+// coordinate j is entry (c + 1) of a per-coordinate table in LDS (kTabE
+// floats a row, copied from ftab), where c is the leading-zero count of the
+// XOR of the query's and the point's digit strings (one v_add_lshl_u32 makes
+// the byte offset; distinct entries of a row lie in distinct banks):
+//   p = 2: the first differing bit c (all equal: v_ffbh_u32 gives -1, entry 0);
+//   p odd: c = 3t + 1..3t + 3 for first differing digit t, 64 when all D
+//          digits agree.  c comes from the high 32 bits of the strings; a
+//          lane whose high words agree for some (point, coordinate) of a group
+//          of 4 points (digits 0..9 equal, rare) redoes that group exactly,
+//          taking c from the low words there.  A running minimum of the
+//          high-word XORs detects it without a branch in the loop.
+constexpr int kTabE = 68;  // table entries per coordinate (p odd uses 0..65)
+
 template <int P, int SMAX>
 __global__ void __launch_bounds__(256) k_spline_eval(const void* __restrict__ Xp, const float* __restrict__ c,
                                                      int64_t N, int s, const void* __restrict__ qv, int64_t nq,
-                                                     const float* __restrict__ tlane, int64_t ppc,
+                                                     const float* __restrict__ ftab, int64_t ppc,
                                                      df* __restrict__ partial) {
   constexpr bool ODD = P != 2;
   constexpr int V = 4;  // points per LDS read
   extern __shared__ __align__(16) unsigned char smem[];
-  uint32_t* lxh = reinterpret_cast<uint32_t*>(smem);                     // [s][kNS] (p odd: high words)
+  float* lt = reinterpret_cast<float*>(smem);                              // [s][kTabE]
+  uint32_t* lxh = reinterpret_cast<uint32_t*>(lt + (size_t)s * kTabE);     // [s][kNS] (p odd: high words)
   uint32_t* lxl = lxh + (size_t)s * kNS;                                  // [s][kNS] p odd: low words
   float* lc = reinterpret_cast<float*>(lxh + (size_t)(ODD ? 2 : 1) * s * kNS);  // [kNS]
-  const int lane = threadIdx.x & 63;
+  for (int i = threadIdx.x; i < s * kTabE; i += blockDim.x) lt[i] = ftab[i];
   const int64_t qi = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const int64_t qq = qi < nq ? qi : nq - 1;
-  // Query high words and table entries stay in registers; the low words
-  // (needed only on the rare path) are read from memory there.
+  // Query high words stay in registers; the low words (needed only on the
+  // rare path) are read from memory there.
   uint32_t qh[SMAX];
-  int tj[SMAX];
 #pragma unroll
   for (int j = 0; j < SMAX; ++j) {
     if (j < s) {
@@ -251,9 +254,12 @@ __global__ void __launch_bounds__(256) k_spline_eval(const void* __restrict__ Xp
       } else {
         qh[j] = ((const uint32_t*)qv)[(int64_t)j * nq + qq];
       }
-      tj[j] = __float_as_int(tlane[j * 64 + lane]);
     }
   }
+  auto factor = [&](int j, int cl) {  // cl in [-1, 64]
+    return *reinterpret_cast<const float*>(reinterpret_cast<const char*>(lt + j * kTabE) +
+                                           ((uint32_t)(cl + 1) << 2));
+  };
   const int64_t nbeg = (int64_t)blockIdx.y * ppc;
   const int64_t nend = min(N, nbeg + ppc);
   df acc = {0.0f, 0.0f};
@@ -277,6 +283,7 @@ __global__ void __launch_bounds__(256) k_spline_eval(const void* __restrict__ Xp
       float pr[V];
 #pragma unroll
       for (int u = 0; u < V; ++u) pr[u] = 1.0f;
+      uint32_t zmin = 0xffffffffu;
 #pragma unroll
       for (int j = 0; j < SMAX; ++j) {
         if (j < s) {
@@ -285,19 +292,33 @@ __global__ void __launch_bounds__(256) k_spline_eval(const void* __restrict__ Xp
 #pragma unroll
           for (int u = 0; u < V; ++u) {
             const uint32_t zh = qh[j] ^ xs[u];
-            int cl = ffbh_raw(zh);
-            if constexpr (ODD) {
-              if (zh == 0u) {
-                // The empty asm keeps this load on the rare path (hoisting it
-                // out of the loop would cost a register pair per coordinate).
-                int64_t qo = qq;
-                asm volatile("" : "+v"(qo));
-                const uint32_t qlo = (uint32_t)((const uint64_t*)qv + (int64_t)j * nq)[qo];
+            if constexpr (ODD) zmin = min(zmin, zh);
+            pr[u] *= factor(j, ffbh_raw(zh));
+          }
+        }
+      }
+      if constexpr (ODD) {
+        if (zmin == 0u) {
+          // Rare: some high words agree; redo the group from the full strings.
+          // The empty asm keeps the query loads on this path.
+          int64_t qo = qq;
+          asm volatile("" : "+v"(qo));
+#pragma unroll
+          for (int u = 0; u < V; ++u) pr[u] = 1.0f;
+          for (int j = 0; j < s; ++j) {
+            const uint64_t qs = ((const uint64_t*)qv + (int64_t)j * nq)[qo];
+            const uint32_t qhi = (uint32_t)(qs >> 32), qlo = (uint32_t)qs;
+            for (int u = 0; u < V; ++u) {
+              const uint32_t zh = qhi ^ lxh[j * kNS + k + u];
+              int cl;
+              if (zh) {
+                cl = ffbh_raw(zh);
+              } else {
                 const uint32_t zl = qlo ^ lxl[j * kNS + k + u];
                 cl = zl ? 32 + ffbh_raw(zl) : 64;
               }
+              pr[u] *= factor(j, cl);
             }
-            pr[u] *= __int_as_float(__builtin_amdgcn_ds_bpermute(cl << 2, tj[j]));
           }
         }
       }
@@ -631,7 +652,7 @@ static int launch_eval(Net& net, const void* Xp, const float* c, int64_t nq, con
   return FDWT_OK;
 }
 
-size_t eval_tables_bytes(const Net& net) { return (size_t)net.s * 64 * 4; }
+size_t eval_tables_bytes(const Net& net) { return (size_t)net.s * kTabE * 4; }
 
 size_t packed_bytes(const Net& net) { return (size_t)net.s * net.N * (net.p == 2 ? 4 : 8); }
 
@@ -649,7 +670,7 @@ static void eval_grid(int64_t N, int64_t nq, int* gy_out, int64_t* ppc_out) {
 }
 
 struct EvalWs {
-  float* tl;     // per-lane factor tables [s][64]
+  float* tl;     // factor tables [s][kTabE]
   void* Xp;      // packed coordinates (when not given)
   uint64_t* qs;  // p odd: query digit strings [s][nq]
   df* partial;
@@ -686,17 +707,19 @@ int run_spline_eval(Net& net, Scratch& sc, const fdwt_kernel* kern, const void* 
   EvalWs w;
   eval_layout(net, nq, packed != nullptr, cv, w);
   // Factor 1 + gamma_j K'(t+1) of first differing digit t < D, and 1 + gamma_j
-  // when all D digits agree, placed in the lanes k_spline_eval selects.
-  std::vector<float> htl((size_t)s * 64, 1.0f);
+  // when all D digits agree, at entry c + 1 of the leading-zero count c that
+  // k_spline_eval computes (p = 2: c = t, or -1 when equal; p odd: c = 3t+1..3t+3,
+  // or 64 when equal).
+  std::vector<float> htl((size_t)s * kTabE, 1.0f);
   for (int j = 0; j < s; ++j) {
-    float* row = htl.data() + (size_t)j * 64;
+    float* row = htl.data() + (size_t)j * kTabE;
     const float eq = (float)(1.0 + kern->gamma[j] * kprime(p, kern->alpha, 0));
     for (int t = 0; t < D; ++t) {
       const float v = (float)(1.0 + kern->gamma[j] * kprime(p, kern->alpha, t + 1));
-      if (p == 2) row[t] = v;
-      else for (int l = 3 * t + 1; l <= 3 * t + 3; ++l) row[l] = v;
+      if (p == 2) row[t + 1] = v;
+      else for (int l = 3 * t + 1; l <= 3 * t + 3; ++l) row[l + 1] = v;
     }
-    row[p == 2 ? 63 : 0] = eq;
+    row[p == 2 ? 0 : 65] = eq;
   }
   rc = upload(sc, htl.data(), htl.size() * 4, w.tl, st);
   if (rc) return rc;
@@ -714,7 +737,8 @@ int run_spline_eval(Net& net, Scratch& sc, const fdwt_kernel* kern, const void* 
     FDWT_HIP(hipGetLastError());
     qv = w.qs;
   }
-  const size_t lds = (size_t)s * kNS * xb + kNS * 4;  // p odd: high and low words of the strings
+  // Tables, then the staged points (p odd: high and low words of the strings).
+  const size_t lds = (size_t)s * kTabE * 4 + (size_t)s * kNS * xb + kNS * 4;
   hipEvent_t tb = timed_begin(st);
   if (p == 2) rc = launch_eval<2>(net, Xp, c, nq, qv, w.tl, w.partial, gy, ppc, lds, st);
   else rc = launch_eval<3>(net, Xp, c, nq, qv, w.tl, w.partial, gy, ppc, lds, st);  // any odd p: digit strings
