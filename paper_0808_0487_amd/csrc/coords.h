@@ -125,13 +125,19 @@ __device__ __forceinline__ uint32_t canon_odd(uint64_t packed, int m) {
   return X;
 }
 
-// Digit string of packed fields for the interpolant evaluation: digit
-// y_{f+1} in bits [62-3f, 60-3f] (3-bit fields under one zero bit), so that
-// the leading-zero count of the XOR of two strings is 3f + 1..3f + 3 when
-// digit f + 1 is the first that differs, and 64 when none does.
+// Digit strings for the interpolant evaluation: fields of B bits under one
+// zero bit, B = 2 for p = 3 and 3 for p = 5, 7 (the fewest that hold a
+// digit), digit y_{f+1} in bits [62 - B f, 63 - B (f + 1)].  The leading-zero
+// count of the XOR of two strings is then B f + 1..B f + B when digit f + 1
+// is the first that differs, and 64 when none does; the first 32 bits hold
+// 15 digits (p = 3) or 10 (p = 5, 7).
+template <int P>
+constexpr int kStrBits = P == 3 ? 2 : 3;
+template <int P>
 __device__ __forceinline__ uint64_t eval_string_odd(uint64_t pk, int m) {
+  constexpr int B = kStrBits<P>;
   uint64_t v = 0;
-  for (int f = 0; f < m; ++f) v |= ((pk >> (4 * (m - 1 - f))) & 7ull) << (60 - 3 * f);
+  for (int f = 0; f < m; ++f) v |= ((pk >> (4 * (m - 1 - f))) & 7ull) << (63 - B * (f + 1));
   return v;
 }
 

@@ -56,7 +56,7 @@ __global__ void __launch_bounds__(kChunk) k_coords_odd(const uint64_t* ptab, int
         const uint64_t pk = oc.X(j, r, k);
         if (MODE == CM_DIGITS) ((uint32_t*)out)[(int64_t)j * N + n] = canon_odd<P>(pk, m);
         if (MODE == CM_POINTS) ((float*)out)[(int64_t)j * N + n] = (float)canon_odd<P>(pk, m) * inv_pm;
-        if (MODE == CM_SHIFTED) ((uint64_t*)out)[(int64_t)j * N + n] = eval_string_odd(pk, m);
+        if (MODE == CM_SHIFTED) ((uint64_t*)out)[(int64_t)j * N + n] = eval_string_odd<P>(pk, m);
       }
     }
   }

@@ -198,7 +198,7 @@ __global__ void __launch_bounds__(256) k_query_prep(const uint32_t* __restrict__
     uint32_t Q = q[i];
     uint64_t v = 0;
     for (int f = D - 1; f >= 0; --f) {
-      v |= (uint64_t)(Q % P) << (60 - 3 * f);
+      v |= (uint64_t)(Q % P) << (63 - kStrBits<P> * (f + 1));
       Q /= P;
     }
     qs[i] = v;
@@ -220,12 +220,13 @@ __device__ __forceinline__ int ffbh_raw(uint32_t z) {
 // XOR of the query's and the point's digit strings (one v_add_lshl_u32 makes
 // the byte offset; distinct entries of a row lie in distinct banks):
 //   p = 2: the first differing bit c (all equal: v_ffbh_u32 gives -1, entry 0);
-//   p odd: c = 3t + 1..3t + 3 for first differing digit t, 64 when all D
-//          digits agree.  c comes from the high 32 bits of the strings; a
-//          lane whose high words agree for some (point, coordinate) of a group
-//          of 4 points (digits 0..9 equal, rare) redoes that group exactly,
-//          taking c from the low words there.  A running minimum of the
-//          high-word XORs detects it without a branch in the loop.
+//   p odd: c = Bt + 1..Bt + B for first differing digit t (B = 2 for p = 3,
+//          3 otherwise: coords.h), 64 when all D digits agree.  c comes from
+//          the high 32 bits of the strings; a lane whose high words agree for
+//          some (point, coordinate) of a group of 4 points (the first 15 or 10
+//          digits equal, rare) redoes that group exactly, taking c from the
+//          low words there.  A running minimum of the high-word XORs detects
+//          it without a branch in the loop.
 constexpr int kTabE = 68;  // table entries per coordinate (p odd uses 0..65)
 
 template <int P, int SMAX>
@@ -708,8 +709,9 @@ int run_spline_eval(Net& net, Scratch& sc, const fdwt_kernel* kern, const void* 
   eval_layout(net, nq, packed != nullptr, cv, w);
   // Factor 1 + gamma_j K'(t+1) of first differing digit t < D, and 1 + gamma_j
   // when all D digits agree, at entry c + 1 of the leading-zero count c that
-  // k_spline_eval computes (p = 2: c = t, or -1 when equal; p odd: c = 3t+1..3t+3,
+  // k_spline_eval computes (p = 2: c = t, or -1 when equal; p odd: c = Bt+1..Bt+B,
   // or 64 when equal).
+  const int B = p == 3 ? kStrBits<3> : kStrBits<5>;  // digit-string field width (coords.h)
   std::vector<float> htl((size_t)s * kTabE, 1.0f);
   for (int j = 0; j < s; ++j) {
     float* row = htl.data() + (size_t)j * kTabE;
@@ -717,7 +719,7 @@ int run_spline_eval(Net& net, Scratch& sc, const fdwt_kernel* kern, const void* 
     for (int t = 0; t < D; ++t) {
       const float v = (float)(1.0 + kern->gamma[j] * kprime(p, kern->alpha, t + 1));
       if (p == 2) row[t + 1] = v;
-      else for (int l = 3 * t + 1; l <= 3 * t + 3; ++l) row[l + 1] = v;
+      else for (int l = B * t + 1; l <= B * t + B; ++l) row[l + 1] = v;
     }
     row[p == 2 ? 0 : 65] = eq;
   }
