@@ -186,6 +186,31 @@ def test_prime_three_full_size_interpolation():
     assert np.all(np.isfinite(sf))
 
 
+def test_prime_two_full_size_interpolation():
+    """p = 2, m = 24, s = 20 (the benchmark's plain-at-scale shape): f sampled
+    on the device; Sf at 128 net points lifted to depth 32 reproduces the
+    oracle's f there (the interpolation property of Section 3.2; this runs
+    the generated kernel-column spectrum, the spectral solve, the inverse and
+    the evaluation at full size), and 4096 random queries give finite values."""
+    p, m, s = 2, 24, 20
+    announce("full p2 interp")
+    C = inputs.upper_triangular_generators(p, m, s, 2)
+    a = inputs.family_params("exp", s, ratio=0.1)
+    net = fdwt.Net(p, m, s, C)
+    kern = fdwt.Kernel(2.0, inputs.kernel_weights(s))
+    f = net.sample("exp", a)
+    idx = sample_indices(p ** m, 128, 5)
+    Xi = onet.net_int(p, m, C, idx)
+    fo = families.exponential(Xi / float(p ** m), a)
+    Q = inputs.queries(p, s, 4096, 5).astype(np.int64)
+    Qall = np.concatenate([Q, kernel.to_depth(p, m, 32, Xi)], axis=1)
+    qd = torch.from_numpy(Qall.astype(np.uint32).view(np.int32)).cuda()
+    c, sf = net.walsh_interp(kern, f, qd)
+    sf = sf.cpu().numpy()
+    assert nrel(sf[-len(idx):].astype(np.float64), fo) <= 1e-5
+    assert np.all(np.isfinite(sf))
+
+
 def test_spectrum_cache_follows_the_kernel():
     """The handle's cached spectrum is keyed by (alpha, gamma): switching
     kernels recomputes it, switching back reproduces the first result bit for
