@@ -83,11 +83,12 @@ def test_effective_dimension_variances(p, m, s, seed):
     assert res["var_total"] - res["var_total_h0"] <= res["var_qmc"] * (1 + 1e-6)
 
 
-@pytest.mark.parametrize("m,s", [(9, 5), (24, 2)])
+@pytest.mark.parametrize("m,s", [(9, 5), (24, 2), (25, 2)])
 def test_kernel_section_closed_form(m, s):
     """f = K(., x_v): every variance has the closed form of the kernel
-    section (Section 4 product structure).  m = 24 is the full-size plan
-    (generated truncation columns, half-width grouped-sum pass)."""
+    section (Section 4 product structure).  m = 24 is the full-size two-pass
+    plan (generated first pass, grouped-sum second pass); m = 25 the
+    three-pass plan (2^13-element generated first pass, a middle pass)."""
     p = 2
     announce("kernel section", p, m, s)
     C = inputs.upper_triangular_generators(p, m, s, 9)
@@ -125,7 +126,7 @@ def test_effdim_invariants_at_scale(p, m, s):
     assert 0.5 * total <= res["var_total"] <= 1.5 * total
 
 
-@pytest.mark.parametrize("m,s,seed", [(15, 6, 21), (16, 10, 22), (17, 20, 23), (15, 64, 24)])
+@pytest.mark.parametrize("m,s,seed", [(15, 6, 21), (16, 10, 22), (17, 20, 23), (15, 64, 24), (16, 1, 27)])
 def test_effdim_two_pass_sizes_against_spectral_route(m, s, seed):
     """p = 2 nets with two-pass transforms (m >= 15; tiles of 2^12, 2^13 and
     2^14 in the first pass, where the truncation columns are generated inside
