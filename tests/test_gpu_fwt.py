@@ -139,6 +139,29 @@ def test_full_size_p2_float_and_int32():
     assert np.array_equal(bi, (N * fi.astype(np.int64) + 2 ** 31) % 2 ** 32 - 2 ** 31)
 
 
+def test_maximum_size_p2_float_and_int32():
+    """m = 26, the largest net (p^m <= 2^26; a three-pass plan): float forward
+    on sampled outputs against the phase form, Parseval, round trip; int32
+    exact on samples."""
+    p, m = 2, 26
+    N = p ** m
+    announce("max p2 m=26")
+    net = fdwt.Net(p, m, 2, inputs.upper_triangular_generators(p, m, 2, 6))
+    f = inputs.uniform_float(N, 26, dtype=np.float64)
+    fd = to_dev(f, torch.float32)
+    ft = net.forward(fd)
+    hs = sample_indices(N, 12, 26)
+    assert nrel(ft.cpu().numpy()[hs], walsh.dwt_phase(p, m, f, hs)) <= TOL
+    e_f = float(torch.sum(fd.double() ** 2)) / N
+    assert abs(float(torch.sum(ft.double() ** 2)) - e_f) <= 1e-5 * e_f
+    back = net.inverse(ft)
+    assert float(torch.linalg.norm(back - fd) / torch.linalg.norm(fd)) <= TOL
+    del ft, back
+    fi = inputs.uniform_int32(N, -1000, 1000, 27)
+    gi = net.forward(to_dev(fi, torch.int32)).cpu().numpy().astype(np.int64)
+    assert np.array_equal(gi[hs], walsh.dwt_phase(p, m, fi, hs))
+
+
 def test_full_size_p3():
     """p = 3, m = 14 (4.78M points): sampled outputs and round trip."""
     p, m = 3, 14
