@@ -26,12 +26,12 @@
  *     code; fdwt_last_error() gives a message for the calling thread.  No
  *     exception crosses the ABI.  Invalid arguments are rejected before any
  *     work is enqueued.
- *   - Tuning knobs read once per process from the environment (results do
- *     not depend on them): FDWT_EFFDIM_CHUNK_MB, the workspace budget of
- *     fdwt_eff_dim's kernel-data columns in MiB (default 12288; smaller
- *     budgets process the columns in chunks); FDWT_LDS_KB_WIDE, the LDS
- *     budget in KiB of the float64 pass tiles (default 160: 2^14-element
- *     tiles).
+ *   - Tuning knobs read once per process from the environment:
+ *     FDWT_EFFDIM_CHUNK_MB, the workspace budget of fdwt_eff_dim's
+ *     kernel-data columns in MiB (default 12288; smaller budgets process the
+ *     columns in chunks, with bit-identical results); FDWT_LDS_KB_WIDE, the
+ *     LDS budget in KiB of the float64 pass tiles (default 160: 2^14-element
+ *     tiles; other budgets change the pass plan and so the rounding).
  */
 #ifndef FDWT_H
 #define FDWT_H
