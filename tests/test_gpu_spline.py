@@ -44,7 +44,7 @@ def test_spline_coefficients_solve_the_interpolation_system(p, m, s, seed):
     assert nrel(c, co) <= max(1e-5, 4e-7 * cond)
 
 
-@pytest.mark.parametrize("p,m,s,seed", CASES)
+@pytest.mark.parametrize("p,m,s,seed", CASES + [(2, 7, 12, 15), (2, 6, 40, 16), (3, 4, 33, 17), (5, 3, 64, 18)])
 def test_interpolant_at_queries(p, m, s, seed):
     """Sf at random D-digit queries against the oracle's direct sum with the
     oracle's coefficients, and Sf(x_n) = f(x_n) at net points."""
