@@ -126,28 +126,58 @@ __device__ __forceinline__ float fam_final(typename FamState<FAM>::T acc, const 
   else return acc;
 }
 
+// p = 2: a workgroup takes blocks of kSampleBlock = 4096 consecutive points;
+// thread t owns base + t + 256 k (k < 16).  X_j is linear over Z_2 in the bits
+// of n and base, t and 256 k occupy disjoint bits, so X_j(n) is the XOR of
+// X_j(base) (uniform), X_j(t) (one table read per coordinate) and X_j(256 k)
+// (four 16-byte broadcasts per coordinate): about one XOR per point and
+// coordinate besides the family's arithmetic.
+constexpr int kSampleBlock = 4096;
 template <int FAM>
-__global__ void __launch_bounds__(kChunk) k_sample_p2(const uint32_t* xtab, int nbytes, FamilyArgs fa, int m,
-                                                      int64_t N, float* f) {
-  extern __shared__ uint32_t lds[];
+__global__ void __launch_bounds__(256) k_sample_p2(const uint32_t* xtab, int nbytes, FamilyArgs fa, int m,
+                                                   int64_t N, float* f) {
+  extern __shared__ __align__(16) uint32_t lds[];
   const int s = fa.s;
-  P2Coords pc{xtab, nbytes, s, lds, lds + s * 256};
-  float* la = reinterpret_cast<float*>(lds + s * 256 + kMaxS);
+  uint32_t* t0 = lds;               // [s][256]: X_j(t)
+  uint32_t* t1 = t0 + s * 256;      // [s][16]:  X_j(256 k)
+  uint32_t* ub = t1 + s * 16;       // [s]: X_j(base)
+  float* la = reinterpret_cast<float*>(ub + kMaxS);
   float* li = la + kMaxS;
-  for (int j = threadIdx.x; j < s; j += blockDim.x) {
+  const int tid = threadIdx.x;
+  for (int i = tid; i < s * 256; i += 256) t0[i] = xtab[(size_t)(i >> 8) * nbytes * 256 + (i & 255)];
+  for (int i = tid; i < s * 16; i += 256) t1[i] = nbytes > 1 ? xtab[((size_t)(i >> 4) * nbytes + 1) * 256 + (i & 15)] : 0u;
+  for (int j = tid; j < s; j += 256) {
     la[j] = fa.a[j];
     li[j] = fa.inv1a[j];
   }
-  pc.stage_tables();
   const float inv = 1.0f / (float)(1u << m);
-  for (int64_t base = (int64_t)blockIdx.x * kChunk; base < N; base += (int64_t)gridDim.x * kChunk) {
+  for (int64_t base = (int64_t)blockIdx.x * kSampleBlock; base < N; base += (int64_t)gridDim.x * kSampleBlock) {
     __syncthreads();
-    pc.stage_group(base);
+    for (int j = tid; j < s; j += 256) {
+      uint32_t v = 0;
+      const uint32_t* tj = xtab + (size_t)j * nbytes * 256;
+      for (int b = 1; b < nbytes; ++b) v ^= tj[b * 256 + (int)((base >> (8 * b)) & 255)];
+      ub[j] = v;
+    }
     __syncthreads();
-    const int64_t n = base + threadIdx.x;
-    auto acc = fam_init<FAM>(fa);
-    for (int j = 0; j < s; ++j) fam_step<FAM>(acc, fa, la[j], li[j], pc.X(j, n), inv, (double)inv);
-    if (n < N) f[n] = fam_final<FAM>(acc, fa);
+    typename FamState<FAM>::T acc[16];
+#pragma unroll
+    for (int k = 0; k < 16; ++k) acc[k] = fam_init<FAM>(fa);
+    for (int j = 0; j < s; ++j) {
+      const uint32_t xl = t0[j * 256 + tid] ^ ub[j];
+      const uint4* r = reinterpret_cast<const uint4*>(t1 + j * 16);
+      const uint4 r0 = r[0], r1 = r[1], r2 = r[2], r3 = r[3];
+      const uint32_t kx[16] = {r0.x, r0.y, r0.z, r0.w, r1.x, r1.y, r1.z, r1.w,
+                               r2.x, r2.y, r2.z, r2.w, r3.x, r3.y, r3.z, r3.w};
+      const float a = la[j], ia = li[j];
+#pragma unroll
+      for (int k = 0; k < 16; ++k) fam_step<FAM>(acc[k], fa, a, ia, xl ^ kx[k], inv, (double)inv);
+    }
+#pragma unroll
+    for (int k = 0; k < 16; ++k) {
+      const int64_t n = base + tid + 256 * k;
+      if (n < N) f[n] = fam_final<FAM>(acc[k], fa);
+    }
   }
 }
 
@@ -224,9 +254,10 @@ int launch_net_packed(const Net& net, void* out, hipStream_t st) { return coords
 template <int FAM>
 static int sample_fam(const Net& net, const FamilyArgs& fa, float* f, unsigned g, hipStream_t st) {
   if (net.p == 2) {
-    const size_t lds = (size_t)net.s * 257 * 4 + 2 * kMaxS * 4 + 4 * kMaxS;
+    const size_t lds = (size_t)net.s * (256 + 16) * 4 + kMaxS * 4 + 2 * kMaxS * 4;
+    const unsigned g2 = (unsigned)std::min<int64_t>((net.N + kSampleBlock - 1) / kSampleBlock, 4096);
     if (int rc = allow_lds((const void*)k_sample_p2<FAM>, lds)) return rc;
-    hipLaunchKernelGGL(k_sample_p2<FAM>, dim3(g), dim3(kChunk), lds, st, net.d_xtab, net.nbytes, fa, net.m,
+    hipLaunchKernelGGL(k_sample_p2<FAM>, dim3(g2), dim3(256), lds, st, net.d_xtab, net.nbytes, fa, net.m,
                        net.N, f);
   } else if (net.p == 3) {
     const size_t lds = OddCoords<3>::lds_bytes(net.s) + 2 * kMaxS * 4;
