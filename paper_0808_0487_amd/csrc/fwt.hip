@@ -673,13 +673,14 @@ struct P2Pass {
 };
 
 // Two passes cover m <= 24: a contiguous first pass of up to 2^14 elements,
-// then strided passes over the remaining digits with rows of 16 elements (64
-// bytes of float, 128 bytes of double: a 128-byte row never shares a cache
-// line with another tile, so the float64 passes, whose tiles of one column
-// are not neighbours in time, do not fetch lines twice), split evenly
-// (>= 2^7 elements per tile).
-static std::vector<P2Pass> plan_p2_e(int m, int emax) {
-  const int wd = 4;
+// then strided passes over the remaining digits with rows of 2^wd elements,
+// split evenly (>= 2^7 elements per tile).  Rows of 16 doubles or 32 floats
+// are 128 bytes, the cache line: a row never shares a line with another tile
+// (tiles of one column are not neighbours in time) and each DRAM access
+// moves a whole line.  4-byte elements take rows of 32 when that does not
+// add a pass (every m <= 23); m = 24 keeps rows of 16 (64 bytes) and two
+// passes.
+static std::vector<P2Pass> plan_p2_w(int m, int emax, int wd) {
   std::vector<P2Pass> out;
   if (m <= emax) {
     out.push_back({0, m, 0});
@@ -695,8 +696,17 @@ static std::vector<P2Pass> plan_p2_e(int m, int emax) {
   return out;
 }
 
+static std::vector<P2Pass> plan_p2_e(int m, int emax, size_t bytes = 4) {
+  std::vector<P2Pass> v = plan_p2_w(m, emax, 4);
+  if (bytes <= 4) {
+    std::vector<P2Pass> w = plan_p2_w(m, emax, 5);
+    if (w.size() <= v.size()) return w;
+  }
+  return v;
+}
+
 static std::vector<P2Pass> plan_p2(int m, size_t bytes) {
-  return plan_p2_e(m, (bytes >= 8 && lds_budget(bytes) < 136 * 1024) ? 13 : 14);
+  return plan_p2_e(m, (bytes >= 8 && lds_budget(bytes) < 136 * 1024) ? 13 : 14, bytes);
 }
 
 template <class Tin, class T, class Tout, int WDIG, int EPI>
@@ -744,9 +754,13 @@ static int launch_p2(const void* in, void* out, const P2Pass& g, int m, int batc
   if (red) {
     if constexpr (wide) fn = g.wdig ? p2_kernel<Tin, T, Tout, 4, EPI_REDUCE>(g.loge) : p2_kernel<Tin, T, Tout, 0, EPI_REDUCE>(g.loge);
   } else {
-    fn = g.wdig ? p2_kernel<Tin, T, Tout, 4, EPI_STORE>(g.loge) : p2_kernel<Tin, T, Tout, 0, EPI_STORE>(g.loge);
+    if (g.wdig == 5) {
+      if constexpr (!wide) fn = p2_kernel<Tin, T, Tout, 5, EPI_STORE>(g.loge);
+    } else {
+      fn = g.wdig ? p2_kernel<Tin, T, Tout, 4, EPI_STORE>(g.loge) : p2_kernel<Tin, T, Tout, 0, EPI_STORE>(g.loge);
+    }
   }
-  if (!fn || (g.wdig != 0 && g.wdig != 4)) return fail(FDWT_EINVAL, "no static pass shape");
+  if (!fn || (g.wdig != 0 && g.wdig != 4 && g.wdig != 5)) return fail(FDWT_EINVAL, "no static pass shape");
   const int64_t N = int64_t(1) << m;
   const int E = 1 << g.loge;
   const int threads = std::max(64, std::min(1024, E / 16));
