@@ -31,7 +31,10 @@
  *     kernel-data columns in MiB (default 12288; smaller budgets process the
  *     columns in chunks, with bit-identical results); FDWT_LDS_KB_WIDE, the
  *     LDS budget in KiB of the float64 pass tiles (default 160: 2^14-element
- *     tiles; other budgets change the pass plan and so the rounding).
+ *     tiles; other budgets change the pass plan and so the rounding);
+ *     FDWT_EFFDIM_BLOCKED = 0 keeps fdwt_eff_dim's p = 2 intermediate
+ *     columns in natural order instead of the blocked layout (the rounding
+ *     of the sums changes).
  */
 #ifndef FDWT_H
 #define FDWT_H

@@ -307,10 +307,19 @@ __global__ void __launch_bounds__((P2Shape<LOGE, WDIG>::THREADS))
       for (int k = 0; k < EPT; ++k) v[k] = lrowS[66 * k];
       reg_bfly<NS>(v);
       if constexpr (EPI == EPI_STORE) {
-        const gptr<Tout> dst =
-            to_global((d.out_tab ? (Tout*)d.out_tab[col] : out + (int64_t)col * d.col_out) + base + goffS);
+        if (WDIG == 0 && d.oblk) {
+          // Blocked layout: e = lane + 64 k + 1024 w has row e >> 4 and column e & 15.
+          const int64_t rs = d.oblk;
+          const gptr<Tout> dst = to_global(out + (int64_t)col * d.col_out + ((lane >> 4) + 64 * wv) * rs +
+                                           (int64_t)tile * 16 + (lane & 15));
 #pragma unroll
-        for (int k = 0; k < EPT; ++k) dst[k * gstepS] = cvt_out<T, Tout>(v[k], d.scale, d.scale64);
+          for (int k = 0; k < EPT; ++k) dst[k * 4 * rs] = cvt_out<T, Tout>(v[k], d.scale, d.scale64);
+        } else {
+          const gptr<Tout> dst =
+              to_global((d.out_tab ? (Tout*)d.out_tab[col] : out + (int64_t)col * d.col_out) + base + goffS);
+#pragma unroll
+          for (int k = 0; k < EPT; ++k) dst[k * gstepS] = cvt_out<T, Tout>(v[k], d.scale, d.scale64);
+        }
       } else {
         double acc = 0.0;
 #pragma unroll
@@ -429,9 +438,17 @@ __global__ void __launch_bounds__((P2Shape<LOGE, 0>::THREADS)) fwt_p2_gen(ColGen
 #pragma unroll
     for (int k = 0; k < EPT; ++k) v[k] = lrowS[66 * k];
     reg_bfly<NS>(v);
-    const gptr<double> dst = to_global(out + (int64_t)col * d.col_out + ((int64_t)lb << LOGE) + goffS);
+    if (d.oblk) {  // blocked layout (PassDesc::oblk)
+      const int64_t rs = d.oblk;
+      const gptr<double> dst =
+          to_global(out + (int64_t)col * d.col_out + ((lane >> 4) + 64 * wv) * rs + (int64_t)lb * 16 + (lane & 15));
 #pragma unroll
-    for (int k = 0; k < EPT; ++k) dst[k * 64] = v[k];
+      for (int k = 0; k < EPT; ++k) dst[k * 4 * rs] = v[k];
+    } else {
+      const gptr<double> dst = to_global(out + (int64_t)col * d.col_out + ((int64_t)lb << LOGE) + goffS);
+#pragma unroll
+      for (int k = 0; k < EPT; ++k) dst[k * 64] = v[k];
+    }
     lds_barrier();
   };
   for (; lb < d.ntiles; lb += G) {
@@ -746,9 +763,12 @@ static int64_t p2_reduce_parts(int m, const P2Pass& g) {
 }
 
 template <class Tin, class T, class Tout>
+// layout: 0 natural; 1 the (contiguous first) pass stores in the blocked
+// layout of PassDesc::oblk; 2 the (strided) pass reads and writes that
+// blocked layout, where each of its tiles is one contiguous block.
 static int launch_p2(const void* in, void* out, const P2Pass& g, int m, int batch, double scale,
                      const ReduceArgs* red, hipStream_t st, const void* const* in_tab = nullptr,
-                     void* const* out_tab = nullptr) {
+                     void* const* out_tab = nullptr, int layout = 0) {
   constexpr bool wide = sizeof(T) >= 8;
   const void* fn = nullptr;
   if (red) {
@@ -790,6 +810,15 @@ static int launch_p2(const void* in, void* out, const P2Pass& g, int m, int batc
   }
   d.in_tab = in_tab;
   d.out_tab = out_tab;
+  if (layout == 1) {
+    if (g.wdig != 0 || g.loge < 10 || in_tab || out_tab) return fail(FDWT_EINVAL, "blocked store needs a first pass");
+    d.oblk = ntiles * 16;
+  } else if (layout == 2) {
+    if (g.wdig != 4 || g.d0 + g.loge - g.wdig != m) return fail(FDWT_EINVAL, "blocked read needs the last pass");
+    d.sd0 = 16;
+    d.nlo = 1;
+    d.shi = E;
+  }
   const size_t lds = ((size_t)cpad(E) * sizeof(T) + 15) / 16 * 16;
   if (int rc = allow_lds(fn, lds)) return rc;
   int64_t G = (int64_t)occupancy(fn, threads, lds) * device_cus();
@@ -806,10 +835,10 @@ static int launch_p2(const void* in, void* out, const P2Pass& g, int m, int batc
 }
 
 static int p2_pass(Kind k, const void* in, void* out, const P2Pass& g, int m, int batch, double scale,
-                   const ReduceArgs* red, hipStream_t st) {
+                   const ReduceArgs* red, hipStream_t st, int layout = 0) {
   if (k == K_F32 && !red) return launch_p2<float, float, float>(in, out, g, m, batch, scale, nullptr, st);
   if (k == K_U32 && !red) return launch_p2<uint32_t, uint32_t, uint32_t>(in, out, g, m, batch, scale, nullptr, st);
-  if (k == K_F64) return launch_p2<double, double, double>(in, out, g, m, batch, scale, red, st);
+  if (k == K_F64) return launch_p2<double, double, double>(in, out, g, m, batch, scale, red, st, nullptr, nullptr, layout);
   return fail(FDWT_EINVAL, "unsupported p = 2 element type");
 }
 
@@ -922,20 +951,29 @@ bool fwt_p2_split_ok(int m) {
   return v.size() >= 2 && v[0].d0 == 0 && v[0].wdig == 0 && v[0].loge >= 12 && v[0].loge <= 14;
 }
 
-int fwt_p2_f64_first(int m, const double* in, double* out, int batch, hipStream_t st) {
-  if (!fwt_p2_split_ok(m)) return fail(FDWT_EINVAL, "no split plan for this m");
-  return p2_pass(K_F64, in, out, plan_p2(m, 8)[0], m, batch, 1.0, nullptr, st);
+// Two-pass plans can keep the intermediate in the blocked layout of
+// PassDesc::oblk (the first pass stores blocks, the grouped-sum pass reads
+// each tile as one contiguous block; its weights then come in the same
+// layout, fwt_p2_blocked_index).
+bool fwt_p2_blocked_ok(int m) { return fwt_p2_split_ok(m) && plan_p2(m, 8).size() == 2; }
+
+// Digits of the first pass of the float64 plan for m.
+int fwt_p2_first_loge(int m) { return plan_p2(m, 8)[0].loge; }
+
+int fwt_p2_f64_first(int m, const double* in, double* out, int batch, bool blocked, hipStream_t st) {
+  if (!fwt_p2_split_ok(m) || (blocked && !fwt_p2_blocked_ok(m))) return fail(FDWT_EINVAL, "no split plan for this m");
+  return p2_pass(K_F64, in, out, plan_p2(m, 8)[0], m, batch, 1.0, nullptr, st, blocked ? 1 : 0);
 }
 
 int fwt_p2_f64_reduce_rest(int m, double* data, int batch, const float2* wts, double* partial, double* h0_out,
-                           int h0_col, hipStream_t st) {
-  if (!fwt_p2_split_ok(m)) return fail(FDWT_EINVAL, "no split plan for this m");
+                           int h0_col, bool blocked, hipStream_t st) {
+  if (!fwt_p2_split_ok(m) || (blocked && !fwt_p2_blocked_ok(m))) return fail(FDWT_EINVAL, "no split plan for this m");
   const std::vector<P2Pass> v = plan_p2(m, 8);
   const ReduceArgs red{wts, partial, h0_out, h0_col};
   int rc = FDWT_OK;
   for (size_t i = 1; !rc && i + 1 < v.size(); ++i) rc = p2_pass(K_F64, data, data, v[i], m, batch, 1.0, nullptr, st);
   if (rc) return rc;
-  return p2_pass(K_F64, data, data, v.back(), m, batch, 1.0, &red, st);
+  return p2_pass(K_F64, data, data, v.back(), m, batch, 1.0, &red, st, blocked ? 2 : 0);
 }
 
 // First pass of the transforms of generated columns (fwt_p2_gen): the
@@ -943,7 +981,7 @@ int fwt_p2_f64_reduce_rest(int m, double* data, int batch, const float2* wts, do
 // receives d1 - d0 columns), or the kernel column K from the K' table (kcol
 // true: one column; d0, d1 unused).
 int fwt_p2_gen_first(int m, int s, const uint32_t* xtab, int nbytes, const double* tab, int ktab, bool kcol,
-                     int d0, int d1, double* out, hipStream_t st) {
+                     int d0, int d1, double* out, bool blocked, hipStream_t st) {
   if (!fwt_p2_split_ok(m) || s < 1 || s > 64 || ktab <= m) return fail(FDWT_EINVAL, "bad generated-column pass");
   if (!kcol && (d0 < 0 || d1 > s || d0 >= d1)) return fail(FDWT_EINVAL, "bad generated-column range");
   const P2Pass g = plan_p2(m, 8)[0];
@@ -962,6 +1000,10 @@ int fwt_p2_gen_first(int m, int s, const uint32_t* xtab, int nbytes, const doubl
   d.ntiles = (int)(N / E);
   d.batch = ncol;
   d.h0_col = -1;
+  if (blocked) {
+    if (!fwt_p2_blocked_ok(m)) return fail(FDWT_EINVAL, "no blocked plan for this m");
+    d.oblk = (int64_t)d.ntiles * 16;
+  }
   const size_t lds = (size_t)((cpad(E) + 1) & ~1) * sizeof(double) + (size_t)s * (m + 1) * sizeof(double) +
                      (size_t)s * m * sizeof(uint32_t);
   if (int rc = allow_lds(fn, lds)) return rc;

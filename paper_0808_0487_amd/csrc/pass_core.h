@@ -32,6 +32,11 @@ struct PassDesc {
   double* partial;
   double* h0_out;
   int32_t h0_col;
+  // Blocked output of a contiguous first pass (LOGE >= 10, WDIG 0): when
+  // nonzero, element e of tile t is stored at (e >> 4) * oblk + 16 t + (e & 15),
+  // oblk = 16 * ntiles, so that each tile of a following strided pass (rows of
+  // 16) is one contiguous block.
+  int64_t oblk;
   // Column pointer tables (store passes of static p = 2 shapes): when set,
   // column c reads in_tab[c] and writes out_tab[c] instead of in/out plus
   // c times the column stride (a group of equal-size jobs anywhere in memory).

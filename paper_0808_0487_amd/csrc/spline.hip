@@ -141,11 +141,18 @@ constexpr int kRedBlocks = 1024;
 template <int P>
 __global__ void __launch_bounds__(256) k_effdim_weights(const void* __restrict__ ft, const void* __restrict__ gk,
                                                         int64_t N, double pm, float2* __restrict__ wts,
-                                                        double* __restrict__ qmc_partial) {
+                                                        double* __restrict__ qmc_partial, int blkF, int m) {
   __shared__ double red[256];
   double qmc = 0.0;
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-  for (int64_t h = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; h < N; h += stride) {
+  for (int64_t b = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; b < N; b += stride) {
+    // wts[b] is the weight of coefficient h: b = h, or (blkF > 0) the blocked
+    // position of h for a first pass of 2^blkF elements (PassDesc::oblk).
+    int64_t h = b;
+    if (blkF > 0) {
+      const int64_t w = b & 15, hi = (b >> 4) & ((int64_t(1) << (m - blkF)) - 1), mid = b >> (4 + m - blkF);
+      h = (hi << blkF) + mid * 16 + w;
+    }
     double fsq, kk;
     if constexpr (P == 2) {
       const double f = (double)((const float*)ft)[h];
@@ -157,7 +164,7 @@ __global__ void __launch_bounds__(256) k_effdim_weights(const void* __restrict__
       kk = ((const double2*)gk)[h].x;
     }
     const double kinv = kk > 0.0 ? fmin(pm / (kk * kk), 3.0e38) : 0.0;
-    wts[h] = make_float2((float)fsq, (float)kinv);
+    wts[b] = make_float2((float)fsq, (float)kinv);
     if (h != 0) qmc += fsq;
   }
   red[threadIdx.x] = qmc;
@@ -483,11 +490,13 @@ int fwt_reduce_f64(int p, int m, const double* in, void* tmp, int batch, const f
                    double* h0_out, int h0_col, int64_t* parts, hipStream_t st);
 int64_t fwt_reduce_parts(int p, int m, size_t elem_bytes);
 bool fwt_p2_split_ok(int m);
-int fwt_p2_f64_first(int m, const double* in, double* out, int batch, hipStream_t st);
+bool fwt_p2_blocked_ok(int m);
+int fwt_p2_first_loge(int m);
+int fwt_p2_f64_first(int m, const double* in, double* out, int batch, bool blocked, hipStream_t st);
 int fwt_p2_f64_reduce_rest(int m, double* data, int batch, const float2* wts, double* partial, double* h0_out,
-                           int h0_col, hipStream_t st);
+                           int h0_col, bool blocked, hipStream_t st);
 int fwt_p2_gen_first(int m, int s, const uint32_t* xtab, int nbytes, const double* tab, int ktab, bool kcol,
-                     int d0, int d1, double* out, hipStream_t st);
+                     int d0, int d1, double* out, bool blocked, hipStream_t st);
 int fwt_p2_f64_rest(int m, double* data, int batch, hipStream_t st);
 
 // ------------------------------------------------------ kernel spectrum
@@ -528,7 +537,8 @@ static int spectrum_into(Net& net, Scratch& sc, const fdwt_kernel* kern, void* w
   }
   if (net.p == 2 && fwt_p2_split_ok(net.m)) {
     // K generated inside the first pass of its transform (no column in memory).
-    if ((rc = fwt_p2_gen_first(net.m, net.s, net.d_xtab, net.nbytes, tab, kTab, true, 0, 0, (double*)gk, st)))
+    if ((rc = fwt_p2_gen_first(net.m, net.s, net.d_xtab, net.nbytes, tab, kTab, true, 0, 0, (double*)gk, false,
+                               st)))
       return rc;
     return fwt_p2_f64_rest(net.m, (double*)gk, 1, st);
   }
@@ -763,6 +773,16 @@ int eff_dim_chunk(const Net& net, size_t budget) {
 
 size_t eff_dim_res_bytes(const Net& net) { return (size_t)(2 * net.s + 2) * sizeof(double); }
 
+// Blocked intermediate layout of the p = 2 variance transforms
+// (FDWT_EFFDIM_BLOCKED = 0 turns it off; results agree to rounding).
+static bool effdim_blocked() {
+  static const bool b = [] {
+    const char* e = getenv("FDWT_EFFDIM_BLOCKED");
+    return e ? atoi(e) != 0 : true;
+  }();
+  return b;
+}
+
 struct EffWs {
   void* gk;
   void* sw;
@@ -823,8 +843,12 @@ int eff_dim_enqueue(Net& net, Scratch& sc, const fdwt_kernel* kern, const void* 
   }
   double* h0 = w.res + ncols + 1;  // h = 0 share of the total
   const double pm = (double)N;
-  if (p == 2) hipLaunchKernelGGL(k_effdim_weights<2>, dim3(kRedBlocks), dim3(256), 0, st, ft, GK, N, pm, w.wts, w.qmc_partial);
-  else hipLaunchKernelGGL(k_effdim_weights<3>, dim3(kRedBlocks), dim3(256), 0, st, ft, GK, N, pm, w.wts, w.qmc_partial);  // any odd p
+  // p = 2 two-pass plans keep the intermediate columns in the blocked layout
+  // (the grouped-sum pass then reads contiguous tiles and weights).
+  const bool blk = p == 2 && fwt_p2_blocked_ok(net.m) && effdim_blocked();
+  const int blkF = blk ? fwt_p2_first_loge(net.m) : 0;
+  if (p == 2) hipLaunchKernelGGL(k_effdim_weights<2>, dim3(kRedBlocks), dim3(256), 0, st, ft, GK, N, pm, w.wts, w.qmc_partial, blkF, net.m);
+  else hipLaunchKernelGGL(k_effdim_weights<3>, dim3(kRedBlocks), dim3(256), 0, st, ft, GK, N, pm, w.wts, w.qmc_partial, 0, net.m);  // any odd p
   FDWT_HIP(hipGetLastError());
   const int h0c = s - 1;  // U_s: its h = 0 term is the h = 0 share of the total
   const double* tr = w.tab + (size_t)s * kTab;
@@ -837,14 +861,14 @@ int eff_dim_enqueue(Net& net, Scratch& sc, const fdwt_kernel* kern, const void* 
       // through memory (kernel data in A, first pass into B after the U_d).
       double* B = (double*)w.B;
       const int u1 = std::min(c1, s), nu = std::max(0, u1 - c0);
-      if (nu > 0 && (rc = fwt_p2_gen_first(net.m, s, net.d_xtab, net.nbytes, tr, kTab, false, c0, u1, B, st)))
+      if (nu > 0 && (rc = fwt_p2_gen_first(net.m, s, net.d_xtab, net.nbytes, tr, kTab, false, c0, u1, B, blk, st)))
         return rc;
       const int q0 = std::max(c0, s);
       if (q0 < c1) {
         if ((rc = launch_kernel_cols(net, w.tab, tr, q0 + 1, c1 + 1, w.A, st))) return rc;
-        if ((rc = fwt_p2_f64_first(net.m, w.A, B + (size_t)nu * N, c1 - q0, st))) return rc;
+        if ((rc = fwt_p2_f64_first(net.m, w.A, B + (size_t)nu * N, c1 - q0, blk, st))) return rc;
       }
-      rc = fwt_p2_f64_reduce_rest(net.m, B, c1 - c0, w.wts, w.partial + (size_t)c0 * parts, h0, h0_col, st);
+      rc = fwt_p2_f64_reduce_rest(net.m, B, c1 - c0, w.wts, w.partial + (size_t)c0 * parts, h0, h0_col, blk, st);
     } else {
       rc = launch_kernel_cols(net, w.tab, tr, c0 + 1, c1 + 1, w.A, st);
       if (rc) return rc;

@@ -86,3 +86,39 @@ def test_three_group_digits_tile_the_pass(loge, wdig):
                 assert cpad(lane + 1024 * wv) + 66 * k == cpad(e)
                 seen.add(e)
     assert seen == set(range(E))
+
+
+@pytest.mark.parametrize("m,F", [(15, 12), (16, 13), (17, 14), (19, 14)])
+def test_blocked_intermediate_layout(m, F):
+    """Two-pass float64 plans with the blocked intermediate (PassDesc::oblk):
+    the first pass (tiles of 2^F, thread mapping e = lane + 64 k + 1024 w)
+    stores element e of tile t at (e >> 4) * 16 NH + 16 t + (e & 15), NH =
+    2^(m - F); the strided pass (rows of 16, NH rows) reads its tile b as the
+    contiguous block b * 16 NH + 16 i + w; the weights kernel maps a blocked
+    position back to the coefficient index h = t 2^F + 16 (e >> 4) + (e & 15).
+    All three agree, and each is a bijection onto [0, 2^m)."""
+    N, E, NH = 1 << m, 1 << F, 1 << (m - F)
+    th = E // 16
+    rs = 16 * NH
+    store = {}
+    for t in range(NH):
+        for wv in range(th // 64):
+            for lane in range(64):
+                for k in range(16):
+                    e = lane + 64 * k + 1024 * wv
+                    off = ((lane >> 4) + 64 * wv) * rs + t * 16 + (lane & 15) + k * 4 * rs
+                    assert off == (e >> 4) * rs + 16 * t + (e & 15)
+                    store[(t, e)] = off
+    assert sorted(store.values()) == list(range(N))
+    inv = {off: te for te, off in store.items()}
+    for b in range(N // rs):                     # strided tiles: one per 16-element column block
+        for i in range(NH):
+            for w in range(16):
+                off = b * rs + 16 * i + w        # base tile*shi (shi = E_strided = rs), row stride 16
+                t, e = inv[off]
+                assert (t, e >> 4, e & 15) == (i, b, w)
+    for off in range(N):
+        w, hi, mid = off & 15, (off >> 4) & (NH - 1), off >> (4 + m - F)
+        h = (hi << F) + mid * 16 + w
+        t, e = inv[off]
+        assert h == (t << F) + e
