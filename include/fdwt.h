@@ -33,8 +33,8 @@
  *     LDS budget in KiB of the float64 pass tiles (default 160: 2^14-element
  *     tiles; other budgets change the pass plan and so the rounding);
  *     FDWT_EFFDIM_BLOCKED = 0 keeps fdwt_eff_dim's p = 2 intermediate
- *     columns in natural order instead of the blocked layout (the rounding
- *     of the sums changes).
+ *     columns in natural order instead of the blocked layout (the variances
+ *     are bit-identical; var_qmc is summed in another order).
  */
 #ifndef FDWT_H
 #define FDWT_H

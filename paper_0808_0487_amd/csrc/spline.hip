@@ -774,7 +774,8 @@ int eff_dim_chunk(const Net& net, size_t budget) {
 size_t eff_dim_res_bytes(const Net& net) { return (size_t)(2 * net.s + 2) * sizeof(double); }
 
 // Blocked intermediate layout of the p = 2 variance transforms
-// (FDWT_EFFDIM_BLOCKED = 0 turns it off; results agree to rounding).
+// (FDWT_EFFDIM_BLOCKED = 0 turns it off: each grouped-sum tile holds the same
+// elements either way, so the variances are bit-identical).
 static bool effdim_blocked() {
   static const bool b = [] {
     const char* e = getenv("FDWT_EFFDIM_BLOCKED");
