@@ -262,10 +262,24 @@ __global__ void __launch_bounds__((P2Shape<LOGE, WDIG>::THREADS))
     return (int64_t)lo * S::W + (int64_t)hi * d.shi;
   };
   Tin pre[EPT];
+  // Converts the prefetched elements into the tile registers.  The empty asm
+  // is a use of each register, so the wait for the prefetch sits here.  A
+  // pass takes the next tile before it stores the current one (or its
+  // partial sum): the prefetch is then the newest memory operation, and its
+  // wait covers at most the stores of the tile before, issued a whole tile
+  // earlier.  With the wait at the top of the loop instead, it also waited
+  // for the stores of the tile just finished.
+  auto take = [&](T (&v)[EPT]) {
+#pragma unroll
+    for (int k = 0; k < EPT; ++k) {
+      v[k] = cvt_in<Tin, T>(pre[k]);
+      asm volatile("" : "+v"(v[k]));
+    }
+  };
   auto prefetch = [&](int l) {
     int col, tile;
     locate(l, col, tile);
-    const Tin* colp = d.in_tab ? (const Tin*)d.in_tab[col] : in + (int64_t)col * d.col_in;
+    const Tin* colp = d.in_tab ? col_ptr<const Tin>(d.in_tab, col) : in + (int64_t)col * d.col_in;
     const gptr<const Tin> src = to_global(colp + tile_base(tile) + goff0);
 #pragma unroll
     for (int k = 0; k < EPT; ++k) pre[k] = src[k * gstep];
@@ -284,10 +298,9 @@ __global__ void __launch_bounds__((P2Shape<LOGE, WDIG>::THREADS))
     const uint32_t goffS = (uint32_t)(lane & (S::W - 1)) + (uint32_t)((lane >> WDIG) + (1024 >> WDIG) * wv) * sd0;
     const uint32_t gstepS = (uint32_t)(64 >> WDIG) * sd0;
     T* lrowS = lds + cpad(lane + 1024 * wv);
+    T v[EPT];
+    if (lb < nb) take(v);
     for (; lb < nb; lb += G) {
-      T v[EPT];
-#pragma unroll
-      for (int k = 0; k < EPT; ++k) v[k] = cvt_in<Tin, T>(pre[k]);
       reg_bfly<4>(v);
 #pragma unroll
       for (int k = 0; k < EPT; ++k) lrow[cpad(k * TH)] = v[k];
@@ -303,42 +316,47 @@ __global__ void __launch_bounds__((P2Shape<LOGE, WDIG>::THREADS))
       }
       prefetch(lb + G < nb ? lb + G : lb);  // unconditional: exact wait counts
       P2Groups<LOGE, WDIG, 0, T, (EPI == EPI_REDUCE && sizeof(T) >= 8) ? 2 : 4, RDL>::run(lds, tid);
+      T y[EPT];
 #pragma unroll
-      for (int k = 0; k < EPT; ++k) v[k] = lrowS[66 * k];
-      reg_bfly<NS>(v);
+      for (int k = 0; k < EPT; ++k) y[k] = lrowS[66 * k];
+      reg_bfly<NS>(y);
       if constexpr (EPI == EPI_STORE) {
+        take(v);  // the next tile (the last round takes its own tile again)
         if (WDIG == 0 && d.oblk) {
           // Blocked layout: e = lane + 64 k + 1024 w has row e >> 4 and column e & 15.
           const int64_t rs = d.oblk;
           const gptr<Tout> dst = to_global(out + (int64_t)col * d.col_out + ((lane >> 4) + 64 * wv) * rs +
                                            (int64_t)tile * 16 + (lane & 15));
 #pragma unroll
-          for (int k = 0; k < EPT; ++k) dst[k * 4 * rs] = cvt_out<T, Tout>(v[k], d.scale, d.scale64);
+          for (int k = 0; k < EPT; ++k) dst[k * 4 * rs] = cvt_out<T, Tout>(y[k], d.scale, d.scale64);
         } else {
           const gptr<Tout> dst =
-              to_global((d.out_tab ? (Tout*)d.out_tab[col] : out + (int64_t)col * d.col_out) + base + goffS);
+              to_global((d.out_tab ? col_ptr<Tout>(d.out_tab, col) : out + (int64_t)col * d.col_out) + base + goffS);
 #pragma unroll
-          for (int k = 0; k < EPT; ++k) dst[k * gstepS] = cvt_out<T, Tout>(v[k], d.scale, d.scale64);
+          for (int k = 0; k < EPT; ++k) dst[k * gstepS] = cvt_out<T, Tout>(y[k], d.scale, d.scale64);
         }
       } else {
         double acc = 0.0;
 #pragma unroll
         for (int k = 0; k < EPT; ++k) {
-          const double rho = fmin(fmax(real_of(v[k]) * (double)wcur[k].y, 0.0), 1.0);
+          const double rho = fmin(fmax(real_of(y[k]) * (double)wcur[k].y, 0.0), 1.0);
           const double term = (double)wcur[k].x * rho;
           acc += term;
           if (col == d.h0_col && base + goffS + (int64_t)k * gstepS == 0) *d.h0_out = term;
         }
         for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off);
+        take(v);
         if (lane == 0) d.partial[((int64_t)col * d.ntiles + tile) * (TH / 64) + wv] = acc;
       }
       lds_barrier();
     }
     return;
   }
+  T v[EPT];
+  if (lb < nb) take(v);
   for (; lb < nb; lb += G) {
 #pragma unroll
-    for (int k = 0; k < EPT; ++k) lrow[cpad(k * TH)] = cvt_in<Tin, T>(pre[k]);
+    for (int k = 0; k < EPT; ++k) lrow[cpad(k * TH)] = v[k];
     lds_barrier();
     int col, tile;
     locate(lb, col, tile);
@@ -358,8 +376,9 @@ __global__ void __launch_bounds__((P2Shape<LOGE, WDIG>::THREADS))
     // butterflies: 2-digit register groups keep it within 128 registers.
     P2Groups<LOGE, WDIG, 0, T, (EPI == EPI_REDUCE && sizeof(T) >= 8) ? 2 : 4>::run(lds, tid);
     if constexpr (EPI == EPI_STORE) {
+      take(v);
       const gptr<Tout> dst =
-          to_global((d.out_tab ? (Tout*)d.out_tab[col] : out + (int64_t)col * d.col_out) + base + goff0);
+          to_global((d.out_tab ? col_ptr<Tout>(d.out_tab, col) : out + (int64_t)col * d.col_out) + base + goff0);
 #pragma unroll
       for (int k = 0; k < EPT; ++k) dst[k * gstep] = cvt_out<T, Tout>(lrow[cpad(k * TH)], d.scale, d.scale64);
     } else {
@@ -373,6 +392,7 @@ __global__ void __launch_bounds__((P2Shape<LOGE, WDIG>::THREADS))
         if (col == d.h0_col && base + goff0 + (int64_t)k * gstep == 0) *d.h0_out = term;
       }
       for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off);
+      take(v);
       if ((tid & 63) == 0) d.partial[((int64_t)col * d.ntiles + tile) * (TH / 64) + (tid >> 6)] = acc;
     }
     lds_barrier();

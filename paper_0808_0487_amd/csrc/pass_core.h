@@ -57,6 +57,16 @@ template <class T>
 __device__ __forceinline__ gptr<T> to_global(T* p) {
   return (gptr<T>)p;
 }
+// Entry i of a column pointer table.  The tables are written before a launch
+// and never by a kernel, so they are read through the constant address
+// space: with a uniform index that is a scalar load, which the vector
+// memory counter does not track (a vector load of the pointer would make
+// the wait for it drain every load and store issued before it).
+template <class T>
+__device__ __forceinline__ T* col_ptr(const void* const* tab, int i) {
+  using cptr = const void* const __attribute__((address_space(4)))*;
+  return (T*)((cptr)tab)[i];
+}
 
 // ------------------------------------------------------------ conversions
 template <class Tin, class T>
