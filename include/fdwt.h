@@ -34,7 +34,11 @@
  *     tiles; other budgets change the pass plan and so the rounding);
  *     FDWT_EFFDIM_BLOCKED = 0 keeps fdwt_eff_dim's p = 2 intermediate
  *     columns in natural order instead of the blocked layout (the variances
- *     are bit-identical; var_qmc is summed in another order).
+ *     are bit-identical; var_qmc is summed in another order);
+ *     FDWT_REDUCE_WKEEP = 0 makes each round of the p = 2 grouped-sum pass
+ *     reload its tile's weights instead of a workgroup keeping one tile's
+ *     weights for all its columns (bit-identical variances).  These two are
+ *     read at each call.
  */
 #ifndef FDWT_H
 #define FDWT_H

@@ -248,7 +248,11 @@ __global__ void __launch_bounds__((P2Shape<LOGE, WDIG>::THREADS))
   const uint32_t gstep = (uint32_t)(TH >> WDIG) * sd0;
   T* lrow = lds + cpad(tid);
   auto locate = [&](int l, int& col, int& tile) {
-    if (EPI == EPI_REDUCE) {
+    if (EPI == EPI_REDUCE && d.wkeep) {
+      const int r = l / G;
+      col = r % d.batch;
+      tile = (r / d.batch) * G + l % G;
+    } else if (EPI == EPI_REDUCE) {
       col = l % d.batch;
       tile = l / d.batch;
     } else {
@@ -294,12 +298,15 @@ __global__ void __launch_bounds__((P2Shape<LOGE, WDIG>::THREADS))
     // after reading the tile back.
     constexpr int NS = (LOGE - 10) < 4 ? (LOGE - 10) : 4;
     constexpr int RDL = 6 - WDIG;
-    const int lane = tid & 63, wv = tid >> 6;
+    // The wave index is uniform in a wave: read as a scalar, the addresses
+    // derived from it stay in scalar registers.
+    const int lane = tid & 63, wv = __builtin_amdgcn_readfirstlane(tid >> 6);
     const uint32_t goffS = (uint32_t)(lane & (S::W - 1)) + (uint32_t)((lane >> WDIG) + (1024 >> WDIG) * wv) * sd0;
     const uint32_t gstepS = (uint32_t)(64 >> WDIG) * sd0;
     T* lrowS = lds + cpad(lane + 1024 * wv);
     T v[EPT];
     if (lb < nb) take(v);
+    float2 wcur[EPI == EPI_REDUCE ? EPT : 1];  // the grouped-sum weights of the tile
     for (; lb < nb; lb += G) {
       reg_bfly<4>(v);
 #pragma unroll
@@ -308,11 +315,12 @@ __global__ void __launch_bounds__((P2Shape<LOGE, WDIG>::THREADS))
       int col, tile;
       locate(lb, col, tile);
       const int64_t base = tile_base(tile);
-      float2 wcur[EPI == EPI_REDUCE ? EPT : 1];
       if constexpr (EPI == EPI_REDUCE) {
-        const float2* wt = d.wts + base + goffS;
+        if (!d.wkeep || col == 0) {  // with wkeep, column 0 starts a new tile
+          const float2* wt = d.wts + base + goffS;
 #pragma unroll
-        for (int k = 0; k < EPT; ++k) wcur[k] = wt[k * gstepS];
+          for (int k = 0; k < EPT; ++k) wcur[k] = wt[k * gstepS];
+        }
       }
       prefetch(lb + G < nb ? lb + G : lb);  // unconditional: exact wait counts
       P2Groups<LOGE, WDIG, 0, T, (EPI == EPI_REDUCE && sizeof(T) >= 8) ? 2 : 4, RDL>::run(lds, tid);
@@ -782,7 +790,16 @@ static int64_t p2_reduce_parts(int m, const P2Pass& g) {
   return ((int64_t(1) << m) >> g.loge) * (threads / 64);
 }
 
+// FDWT_REDUCE_WKEEP = 0 turns the grouped-sum weight reuse off (the sums are
+// bit-identical either way: each partial sum covers the same elements).
+// Read at each launch.
+static bool wkeep_enabled() {
+  const char* e = getenv("FDWT_REDUCE_WKEEP");
+  return !(e && atoi(e) == 0);
+}
+
 template <class Tin, class T, class Tout>
+
 // layout: 0 natural; 1 the (contiguous first) pass stores in the blocked
 // layout of PassDesc::oblk; 2 the (strided) pass reads and writes that
 // blocked layout, where each of its tiles is one contiguous block.
@@ -845,6 +862,9 @@ static int launch_p2(const void* in, void* out, const P2Pass& g, int m, int batc
   if (G >= nb) G = nb;
   if (G >= 64) G -= G % 8;
   d.xcd = (G % 8 == 0 && G >= 64) ? 1 : 0;
+  // Grouped sums over several columns: a workgroup keeps one tile's weights
+  // for all its columns when the tiles split evenly over the grid.
+  d.wkeep = (red && g.loge >= 10 && batch > 1 && ntiles % G == 0 && wkeep_enabled()) ? 1 : 0;
   void* args[] = {(void*)&in, (void*)&out, (void*)&d};
   const double elems = (double)N * batch;
   const double work = red ? elems * sizeof(Tin) + (double)N * sizeof(float2) : elems * (sizeof(Tin) + sizeof(Tout));

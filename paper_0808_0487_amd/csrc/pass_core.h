@@ -32,6 +32,11 @@ struct PassDesc {
   double* partial;
   double* h0_out;
   int32_t h0_col;
+  // Grouped-sum order of the static p = 2 pass (requires ntiles % grid == 0):
+  // when nonzero, block l (grid size G) is column (l / G) % batch of tile
+  // ((l / G) / batch) * G + l % G, so a workgroup takes every column of one
+  // tile in successive rounds and keeps that tile's weights in registers.
+  int32_t wkeep;
   // Blocked output of a contiguous first pass (LOGE >= 10, WDIG 0): when
   // nonzero, element e of tile t is stored at (e >> 4) * oblk + 16 t + (e & 15),
   // oblk = 16 * ntiles, so that each tile of a following strided pass (rows of

@@ -776,12 +776,9 @@ size_t eff_dim_res_bytes(const Net& net) { return (size_t)(2 * net.s + 2) * size
 // Blocked intermediate layout of the p = 2 variance transforms
 // (FDWT_EFFDIM_BLOCKED = 0 turns it off: each grouped-sum tile holds the same
 // elements either way, so the variances are bit-identical).
-static bool effdim_blocked() {
-  static const bool b = [] {
-    const char* e = getenv("FDWT_EFFDIM_BLOCKED");
-    return e ? atoi(e) != 0 : true;
-  }();
-  return b;
+static bool effdim_blocked() {  // read at each call
+  const char* e = getenv("FDWT_EFFDIM_BLOCKED");
+  return e ? atoi(e) != 0 : true;
 }
 
 struct EffWs {

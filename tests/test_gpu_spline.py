@@ -233,3 +233,31 @@ def test_spectrum_cache_follows_the_kernel():
     net.drop_spectrum()
     e2 = net.eff_dim(kern, ft)
     assert np.array_equal(e1["var_trc"], e2["var_trc"]) and np.array_equal(e1["var_sup"], e2["var_sup"])
+
+
+
+def test_effdim_layout_switches_bit_identical(monkeypatch):
+    """The float64 variance passes' memory orders (the blocked intermediate
+    layout, and grouped sums that keep a tile's weights for all its columns)
+    change which workgroup handles which block, not what any partial sum
+    covers: the variances equal those with both turned off, bit for bit (the
+    library reads both switches at each call).  m = 23 gives two tiles per
+    workgroup in the grouped-sum pass, so the switch from one tile's weights
+    to the next is covered."""
+    m, s = 23, 6
+    announce("eff_dim layout switches", m, s)
+    net = fdwt.Net(2, m, s, inputs.upper_triangular_generators(2, m, s, 51))
+    kern = fdwt.Kernel(2.0, inputs.kernel_weights(s))
+    ft = net.forward(net.sample("exp", inputs.family_params("exp", s)))
+    on = net.eff_dim(kern, ft)
+    monkeypatch.setenv("FDWT_REDUCE_WKEEP", "0")
+    monkeypatch.setenv("FDWT_EFFDIM_BLOCKED", "0")
+    off = net.eff_dim(kern, ft)
+    monkeypatch.delenv("FDWT_REDUCE_WKEEP")
+    monkeypatch.delenv("FDWT_EFFDIM_BLOCKED")
+    again = net.eff_dim(kern, ft)
+    for r in (off, again):
+        assert np.array_equal(on["var_trc"], r["var_trc"]) and np.array_equal(on["var_sup"], r["var_sup"])
+        assert on["var_total"] == r["var_total"]
+    assert np.all(np.isfinite(on["var_trc"])) and on["var_total"] > 0
+    net.close()
