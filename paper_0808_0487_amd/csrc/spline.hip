@@ -48,8 +48,8 @@ struct NetArgs {
 // ------------------------------------------------ kernel-data columns (f64)
 // Column layout: 0 = K, 1..s = U_d (d = 1..s), s+1..2s = Q_j (j = 1..s).
 // Writes columns [c0, c1) to out[(c - c0) * N + n].  The elementary symmetric
-// polynomials e_0..e_SMAX live in registers (fully unrolled updates; the
-// coordinates beyond s contribute r = 0 and change nothing).
+// polynomials e_0..e_SMAX live in registers (updates unrolled, truncated per
+// chunk of coordinates where the higher ones are still zero).
 template <int P, int SMAX>
 __global__ void __launch_bounds__(kChunk) k_kernel_cols(NetArgs na, const double* __restrict__ tk,
                                                         const double* __restrict__ tr, int c0, int c1,
@@ -85,19 +85,28 @@ __global__ void __launch_bounds__(kChunk) k_kernel_cols(NetArgs na, const double
     double e[SMAX + 1];
 #pragma unroll
     for (int i = 0; i <= SMAX; ++i) e[i] = i == 0 ? 1.0 : 0.0;
-    for (int j = 0; j < s; ++j) {
-      int t;
-      if constexpr (P == 2) t = lead_p2(pc.X(j, nn), m);
-      else t = lead_odd(oc.X(j, orr, ok), m);
-      K *= ltk[j * kTab + t];
-      if (need_r) {
-        const double r = ltr[j * kTab + t];
-        u = u + r + u * r;  // (1 + u)(1 + r) - 1
-        const int c = 1 + j;
-        if (c >= c0 && c < c1 && n < N) out[(int64_t)(c - c0) * N + n] = u;
-        if (need_q) {
+    // Coordinates in chunks of 4 (SMAX is a multiple of 4): after chunk q
+    // only e[1..4(q + 1)] can be non-zero, so the update of the symmetric
+    // polynomials stops there (a compile-time bound per chunk).  The last
+    // chunk runs to s: s > SMAX only when no symmetric polynomial is wanted
+    // (K and the U_d alone).
 #pragma unroll
-          for (int i = SMAX; i >= 1; --i) e[i] += r * e[i - 1];
+    for (int q = 0; q < SMAX / 4; ++q) {
+      const int je = (q == SMAX / 4 - 1 || 4 * q + 4 > s) ? s : 4 * q + 4;
+      for (int j = 4 * q; j < je; ++j) {
+        int t;
+        if constexpr (P == 2) t = lead_p2(pc.X(j, nn), m);
+        else t = lead_odd(oc.X(j, orr, ok), m);
+        K *= ltk[j * kTab + t];
+        if (need_r) {
+          const double r = ltr[j * kTab + t];
+          u = u + r + u * r;  // (1 + u)(1 + r) - 1
+          const int c = 1 + j;
+          if (c >= c0 && c < c1 && n < N) out[(int64_t)(c - c0) * N + n] = u;
+          if (need_q) {
+#pragma unroll
+            for (int i = 4 * q + 4; i >= 1; --i) e[i] += r * e[i - 1];
+          }
         }
       }
     }
