@@ -115,17 +115,19 @@ def test_alone_and_in_the_mix_bit_identical():
     sv.close()
 
 
-def test_chunked_effdim_bit_identical():
+@pytest.mark.parametrize("m,budget_mib", [(16, 256), (22, 4096)])
+def test_chunked_effdim_bit_identical(m, budget_mib):
     """eff_dim in column chunks (the server's effdim_chunk_bytes: here 5 of the
     2s = 12 columns at a time, so one chunk holds U_6 and Q_1..Q_4) equals the
     one-call path, which takes all columns at once, bit for bit: every
-    column's transform and partial sums are the same in any grouping.  p = 2,
-    m = 16 uses the generated truncation-column pass."""
-    announce("server chunked eff_dim")
-    p, m, s = 2, 16, 6
+    column's transform and partial sums are the same in any grouping.  p = 2
+    uses the generated truncation-column pass; at m = 22 the grouped-sum pass
+    keeps each tile's weights for the columns of a chunk."""
+    announce("server chunked eff_dim", m)
+    p, s = 2, 6
     reqs = [make_request("eff_dim", p, m, s, 300 + i, fam) for i, fam in enumerate(("product", "exp"))]
     per_col = (p ** m) * 16
-    sv = fdwt.Server(256 * MiB, lanes=2, effdim_chunk_bytes=5 * per_col)
+    sv = fdwt.Server(budget_mib * MiB, lanes=2, effdim_chunk_bytes=5 * per_col)
     served = run_all(sv, reqs)
     sv.close()
     for r, (_, res) in zip(reqs, served):
