@@ -26,10 +26,11 @@
  *     code; fdwt_last_error() gives a message for the calling thread.  No
  *     exception crosses the ABI.  Invalid arguments are rejected before any
  *     work is enqueued.
- *   - Tuning knobs read once per process from the environment:
- *     FDWT_EFFDIM_CHUNK_MB, the workspace budget of fdwt_eff_dim's
- *     kernel-data columns in MiB (default 12288; smaller budgets process the
- *     columns in chunks, with bit-identical results); FDWT_LDS_KB_WIDE, the
+ *   - Tuning knobs from the environment (the first two read once per
+ *     process, the last two at each call): FDWT_EFFDIM_CHUNK_MB, the
+ *     workspace budget of fdwt_eff_dim's kernel-data columns in MiB
+ *     (default 12288; smaller budgets process the columns in chunks, with
+ *     bit-identical results); FDWT_LDS_KB_WIDE, the
  *     LDS budget in KiB of the float64 pass tiles (default 160: 2^14-element
  *     tiles; other budgets change the pass plan and so the rounding);
  *     FDWT_EFFDIM_BLOCKED = 0 keeps fdwt_eff_dim's p = 2 intermediate
@@ -37,8 +38,7 @@
  *     are bit-identical; var_qmc is summed in another order);
  *     FDWT_REDUCE_WKEEP = 0 makes each round of the p = 2 grouped-sum pass
  *     reload its tile's weights instead of a workgroup keeping one tile's
- *     weights for all its columns (bit-identical variances).  These two are
- *     read at each call.
+ *     weights for all its columns (bit-identical variances).
  */
 #ifndef FDWT_H
 #define FDWT_H
