@@ -87,8 +87,8 @@ int fdwt_net_info(const fdwt_net* net, int* p, int* m, int* s, int64_t* n_points
  * X_dev uint32 [s][N].  Bit-exact. */
 int fdwt_net_digits(const fdwt_net* net, uint32_t* X_dev, void* stream);
 
-/* Points x_{j,n} = X_{j,n} p^-m as float into x_dev [s][N] (exact for p = 2
- * and m <= 24, otherwise within 1.5 ulp). */
+/* Points x_{j,n} = X_{j,n} p^-m as float into x_dev [s][N], correctly
+ * rounded to nearest (exact for p = 2 and m <= 24). */
 int fdwt_net_points(const fdwt_net* net, float* x_dev, void* stream);
 
 void fdwt_net_free(fdwt_net* net);

@@ -4,6 +4,14 @@
 //
 // Coordinates come from the table machinery of coords.h (byte tables and
 // per-group XORs for p = 2, packed digits for p odd).
+//
+// Points in float are x = X p^-m rounded once to nearest.  p = 2: (float)X
+// rounds (only for m > 24) and the power of two scales exactly.  p odd:
+// x_d = (double)X * (double)p^-m is within 2^-52 (relative) of X / p^m, and
+// X / p^m is at least 2^-25 p^-m >= 2^-51 (relative) away from every
+// midpoint between two floats (a midpoint is M 2^-k with M odd, and
+// X 2^k - M p^m is a non-zero integer since M p^m is odd), so rounding x_d
+// to float gives the correctly rounded point.
 #include "coords.h"
 #include "dev_math.h"
 
@@ -40,7 +48,7 @@ __global__ void __launch_bounds__(kChunk) k_coords_p2(const uint32_t* xtab, int 
 
 template <int P, int MODE>
 __global__ void __launch_bounds__(kChunk) k_coords_odd(const uint64_t* ptab, int s, int m, int64_t N,
-                                                       float inv_pm, void* out) {
+                                                       double inv_pm, void* out) {
   extern __shared__ __align__(16) uint64_t lds_odd[];
   OddCoords<P> oc{ptab, s, m, lds_odd, lds_odd + s * OddCoords<P>::PK};
   oc.stage_tables();
@@ -55,7 +63,7 @@ __global__ void __launch_bounds__(kChunk) k_coords_odd(const uint64_t* ptab, int
       for (int j = 0; j < s; ++j) {
         const uint64_t pk = oc.X(j, r, k);
         if (MODE == CM_DIGITS) ((uint32_t*)out)[(int64_t)j * N + n] = canon_odd<P>(pk, m);
-        if (MODE == CM_POINTS) ((float*)out)[(int64_t)j * N + n] = (float)canon_odd<P>(pk, m) * inv_pm;
+        if (MODE == CM_POINTS) ((float*)out)[(int64_t)j * N + n] = (float)((double)canon_odd<P>(pk, m) * inv_pm);
         if (MODE == CM_SHIFTED) ((uint64_t*)out)[(int64_t)j * N + n] = eval_string_odd<P>(pk, m);
       }
     }
@@ -105,15 +113,16 @@ __device__ __forceinline__ typename FamState<FAM>::T fam_init(const FamilyArgs& 
   if constexpr (FAM == FDWT_FAMILY_ASIAN) return make_double2(fa.g[0], exp(fa.g[0]));  // S_0 in the mean
   else return FAM == FDWT_FAMILY_EXP ? 0.0f : 1.0f;
 }
-// One coordinate: X its integer value, inv_f / inv_d the factor p^-m.
-template <int FAM>
+// One coordinate: X its integer value, inv_f / inv_d the factor p^-m (inv_f
+// is used only for p = 2, where it is a power of two).
+template <int FAM, bool ODD>
 __device__ __forceinline__ void fam_step(typename FamState<FAM>::T& acc, const FamilyArgs& fa, float a, float inv1a,
                                          uint32_t X, float inv_f, double inv_d) {
   if constexpr (FAM == FDWT_FAMILY_ASIAN) {
     acc.x += fa.g[2] + fa.g[3] * inv_normal((double)X * inv_d);
     acc.y += exp(acc.x);
   } else {
-    const float x = (float)X * inv_f;
+    const float x = ODD ? (float)((double)X * inv_d) : (float)X * inv_f;
     if constexpr (FAM == FDWT_FAMILY_PRODUCT) acc = acc * (1.0f + a * (x - 0.5f));
     else if constexpr (FAM == FDWT_FAMILY_EXP) acc = acc + a * x * x;
     else acc = acc * ((fabsf(4.0f * x - 2.0f) + a) * inv1a);
@@ -171,7 +180,7 @@ __global__ void __launch_bounds__(256) k_sample_p2(const uint32_t* xtab, int nby
                                r2.x, r2.y, r2.z, r2.w, r3.x, r3.y, r3.z, r3.w};
       const float a = la[j], ia = li[j];
 #pragma unroll
-      for (int k = 0; k < 16; ++k) fam_step<FAM>(acc[k], fa, a, ia, xl ^ kx[k], inv, (double)inv);
+      for (int k = 0; k < 16; ++k) fam_step<FAM, false>(acc[k], fa, a, ia, xl ^ kx[k], inv, (double)inv);
     }
 #pragma unroll
     for (int k = 0; k < 16; ++k) {
@@ -183,7 +192,7 @@ __global__ void __launch_bounds__(256) k_sample_p2(const uint32_t* xtab, int nby
 
 template <int P, int FAM>
 __global__ void __launch_bounds__(kChunk) k_sample_odd(const uint64_t* ptab, FamilyArgs fa, int m, int64_t N,
-                                                       float inv_pm, double inv_pm_d, float* f) {
+                                                       double inv_pm_d, float* f) {
   extern __shared__ __align__(16) uint64_t lds_odd[];
   const int s = fa.s;
   OddCoords<P> oc{ptab, s, m, lds_odd, lds_odd + s * OddCoords<P>::PK};
@@ -204,7 +213,7 @@ __global__ void __launch_bounds__(kChunk) k_sample_odd(const uint64_t* ptab, Fam
       oc.split(n, r, k);
       auto acc = fam_init<FAM>(fa);
       for (int j = 0; j < s; ++j)
-        fam_step<FAM>(acc, fa, la[j], li[j], canon_odd<P>(oc.X(j, r, k), m), inv_pm, inv_pm_d);
+        fam_step<FAM, true>(acc, fa, la[j], li[j], canon_odd<P>(oc.X(j, r, k), m), 0.0f, inv_pm_d);
       f[n] = fam_final<FAM>(acc, fa);
     }
   }
@@ -218,7 +227,7 @@ static unsigned grid_for(int64_t N, int threads) {
   return (unsigned)std::min<int64_t>(b, 2048);
 }
 
-static float inv_pm(const Net& net) { return (float)(1.0 / (double)net.N); }
+static double inv_pm(const Net& net) { return 1.0 / (double)net.N; }
 
 template <int MODE>
 static int coords(const Net& net, void* out, hipStream_t st) {
@@ -263,17 +272,17 @@ static int sample_fam(const Net& net, const FamilyArgs& fa, float* f, unsigned g
     const size_t lds = OddCoords<3>::lds_bytes(net.s) + 2 * kMaxS * 4;
     if (int rc = allow_lds((const void*)k_sample_odd<3, FAM>, lds)) return rc;
     hipLaunchKernelGGL((k_sample_odd<3, FAM>), dim3(g), dim3(kChunk), lds, st, net.d_ptab, fa, net.m, net.N,
-                       inv_pm(net), 1.0 / (double)net.N, f);
+                       inv_pm(net), f);
   } else if (net.p == 5) {
     const size_t lds = OddCoords<5>::lds_bytes(net.s) + 2 * kMaxS * 4;
     if (int rc = allow_lds((const void*)k_sample_odd<5, FAM>, lds)) return rc;
     hipLaunchKernelGGL((k_sample_odd<5, FAM>), dim3(g), dim3(kChunk), lds, st, net.d_ptab, fa, net.m, net.N,
-                       inv_pm(net), 1.0 / (double)net.N, f);
+                       inv_pm(net), f);
   } else {
     const size_t lds = OddCoords<7>::lds_bytes(net.s) + 2 * kMaxS * 4;
     if (int rc = allow_lds((const void*)k_sample_odd<7, FAM>, lds)) return rc;
     hipLaunchKernelGGL((k_sample_odd<7, FAM>), dim3(g), dim3(kChunk), lds, st, net.d_ptab, fa, net.m, net.N,
-                       inv_pm(net), 1.0 / (double)net.N, f);
+                       inv_pm(net), f);
   }
   return FDWT_OK;
 }

@@ -6,7 +6,7 @@ import torch
 
 from oracle import families, net as onet, walsh
 from paper_0808_0487_amd import fdwt, inputs
-from tests.gpu_common import announce, nrel, sample_indices
+from tests.gpu_common import announce, correctly_rounded_points, nrel, sample_indices
 
 pytestmark = pytest.mark.gpu
 
@@ -23,11 +23,7 @@ def test_net_digits_bit_exact(p, m, s, seed):
     X = net.digits().cpu().numpy().astype(np.int64)
     assert np.array_equal(X, onet.net_int(p, m, C))
     x = net.points().cpu().numpy()
-    xo = onet.net_points(p, m, C)
-    # exact for p = 2 (m <= 24); within 1.5 ulp otherwise (as documented)
-    ulp = np.spacing(xo.astype(np.float32)).astype(np.float64)
-    bound = 0.0 if p == 2 else 1.5
-    assert np.all(np.abs(x.astype(np.float64) - xo) <= bound * ulp + (0.5 * ulp if p != 2 else 0.0))
+    assert np.array_equal(x, correctly_rounded_points(p, m, onet.net_points(p, m, C)))
 
 
 @pytest.mark.parametrize("p,m,s,seed", [(2, 6, 3, 21), (3, 4, 3, 22)])
@@ -38,17 +34,23 @@ def test_singular_generators_bit_exact(p, m, s, seed):
     assert np.array_equal(net.digits().cpu().numpy().astype(np.int64), onet.net_int(p, m, C))
 
 
-@pytest.mark.parametrize("p,m,s,seed", [(2, 24, 20, 2), (3, 14, 10, 3), (5, 11, 8, 4), (2, 26, 3, 5)])
+@pytest.mark.parametrize("p,m,s,seed", [(2, 24, 20, 2), (3, 14, 10, 3), (5, 11, 8, 4), (2, 26, 3, 5),
+                                        (3, 16, 3, 6)])
 def test_net_digits_full_size_sampled(p, m, s, seed):
-    """Full-size nets: sampled points bit-exact; every coordinate a
-    permutation of 0..p^m-1 (non-singular generators)."""
+    """Full-size nets: sampled digits bit-exact and sampled points
+    correctly rounded (p = 3, m = 16 and p = 2, m = 26 have X > 2^24); every
+    coordinate a permutation of 0..p^m-1 (non-singular generators)."""
     announce("net_digits full", p, m, s, seed)
     C = inputs.upper_triangular_generators(p, m, s, seed)
     net = fdwt.Net(p, m, s, C)
     Xd = net.digits()
     idx = sample_indices(p ** m, 20000, seed)
-    got = Xd[:, torch.from_numpy(idx).cuda()].cpu().numpy().astype(np.int64)
-    assert np.array_equal(got, onet.net_int(p, m, C, idx))
+    it = torch.from_numpy(idx).cuda()
+    got = Xd[:, it].cpu().numpy().astype(np.int64)
+    Xo = onet.net_int(p, m, C, idx)
+    assert np.array_equal(got, Xo)
+    x = net.points()[:, it].cpu().numpy()
+    assert np.array_equal(x, correctly_rounded_points(p, m, Xo.astype(np.float64) / float(p ** m)))
     ar = torch.arange(p ** m, dtype=torch.int32, device="cuda")
     for j in range(s):
         assert torch.equal(torch.sort(Xd[j])[0], ar)

@@ -128,3 +128,26 @@ def test_asian_payoff_limits():
     assert abs(v - np.exp(-r * T) * (np.mean(S0 * np.exp(r * t)) - K)) <= 1e-8
     x[0, 0] = 0.0
     assert families.asian(x, S0, K, 0.2, r, T)[0] == 0.0  # only S0 remains: (S0/(s+1) - K)+ = 0
+
+
+@pytest.mark.parametrize("p,m", [(3, 16), (5, 11), (7, 9), (3, 9), (2, 26)])
+def test_float_points_from_the_float64_quotient_are_correctly_rounded(p, m):
+    """Definition of a digital net: x = X p^-m.  The float32 points the GPU
+    tests expect (the float64 quotient cast to float32) equal the float32
+    nearest to the exact rational X / p^m, found here with Fractions among
+    the neighbours of the candidate.  For odd p no ties occur (X / p^m is
+    never a float midpoint); for p = 2 at m > 24 they do, and go to the even
+    mantissa, as the device's conversion of X to float rounds them."""
+    from fractions import Fraction
+    from tests.gpu_common import correctly_rounded_points
+    N = p ** m
+    X = np.unique(np.concatenate([np.arange(0, 200), N - 1 - np.arange(0, 200),
+                                  np.random.default_rng(p * 100 + m).integers(0, N, 3000)]))
+    got = correctly_rounded_points(p, m, X.astype(np.float64) / float(N))
+    for Xi, g in zip(X.tolist(), got.tolist()):
+        q = Fraction(Xi, N)
+        c = np.float32(g)
+        even = int(np.array(c).view(np.uint32)) & 1 == 0
+        for nb in (np.nextafter(c, np.float32(-1)), np.nextafter(c, np.float32(2))):
+            dc, dn = abs(Fraction(float(c)) - q), abs(Fraction(float(nb)) - q)
+            assert dc < dn or (p == 2 and dc == dn and even), (p, m, Xi)
