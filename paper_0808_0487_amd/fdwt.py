@@ -144,6 +144,34 @@ def _ptr(t):
     return ctypes.c_void_p(t.data_ptr())
 
 
+def _need(t, name, numel, dtypes, device=None):
+    """Validate a tensor before its pointer crosses the ABI: the kernels
+    read or write exactly `numel` contiguous elements of one of `dtypes`
+    (torch dtype names) through it, on the net's device, so a shorter,
+    differently typed, strided or misplaced tensor is refused here with
+    ValueError (a host tensor is refused by _ptr, after every tensor of the
+    call has passed these checks)."""
+    if t is None:
+        raise ValueError("%s is required" % name)
+    dt = str(t.dtype).replace("torch.", "")
+    if dt not in dtypes:
+        raise ValueError("%s must be %s, got %s" % (name, " or ".join(dtypes), dt))
+    if t.numel() != numel:
+        raise ValueError("%s must hold %d elements, got %d" % (name, numel, t.numel()))
+    if not t.is_contiguous():
+        raise ValueError("%s must be contiguous" % name)
+    if device is not None and t.is_cuda and t.device.index != device:
+        raise ValueError("%s is on cuda:%s, the net on cuda:%d" % (name, t.device.index, device))
+    return t
+
+
+def _need_params(a, n, name="a"):
+    a = np.ascontiguousarray(a, dtype=np.float64)
+    if a.shape != (n,):
+        raise ValueError("%s must have %d values, got shape %s" % (name, n, a.shape))
+    return a
+
+
 def _type_of(t):
     import torch
     return {torch.float32: F32, torch.int32: I32, torch.complex64: CF32,
@@ -229,6 +257,28 @@ class Net:
         self.h = h
         self.p, self.m, self.s = p, m, s
         self.N = p ** m
+        import torch
+        self.device = torch.cuda.current_device()
+
+    # Element types of transform coefficients and of each element type's
+    # forward output, per p (fdwt_dwt_forward).
+    def _coef_dtype(self):
+        return "float32" if self.p == 2 else "complex64"
+
+    def _fwd_out_dtype(self, dt):
+        if dt == "int32":
+            return "int32"
+        if dt in ("float64", "complex128"):
+            return "float64" if self.p == 2 else "complex128"
+        return "float32" if self.p == 2 else "complex64"
+
+    def _queries(self, q):
+        """q: uint32 digits [s][nq] (or int32 holding their bit patterns);
+        returns nq."""
+        if q is None or q.dim() != 2 or q.shape[0] != self.s:
+            raise ValueError("queries must have shape (s, nq) = (%d, nq)" % self.s)
+        _need(q, "queries", q.numel(), ("int32", "uint32"), self.device)
+        return q.shape[1]
 
     def close(self):
         if self.h:
@@ -251,6 +301,7 @@ class Net:
         import torch
         if out is None:
             out = torch.empty((self.s, self.N), dtype=torch.int32, device="cuda")
+        _need(out, "out", self.s * self.N, ("int32",), self.device)
         _check(lib().fdwt_net_digits(self.h, _ptr(out), _stream(stream)))
         return out
 
@@ -258,14 +309,16 @@ class Net:
         import torch
         if out is None:
             out = torch.empty((self.s, self.N), dtype=torch.float32, device="cuda")
+        _need(out, "out", self.s * self.N, ("float32",), self.device)
         _check(lib().fdwt_net_points(self.h, _ptr(out), _stream(stream)))
         return out
 
     def sample(self, family, a, out=None, stream=None):
         import torch
-        a = np.ascontiguousarray(a, dtype=np.float64)
+        a = _need_params(a, 5 if family == "asian" else self.s)
         if out is None:
             out = torch.empty(self.N, dtype=torch.float32, device="cuda")
+        _need(out, "out", self.N, ("float32",), self.device)
         _check(lib().fdwt_sample(self.h, FAMILY[family], a.ctypes.data_as(ctypes.c_void_p), _ptr(out),
                                  _stream(stream)))
         return out
@@ -288,15 +341,19 @@ class Net:
             else:
                 dt = torch.float32 if self.p == 2 else torch.complex64
             out = torch.empty(self.N, dtype=dt, device=x.device)
+        ins = ("float32", "int32", "float64") if self.p == 2 else ("float32", "complex64", "float64", "complex128")
+        _need(x, "x", self.N, ins, self.device)
+        _need(out, "out", self.N, (self._fwd_out_dtype(str(x.dtype).replace("torch.", "")),), self.device)
         _check(lib().fdwt_dwt_forward(self.h, _type_of(x), _ptr(x), _type_of(out), _ptr(out), _stream(stream)))
         return out
 
     def forward_family(self, family, a, out=None, stream=None):
         """dwt_forward of f sampled on the device (fdwt_dwt_forward_family)."""
         import torch
-        a = np.ascontiguousarray(a, dtype=np.float64)
+        a = _need_params(a, 5 if family == "asian" else self.s)
         if out is None:
             out = torch.empty(self.N, dtype=torch.float32 if self.p == 2 else torch.complex64, device="cuda")
+        _need(out, "out", self.N, (self._coef_dtype(),), self.device)
         _check(lib().fdwt_dwt_forward_family(self.h, FAMILY[family], a.ctypes.data_as(ctypes.c_void_p),
                                              _type_of(out), _ptr(out), _stream(stream)))
         return out
@@ -312,6 +369,14 @@ class Net:
             elif real and x.dtype == torch.complex128:
                 dt = torch.float64
             out = torch.empty(self.N, dtype=dt, device=x.device)
+        if self.p == 2:
+            ins, outs = ("float32", "int32", "float64"), {"float32": ("float32",), "int32": ("int32",),
+                                                           "float64": ("float64",)}
+        else:
+            ins, outs = ("complex64", "complex128"), {"complex64": ("complex64", "float32"),
+                                                      "complex128": ("complex128", "float64")}
+        _need(x, "x", self.N, ins, self.device)
+        _need(out, "out", self.N, outs[str(x.dtype).replace("torch.", "")], self.device)
         _check(lib().fdwt_dwt_inverse(self.h, _type_of(x), _ptr(x), _type_of(out), _ptr(out), _stream(stream)))
         return out
 
@@ -320,14 +385,18 @@ class Net:
         import torch
         if out is None:
             out = torch.empty(self.N, dtype=torch.float32, device=ft.device)
+        _need(ft, "ft", self.N, (self._coef_dtype(),), self.device)
+        _need(out, "out", self.N, ("float32",), self.device)
         _check(lib().fdwt_spline_coef(self.h, kern.c, _type_of(ft), _ptr(ft), _ptr(out), _stream(stream)))
         return out
 
     def spline_eval(self, kern, c, q, out=None, stream=None):
         import torch
-        nq = q.shape[1]
+        nq = self._queries(q)
         if out is None:
             out = torch.empty(nq, dtype=torch.float32, device=c.device)
+        _need(c, "c", self.N, ("float32",), self.device)
+        _need(out, "out", nq, ("float32",), self.device)
         _check(lib().fdwt_spline_eval(self.h, kern.c, _ptr(c), nq, _ptr(q), _ptr(out), _stream(stream)))
         return out
 
@@ -335,9 +404,13 @@ class Net:
         import torch
         if c_out is None:
             c_out = torch.empty(self.N, dtype=torch.float32, device=f.device)
-        nq = 0 if q is None else q.shape[1]
+        nq = 0 if q is None else self._queries(q)
         if nq and sf_out is None:
             sf_out = torch.empty(nq, dtype=torch.float32, device=f.device)
+        _need(f, "f", self.N, ("float32",), self.device)
+        _need(c_out, "c_out", self.N, ("float32",), self.device)
+        if nq:
+            _need(sf_out, "sf_out", nq, ("float32",), self.device)
         _check(lib().fdwt_walsh_interp(self.h, kern.c, _ptr(f), _ptr(c_out), nq, _ptr(q) if nq else None,
                                        _ptr(sf_out) if nq else None, _stream(stream)))
         return c_out, sf_out
@@ -347,6 +420,7 @@ class Net:
         """Section 5.1 cost (and Sf at the second half) for a p = 2 net of
         2N points; f2 float32 [2N] on the device."""
         import torch
+        _need(f2, "f2", self.N, ("float32",), self.device)
         sf = torch.empty(self.N // 2, dtype=torch.float32, device=f2.device) if want_sf else None
         c = ctypes.c_double()
         _check(lib().fdwt_split_cost(self.h, _ptr(f2), alpha, beta, q, _ptr(sf) if want_sf else None,
@@ -354,12 +428,14 @@ class Net:
         return (c.value, sf) if want_sf else c.value
 
     def kernel_tune(self, f2, start=(2.0, 1.0, -2.0), max_evals=200):
-        st = np.ascontiguousarray(start, dtype=np.float64)
+        _need(f2, "f2", self.N, ("float32",), self.device)
+        st = _need_params(start, 3, "start")
         out = KernelFitC()
         _check(lib().fdwt_kernel_tune(self.h, _ptr(f2), st.ctypes.data, max_evals, ctypes.byref(out), _stream(None)))
         return {"alpha": out.alpha, "beta": out.beta, "q": out.q, "cost": out.cost, "evaluations": out.evaluations}
 
     def eff_dim(self, kern, ft, stream=None):
+        _need(ft, "ft", self.N, (self._coef_dtype(),), self.device)
         trc = np.zeros(self.s + 1)
         sup = np.zeros(self.s + 1)
         out = EffDimC(trc.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),

@@ -37,3 +37,43 @@ def correctly_rounded_points(p, m, xo):
     (pinned against exact rationals in tests/test_oracle_net.py)."""
     assert p ** m <= 2 ** 26
     return np.asarray(xo, dtype=np.float64).astype(np.float32)
+
+
+def net_int_p2_doubling(m, C):
+    """X_{j,n} of a p = 2 net at every n, from the Z_2-linearity of
+    y = C_j n (Definition of a digital net): for n < 2^c,
+    X_j(n + 2^c) = X_j(n) XOR X_j(2^c), where X_j(2^c) is column c of C_j read
+    as an m-bit integer (row r -> bit m-1-r).  O(N) per coordinate, for inputs
+    at sizes where oracle.net.net_int takes minutes; pinned against it in
+    tests/test_oracle_net.py."""
+    C = np.asarray(C, dtype=np.int64) % 2
+    s = C.shape[0]
+    w = np.int64(1) << (m - 1 - np.arange(m, dtype=np.int64))
+    X = np.zeros((s, 1 << m), dtype=np.int64)
+    for j in range(s):
+        cols = C[j].T @ w
+        for c in range(m):
+            X[j, 1 << c:2 << c] = X[j, :1 << c] ^ cols[c]
+    return X
+
+
+def first_diff_digit_p2(D, a, b):
+    """Index (1-based, most significant first) of the first binary digit in
+    which the D-digit integers a and b differ, 0 when equal: D minus the bit
+    length of a XOR b, plus one.  The same function as
+    oracle.kernel.first_diff_digit for p = 2 (pinned in
+    tests/test_oracle_net.py), vectorised through the bit length."""
+    z = np.bitwise_xor(np.asarray(a, dtype=np.int64), np.asarray(b, dtype=np.int64))
+    _, e = np.frexp(z.astype(np.float64))  # z = mant 2^e, mant in [0.5, 1): e = bit length (exact, z < 2^53)
+    return np.where(z == 0, 0, D - e + 1).astype(np.int64)
+
+
+def kernel_section_p2(alpha, gamma, D, X, Xv):
+    """K(x_n, x_v) = prod_j [1 + gamma_j K'(x_{n,j} (-) x_{v,j}, 0)] (Section 4)
+    for p = 2 points given as D-digit integers X (s, N) and Xv (s,), with the
+    oracle's closed form of K'."""
+    from oracle import kernel
+    out = np.ones(X.shape[1])
+    for j in range(X.shape[0]):
+        out *= 1.0 + gamma[j] * kernel.kprime_closed(2, alpha, first_diff_digit_p2(D, X[j], Xv[j]))
+    return out

@@ -1,5 +1,7 @@
 """Forward and inverse transforms on the GPU against the oracle's
 definition (Eq. (eq_dwalshcoeff), Lemma of Section 3.3)."""
+import ctypes
+
 import numpy as np
 import pytest
 import torch
@@ -185,8 +187,13 @@ def test_in_place_and_errors():
     g = f.clone()
     net.forward(g, out=g)
     assert torch.equal(g, ref)
-    with pytest.raises(fdwt.FdwtError):
-        net.forward(f, out=torch.empty(2 ** m, dtype=torch.int32, device="cuda"))
+    bad = torch.empty(2 ** m, dtype=torch.int32, device="cuda")
+    with pytest.raises(ValueError):  # the binding refuses the pair of types
+        net.forward(f, out=bad)
+    # and so does the library, called directly
+    rc = fdwt.lib().fdwt_dwt_forward(net.h, fdwt.F32, ctypes.c_void_p(f.data_ptr()), fdwt.I32,
+                                     ctypes.c_void_p(bad.data_ptr()), None)
+    assert rc == fdwt.EINVAL
 
 
 @pytest.mark.parametrize("p,m", [(2, 5), (2, 13), (2, 18), (3, 6), (3, 11), (5, 7)])
@@ -206,3 +213,22 @@ def test_double_precision_transforms(p, m):
     back = net.inverse(torch.from_numpy(ft).cuda(), real=True).cpu().numpy()
     assert back.dtype == np.float64
     assert nrel(back, f) <= 1e-13
+
+
+@pytest.mark.parametrize("p,m,seed", [(3, 9, 1), (5, 6, 2), (7, 5, 3), (3, 13, 4), (5, 9, 5)])
+def test_inverse_of_arbitrary_complex_coefficients(p, m, seed):
+    """Algorithm 2 on coefficients that are not the transform of real data
+    (random, non-Hermitian): the complex output against the Lemma's sum at
+    sampled n, and the complex-to-real output equal to its real part."""
+    announce("inverse non-Hermitian", p, m, seed)
+    N = p ** m
+    g = np.random.default_rng(seed)
+    ct = g.standard_normal(N) + 1j * g.standard_normal(N)
+    net = fdwt.Net(p, m, 1, inputs.upper_triangular_generators(p, m, 1, seed))
+    cd = torch.from_numpy(ct.astype(np.complex64)).cuda()
+    got = net.inverse(cd).cpu().numpy()
+    real = net.inverse(cd, real=True).cpu().numpy()
+    ns = sample_indices(N, 300, seed)
+    ref = walsh.idwt_phase(p, m, ct.astype(np.complex64).astype(np.complex128), ns)
+    assert nrel(got[ns], ref) <= 1e-5
+    assert np.array_equal(real, got.real)

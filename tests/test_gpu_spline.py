@@ -44,7 +44,14 @@ def test_spline_coefficients_solve_the_interpolation_system(p, m, s, seed):
     assert nrel(c, co) <= max(1e-5, 4e-7 * cond)
 
 
-@pytest.mark.parametrize("p,m,s,seed", CASES + [(2, 7, 12, 15), (2, 6, 40, 16), (3, 4, 33, 17), (5, 3, 64, 18)])
+# every register length of the evaluation kernel (s <= 8, 16, 32, 64) for
+# each p
+QUERY_WIDE = [(2, 7, 12, 15), (2, 6, 40, 16), (3, 4, 33, 17), (5, 3, 64, 18), (3, 5, 12, 19), (3, 4, 16, 20),
+              (2, 7, 20, 21), (2, 6, 32, 22), (3, 4, 25, 23), (5, 3, 14, 24), (7, 3, 10, 25), (5, 3, 30, 26),
+              (7, 3, 20, 27), (7, 3, 48, 28)]
+
+
+@pytest.mark.parametrize("p,m,s,seed", CASES + QUERY_WIDE)
 def test_interpolant_at_queries(p, m, s, seed):
     """Sf at random D-digit queries against the oracle's direct sum with the
     oracle's coefficients, and Sf(x_n) = f(x_n) at net points."""

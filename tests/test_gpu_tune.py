@@ -23,7 +23,9 @@ def setup(m2, s, seed, a="k"):
 
 
 @pytest.mark.parametrize("m2,s,seed,prm", [(6, 2, 1, (2.0, 1.0, -2.0)), (9, 4, 2, (1.6, 0.5, -1.0)),
-                                           (12, 8, 3, (3.0, 2.0, -2.5)), (11, 5, 4, (2.2, 0.3, 0.0))])
+                                           (12, 8, 3, (3.0, 2.0, -2.5)), (11, 5, 4, (2.2, 0.3, 0.0)),
+                                           (10, 20, 6, (2.0, 1.0, -2.0)), (10, 40, 7, (1.8, 0.8, -1.5)),
+                                           (10, 40, 8, (2.5, 1.5, -3.0))])
 def test_second_half_and_cost_against_oracle(m2, s, seed, prm):
     announce("split cost", m2, s, seed, prm)
     C2, f2, net, fd = setup(m2, s, seed)

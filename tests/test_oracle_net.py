@@ -151,3 +151,35 @@ def test_float_points_from_the_float64_quotient_are_correctly_rounded(p, m):
         for nb in (np.nextafter(c, np.float32(-1)), np.nextafter(c, np.float32(2))):
             dc, dn = abs(Fraction(float(c)) - q), abs(Fraction(float(nb)) - q)
             assert dc < dn or (p == 2 and dc == dn and even), (p, m, Xi)
+
+
+def test_p2_doubling_net_equals_the_oracle():
+    """The tests' O(N) construction of p = 2 nets (XOR doubling) equals the
+    oracle's matrix-vector definition: every point at m = 12, sampled points
+    at m = 24."""
+    from tests.gpu_common import net_int_p2_doubling
+    for m, s, seed in ((12, 3, 1), (9, 5, 2)):
+        C = inputs.random_generators(2, m, s, seed)
+        assert np.array_equal(net_int_p2_doubling(m, C), net.net_int(2, m, C))
+    C = inputs.upper_triangular_generators(2, 24, 2, 9)
+    X = net_int_p2_doubling(24, C)
+    idx = np.random.default_rng(3).integers(0, 1 << 24, 3000)
+    assert np.array_equal(X[:, idx], net.net_int(2, 24, C, idx))
+
+
+def test_p2_first_differing_digit_and_kernel_section_equal_the_oracle():
+    """The bit-length form of the first differing digit equals the oracle's
+    digit-by-digit one (D = 24 and 32), and the p = 2 kernel section built on
+    it equals oracle.kernel.kernel_K."""
+    from oracle import kernel
+    from tests.gpu_common import first_diff_digit_p2, kernel_section_p2
+    g = np.random.default_rng(4)
+    for D in (24, 32):
+        a = g.integers(0, 1 << D, 5000, dtype=np.int64)
+        b = np.where(g.random(5000) < 0.3, a ^ (1 << g.integers(0, D, 5000)), g.integers(0, 1 << D, 5000))
+        b[:10] = a[:10]
+        assert np.array_equal(first_diff_digit_p2(D, a, b), kernel.first_diff_digit(2, D, a, b))
+    X = g.integers(0, 1 << 24, (5, 4000), dtype=np.int64)
+    gam = np.array([0.9, 0.5, 0.3, 0.2, 0.1])
+    ref = kernel.kernel_K(2, 2.5, gam, 24, X, X[:, 17:18])
+    assert np.allclose(kernel_section_p2(2.5, gam, 24, X, X[:, 17]), ref, rtol=1e-15, atol=0)
