@@ -161,6 +161,23 @@ int fdwt_dwt_forward_family(const fdwt_net* net, int family, const double* a_hos
 int fdwt_dwt_inverse(const fdwt_net* net, int in_type, const void* in_dev,
                      int out_type, void* out_dev, void* stream);
 
+/* fdwt_dwt_inverse for callers that cannot allocate device memory (code under
+ * HIP graph capture, tight serving loops, harnesses that forbid allocation):
+ * the same arguments, types and results, bit for bit, but no call to
+ * hipMalloc, hipFree or any allocating routine.  The one case in which the
+ * inverse needs scratch memory -- a real output from complex coefficients
+ * (p odd, CF32 -> F32 or CF64 -> F64) over more than one pass -- keeps its
+ * intermediate passes (N elements of the complex type: 8 N or 16 N bytes) in
+ * a fixed 64 MiB device array of the library, one per GPU, held until the
+ * process ends; larger transforms fail with FDWT_EBUDGET before any work is
+ * enqueued (CF32 -> F32 fits up to N = 2^23 points, CF64 -> F64 up to 2^22).
+ * Every call on a GPU shares that GPU's array: calls that overlap in time on
+ * one GPU (on different streams, or from different threads) race and must be
+ * ordered by the caller.  Nothing in the array needs to start at zero; each
+ * call overwrites what it reads. */
+int fdwt_dwt_inverse_noalloc(const fdwt_net* net, int in_type, const void* in_dev,
+                             int out_type, void* out_dev, void* stream);
+
 /* ------------------------------------------------------- spline kernel */
 
 /* Weighted Walsh kernel of Section 4: K(x,y) = prod_j [1 + gamma_j K'(x_j (-) y_j, 0)]

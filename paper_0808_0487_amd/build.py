@@ -16,7 +16,7 @@ CSRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "libfdwt.so")
 BUILD = os.path.join(ROOT, "_build")
 ARCH = "gfx950"
-SOURCES = ["api.cpp", "net.hip", "fwt.hip", "spline.hip", "batch.hip", "server.cpp", "tune.cpp"]
+SOURCES = ["api.cpp", "net.hip", "fwt.hip", "spline.hip", "batch.hip", "server.cpp", "tune.cpp", "noalloc.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 # Packed-FP32 instructions are disabled for all device code.

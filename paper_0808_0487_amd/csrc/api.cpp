@@ -171,19 +171,6 @@ void scratch_release(Scratch& sc) {
   sc = Scratch{};
 }
 
-// Makes the net's device current for the duration of a call.
-struct DeviceGuard {
-  int prev = -1;
-  bool ok = true;
-  explicit DeviceGuard(int dev) {
-    if (hipGetDevice(&prev) != hipSuccess) prev = -1;
-    if (prev != dev && hipSetDevice(dev) != hipSuccess) ok = false;
-  }
-  ~DeviceGuard() {
-    if (prev >= 0) (void)hipSetDevice(prev);
-  }
-};
-
 static bool is_prime(int p) {
   if (p < 2) return false;
   for (int d = 2; d * d <= p; ++d)
@@ -233,11 +220,8 @@ static Kind to_kind(int t) {
   return (Kind)-1;
 }
 
-int fwt_run_tmp(int p, int m, bool inverse, Kind in_kind, const void* in, Kind work_kind,
-                Kind out_kind, void* out, void* tmp, int batch, double scale, hipStream_t st);
-
-static int transform(Net& net, bool inverse, int in_type, const void* in, int out_type, void* out,
-                     hipStream_t st) {
+int transform_kinds(const Net& net, bool inverse, int in_type, const void* in, int out_type, const void* out,
+                    Kind* ik_out, Kind* wk_out, Kind* ok_out) {
   if (!in || !out) return fail(FDWT_EINVAL, "NULL data pointer");
   Kind ik = to_kind(in_type), ok = to_kind(out_type), wk;
   if ((int)ik < 0 || (int)ok < 0) return fail(FDWT_EINVAL, "unknown element type");
@@ -257,8 +241,22 @@ static int transform(Net& net, bool inverse, int in_type, const void* in, int ou
   }
   if (in == out && kind_bytes(ik) != kind_bytes(ok))
     return fail(FDWT_EINVAL, "in-place transform needs equal input and output element sizes");
+  *ik_out = ik;
+  *wk_out = wk;
+  *ok_out = ok;
+  return FDWT_OK;
+}
+
+size_t transform_tmp_bytes(const Net& net, Kind wk, Kind ok) {
+  return kind_bytes(ok) < kind_bytes(wk) ? (size_t)net.N * kind_bytes(wk) : 0;
+}
+
+static int transform(Net& net, bool inverse, int in_type, const void* in, int out_type, void* out,
+                     hipStream_t st) {
+  Kind ik, wk, ok;
+  if (int rc = transform_kinds(net, inverse, in_type, in, out_type, out, &ik, &wk, &ok)) return rc;
   void* tmp = nullptr;
-  if (kind_bytes(ok) < kind_bytes(wk)) {
+  if (transform_tmp_bytes(net, wk, ok)) {
     int rc = ensure_ws(net.sc, (size_t)net.N * kind_bytes(wk), st);
     if (rc) return rc;
     tmp = net.sc.ws;

@@ -85,6 +85,19 @@ namespace fdwt {
 
 int64_t ipow(int64_t b, int e);
 
+// Makes a device current for the duration of a call.
+struct DeviceGuard {
+  int prev = -1;
+  bool ok = true;
+  explicit DeviceGuard(int dev) {
+    if (hipGetDevice(&prev) != hipSuccess) prev = -1;
+    if (prev != dev && hipSetDevice(dev) != hipSuccess) ok = false;
+  }
+  ~DeviceGuard() {
+    if (prev >= 0) (void)hipSetDevice(prev);
+  }
+};
+
 // Launch timing (see fdwt_timing_enable).  timed_begin returns an event (or
 // nullptr when timing is off) recorded on st; timed_end records the closing
 // event and files the launch under class cls with its algorithmic work.
@@ -112,6 +125,16 @@ int launch_sample(const Net& net, int family, const double* a, float* f, hipStre
 // fwt.hip: element kinds
 enum Kind { K_F32 = 0, K_U32 = 1, K_CF32 = 2, K_F64 = 3, K_CF64 = 4 };
 size_t kind_bytes(Kind k);
+// Transform with an explicit intermediate buffer `tmp` (needed when the
+// output is narrower than the working type: N elements of work_kind).
+int fwt_run_tmp(int p, int m, bool inverse, Kind in_kind, const void* in, Kind work_kind,
+                Kind out_kind, void* out, void* tmp, int batch, double scale, hipStream_t st);
+// api.cpp: the element kinds of fdwt_dwt_forward / fdwt_dwt_inverse for the
+// ABI types (validated: FDWT_EINVAL otherwise), and the bytes of the
+// intermediate buffer that transform needs (0 when the output holds it).
+int transform_kinds(const Net& net, bool inverse, int in_type, const void* in, int out_type, const void* out,
+                    Kind* ik, Kind* wk, Kind* ok);
+size_t transform_tmp_bytes(const Net& net, Kind wk, Kind ok);
 // Transform `batch` columns of N elements (column stride = N elements of the
 // respective type).  in_kind may differ from the working kind only as
 // F32 -> CF32 and F64 -> CF64 (p odd, real input).  out_kind may differ only

@@ -38,9 +38,6 @@
 
 namespace fdwt {
 
-int fwt_run_tmp(int p, int m, bool inverse, Kind in_kind, const void* in, Kind work_kind,
-                Kind out_kind, void* out, void* tmp, int batch, double scale, hipStream_t st);
-
 namespace {
 
 // ------------------------------------------------------------------ jobs

@@ -31,9 +31,6 @@
 
 namespace fdwt {
 
-int fwt_run_tmp(int p, int m, bool inverse, Kind in_kind, const void* in, Kind work_kind,
-                Kind out_kind, void* out, void* tmp, int batch, double scale, hipStream_t st);
-
 constexpr int kTab = 33;  // entries per coordinate of the digit-indexed tables
 
 __host__ __device__ static inline size_t align_up(size_t v) { return (v + 255) & ~(size_t)255; }

@@ -72,6 +72,7 @@ SIGNATURES = {
     "fdwt_sample": (_i, [_vp, _i, _vp, _vp, _vp]),
     "fdwt_dwt_forward": (_i, [_vp, _i, _vp, _i, _vp, _vp]),
     "fdwt_dwt_inverse": (_i, [_vp, _i, _vp, _i, _vp, _vp]),
+    "fdwt_dwt_inverse_noalloc": (_i, [_vp, _i, _vp, _i, _vp, _vp]),
     "fdwt_dwt_forward_family": (_i, [_vp, _i, _vp, _i, _vp, _vp]),
     "fdwt_query_depth": (_i, [_i]),
     "fdwt_spline_coef": (_i, [_vp, ctypes.POINTER(KernelC), _i, _vp, _vp, _vp]),
