@@ -8,6 +8,7 @@
 #include <new>
 #include <unordered_set>
 
+#include "family.h"
 #include "fdwt_internal.h"
 
 namespace fdwt {
@@ -467,8 +468,13 @@ int fdwt_dwt_forward_family(const fdwt_net* h, int family, const double* a_host,
     return fail(FDWT_EINVAL, "coefficients are F32 (p = 2) or CF32 (p odd)");
   DeviceGuard g(net.device);
   hipStream_t st = (hipStream_t)stream;
-  // p = 2 samples into the output and transforms in place; p odd samples
-  // into the workspace (the complex output is twice as wide).
+  // p = 2 samples inside the first pass (m >= 10), or into the output and
+  // transforms in place; p odd samples into the workspace (the complex
+  // output is twice as wide).
+  if (net.p == 2) {
+    const int rc = fwt_p2_forward_family(net, family, make_family_args(net, family, a_host), (float*)out_dev, st);
+    if (rc != FDWT_EUNSUPPORTED) return rc;
+  }
   float* f = (float*)out_dev;
   if (net.p != 2) {
     if (int rc = ensure_ws(net.sc, (size_t)net.N * sizeof(float), st)) return rc;

@@ -16,9 +16,16 @@
 //    tiles with a fixed stride (largest jobs first).
 //
 // In both no workgroup ever waits for another: the kernel boundary between
-// passes orders pass k before pass k+1 (the L2 caches of MI355X's XCDs are
-// not kept coherent with each other inside a kernel for ordinary device
-// memory, so cross-workgroup hand-offs within one launch are avoided).
+// passes orders pass k before pass k+1.  An earlier design ran all passes of
+// the batch in one launch, workgroups spinning on per-job pass counters that
+// other workgroups advanced; it did not finish on the device and was
+// replaced before its cause was established.  Two causes fit what was seen
+// and neither was shown: counter updates and reads without device-scope
+// release/acquire ordering (each XCD has its own L2), and waits on producer
+// workgroups that were not yet resident (a fixed-stride item order gives no
+// forward-progress guarantee).  A single-launch version would need both
+// ruled out first, by emulating its item order and counter protocol on the
+// host.
 //
 // Precision FDWT_PREC_BF16X2: in each job's first pass the stages of index
 // digits 0..3 (16-point Walsh-Hadamard blocks) run on the matrix cores as

@@ -11,6 +11,7 @@
 // held in registers (p^k values per thread, one LDS round trip per group),
 // and writes the tile back in place.  The output is in natural order
 // (h = sum h_i p^i), as in Algorithm 1.
+#include "family.h"
 #include "pass_core.h"
 
 #include <algorithm>
@@ -33,17 +34,41 @@ size_t kind_bytes(Kind k) {
   return 0;
 }
 
+// Per-thread geometry of the generic pass.  A register group holds R = p^KMAX
+// elements; each thread loads LPT elements of a tile (e = tid + k TH): one
+// group, except for p = 5, whose groups are one digit (a two-digit group of
+// 25 complex values, with as many prefetched, needs more registers than a
+// wave gets) and whose threads load 16 elements, so that 1024 threads cover
+// a 5^6-element tile.
+template <int P, int KMAX, int BYTES>
+struct PassShape {
+  static constexpr int R = PowC<P, KMAX>::v;
+  static constexpr int LPT = P == 5 ? 16 : R;
+  // Largest tile the planner can give this kernel (padded tile within
+  // 160 KiB of LDS, at most 1024 x LPT elements) and the threads it takes:
+  // the kernel is compiled for that many, which sets its register budget.
+  static constexpr int emax_elems() {
+    int E = 1;
+    while ((int64_t)E * P <= 1024 * LPT && ((int64_t)E * P + E * P / 32 + 1) * BYTES <= 160 * 1024) E *= P;
+    return E;
+  }
+  static constexpr int THREADS_RAW = (emax_elems() + LPT - 1) / LPT;
+  static constexpr int THREADS = THREADS_RAW < 64 ? 64 : (THREADS_RAW + 63) / 64 * 64;
+};
+
 // A pass is a persistent kernel: each workgroup walks over logical blocks
 // (tile, column) with stride gridDim.x.  The next tile's elements are loaded
 // into registers right after the current tile is in LDS, so the HBM reads of
 // tile k+1 overlap the butterflies and stores of tile k.
 template <int P, bool INV, class Tin, class T, class Tout, int KMAX, int EPI>
-__global__ void __launch_bounds__(1024) fwt_pass(const Tin* __restrict__ in, Tout* out, PassDesc d) {
-  constexpr int RMAX = PowC<P, KMAX>::v;  // elements each thread loads per tile
+__global__ void __launch_bounds__((PassShape<P, KMAX, sizeof(T)>::THREADS))
+    fwt_pass(const Tin* __restrict__ in, Tout* out, PassDesc d) {
+  constexpr int LPT = PassShape<P, KMAX, sizeof(T)>::LPT;
   extern __shared__ __align__(16) unsigned char smem_raw[];
   T* lds = reinterpret_cast<T*>(smem_raw);
   const int G = gridDim.x;
   const int nb = d.ntiles * d.batch;
+  const int tid = threadIdx.x, TH = blockDim.x;
   // Workgroups are dispatched round-robin over the 8 XCDs; with xcd set, XCD x
   // takes the contiguous logical range [x G/8, (x+1) G/8) of every round, so
   // neighbouring tiles (which share cache lines and DRAM pages, and for the
@@ -65,47 +90,66 @@ __global__ void __launch_bounds__(1024) fwt_pass(const Tin* __restrict__ in, Tou
     const int hi = tile / d.nlo;
     return (int64_t)lo * d.w + (int64_t)hi * d.shi;
   };
-  Tin pre[RMAX];
-  // Branch-free loads (indices past the tile end re-read its last element),
-  // so the loads of a tile are all in flight together.  Offsets within a
-  // column fit in 32 bits (N <= 2^26).
+  // Element e = tid + k TH of a tile sits in row e / w, column e mod w, at
+  // global offset (e mod w) + (e / w) sd0 from the tile base.  The thread's
+  // (row, column) for k = 0 and the step TH are split once; each next k
+  // advances them with a carry, so no element needs a division.  Offsets
+  // within a column fit in 32 bits (N <= 2^26).
+  const float inv_w = 1.0f / (float)d.w;
+  int i0, c0, ti, tc;
+  divmod_small(tid, d.w, inv_w, i0, c0);
+  divmod_small(TH, d.w, inv_w, ti, tc);
+  const uint32_t sd0 = (uint32_t)d.sd0;
+  // f(k, e, offset) for the thread's elements; clamp: indices past the tile
+  // end take its last element (offset and index), so the loads of a tile
+  // are all in flight together.
+  const uint32_t last = (uint32_t)(d.w - 1) + (uint32_t)(d.E / d.w - 1) * sd0;
+  auto for_elems = [&](bool clamp, auto&& f) {
+    // The empty asm makes the counters opaque here, so the offsets are
+    // recomputed at each sweep (a few operations per element) instead of
+    // being hoisted out of the tile loop into LPT live registers.
+    int c = c0, i = i0;
+    asm volatile("" : "+v"(c), "+v"(i));
+#pragma unroll
+    for (int k = 0; k < LPT; ++k) {
+      const int e = tid + k * TH;
+      if (e < d.E) f(k, e, (uint32_t)c + (uint32_t)i * sd0);
+      else if (clamp) f(k, d.E - 1, last);
+      c += tc;
+      i += ti;
+      if (c >= d.w) {
+        c -= d.w;
+        ++i;
+      }
+    }
+  };
+  Tin pre[LPT];
   auto prefetch = [&](int l) {
     int col, tile;
     locate(l, col, tile);
     const Tin* src = in + (int64_t)col * d.col_in + tile_base(tile);
-    const uint32_t sd0 = (uint32_t)d.sd0;
-#pragma unroll
-    for (int k = 0; k < RMAX; ++k) {
-      const int e = min((int)threadIdx.x + k * (int)blockDim.x, d.E - 1);
-      const uint32_t c = (uint32_t)Ix<P>::mod(e, d.wdig, d.w);
-      const uint32_t i = (uint32_t)Ix<P>::div(e, d.wdig, d.w);
-      pre[k] = src[c + i * sd0];
-    }
+    for_elems(true, [&](int k, int, uint32_t off) { pre[k] = src[off]; });
   };
   double* red = reinterpret_cast<double*>(smem_raw + (size_t)(d.E + d.E / 32 + 1) * sizeof(T) + 8 -
                                           ((d.E + d.E / 32 + 1) * sizeof(T)) % 8);
   if (lb < nb) prefetch(lb);
   for (; lb < nb; lb += G) {
     // Clamped indices write the tile's last element again, with its value.
-#pragma unroll
-    for (int k = 0; k < RMAX; ++k) {
-      const int e = min((int)threadIdx.x + k * (int)blockDim.x, d.E - 1);
-      lds[pad(e)] = cvt_in<Tin, T>(pre[k]);
-    }
+    for_elems(true, [&](int k, int e, uint32_t) { lds[pad(e)] = cvt_in<Tin, T>(pre[k]); });
     lds_barrier();
     prefetch(lb + G < nb ? lb + G : lb);  // unconditional: exact wait counts
     for (int q = 0; q < d.r; q += d.kreg) {
       const int kk = min(d.kreg, d.r - q);
       if constexpr (KMAX >= 4) {
-        if (kk == 4) run_group<P, INV, T, 4>(lds, d, q);
+        if (kk == 4) run_group<P, INV, T, 4>(lds, d, q, inv_w);
       }
       if constexpr (KMAX >= 3) {
-        if (kk == 3) run_group<P, INV, T, 3>(lds, d, q);
+        if (kk == 3) run_group<P, INV, T, 3>(lds, d, q, inv_w);
       }
       if constexpr (KMAX >= 2) {
-        if (kk == 2) run_group<P, INV, T, 2>(lds, d, q);
+        if (kk == 2) run_group<P, INV, T, 2>(lds, d, q, inv_w);
       }
-      if (kk == 1) run_group<P, INV, T, 1>(lds, d, q);
+      if (kk == 1) run_group<P, INV, T, 1>(lds, d, q, inv_w);
       lds_barrier();
     }
     int col, tile;
@@ -113,24 +157,17 @@ __global__ void __launch_bounds__(1024) fwt_pass(const Tin* __restrict__ in, Tou
     const int64_t base = tile_base(tile);
     if constexpr (EPI == EPI_STORE) {
       Tout* dst = out + (int64_t)col * d.col_out + base;
-      const uint32_t sd0 = (uint32_t)d.sd0;
-      for (int e = threadIdx.x; e < d.E; e += blockDim.x) {
-        const uint32_t c = (uint32_t)Ix<P>::mod(e, d.wdig, d.w);
-        const uint32_t i = (uint32_t)Ix<P>::div(e, d.wdig, d.w);
-        dst[c + i * sd0] = cvt_out<T, Tout>(lds[pad(e)], d.scale, d.scale64);
-      }
+      for_elems(false, [&](int, int e, uint32_t off) { dst[off] = cvt_out<T, Tout>(lds[pad(e)], d.scale, d.scale64); });
     } else {
       double acc = 0.0;
-      for (int e = threadIdx.x; e < d.E; e += blockDim.x) {
-        const int c = Ix<P>::mod(e, d.wdig, d.w);
-        const int i = Ix<P>::div(e, d.wdig, d.w);
-        const int64_t h = base + c + (int64_t)i * d.sd0;
+      for_elems(false, [&](int, int e, uint32_t off) {
+        const int64_t h = base + off;
         const float2 wt = d.wts[h];
         const double rho = fmin(fmax(real_of(lds[pad(e)]) * (double)wt.y, 0.0), 1.0);
         const double term = (double)wt.x * rho;
         acc += term;
         if (h == 0 && col == d.h0_col) *d.h0_out = term;
-      }
+      });
       // Wave sums by butterfly shuffles, then the waves in a fixed order.
       for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off);
       if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = acc;
@@ -515,6 +552,85 @@ __global__ void __launch_bounds__((P2Shape<LOGE, 0>::THREADS)) fwt_p2_gen(ColGen
 }
 
 
+// First pass of the forward transform of a test function sampled at the
+// net (p = 2, fdwt_dwt_forward_family): the 16 values each thread would load
+// are generated instead, f(x_n) at n = tile E + tid + k TH, with the sampling
+// kernel's arithmetic (family.h, the same operations in the same order), then
+// transformed and stored exactly as fwt_p2's first pass does, so the result
+// equals sampling then transforming bit for bit while the samples never
+// cross HBM.  X_j(n) is linear over Z_2 in the bits of n, which split into
+// the tid part (a vector lookup in the net's byte tables), the 16 k parts
+// (built by doubling from four generator columns) and the tile part; the
+// last two are the same for the whole workgroup and come from scalar loads.
+struct FamGen {
+  const uint32_t* xtab;  // [s][nbytes][256]: X_j of byte value v at byte b
+  int nbytes, m;
+  FamilyArgs fa;
+};
+
+template <int LOGE, int FAM>
+__global__ void __launch_bounds__((P2Shape<LOGE, 0>::THREADS)) fwt_p2_fam(FamGen g, float* out, PassDesc d) {
+  using S = P2Shape<LOGE, 0>;
+  constexpr int EPT = S::EPT, TH = S::THREADS, TB = LOGE - 4;  // tid has TB bits
+  static_assert(LOGE >= 10 && EPT == 16, "16 elements per thread");
+  constexpr int NS = (LOGE - 10) < 4 ? (LOGE - 10) : 4;
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  float* lds = reinterpret_cast<float*>(smem_raw);
+  using ctab = const uint32_t __attribute__((address_space(4)))*;
+  const ctab tc = (ctab)g.xtab;
+  const int tid = threadIdx.x, lane = tid & 63, wv = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int s = g.fa.s, nby = g.nbytes;
+  const float inv = 1.0f / (float)(1u << g.m);  // exact power of two, as the sampling kernel's
+  float* lrow = lds + cpad(tid);
+  float* lrowS = lds + cpad(lane + 1024 * wv);
+  const uint32_t goffS = (uint32_t)(lane + 1024 * wv);
+  const int G = gridDim.x, hw = blockIdx.x;
+  int lb = d.xcd ? ((hw & 7) * (G >> 3) + (hw >> 3)) : hw;
+  for (; lb < d.ntiles; lb += G) {
+    const uint32_t n0 = (uint32_t)lb << LOGE;
+    typename FamState<FAM>::T acc[EPT];
+#pragma unroll
+    for (int k = 0; k < EPT; ++k) acc[k] = fam_init<FAM>(g.fa);
+    for (int j = 0; j < s; ++j) {
+      const uint32_t* tj = g.xtab + (size_t)j * nby * 256;
+      uint32_t xt = tj[tid & 255];
+      if constexpr (TB > 8) xt ^= tj[256 + (tid >> 8)];
+      uint32_t tp = 0;  // X_j(n0)
+      for (int b = 1; b < nby; ++b) tp ^= tc[(j * nby + b) * 256 + ((n0 >> (8 * b)) & 255)];
+      xt ^= tp;
+      uint32_t kx[EPT];  // X_j(k TH)
+      kx[0] = 0;
+#pragma unroll
+      for (int b = 0; b < 4; ++b) {
+        const int bit = TB + b;
+        const uint32_t cb = tc[(j * nby + (bit >> 3)) * 256 + (1 << (bit & 7))];
+#pragma unroll
+        for (int k = 0; k < (1 << b); ++k) kx[k + (1 << b)] = kx[k] ^ cb;
+      }
+      const float a = g.fa.a[j], ia = g.fa.inv1a[j];
+#pragma unroll
+      for (int k = 0; k < EPT; ++k) fam_step<FAM, false>(acc[k], g.fa, a, ia, xt ^ kx[k], inv, (double)inv);
+    }
+    float v[EPT];
+#pragma unroll
+    for (int k = 0; k < EPT; ++k) v[k] = fam_final<FAM>(acc[k], g.fa);
+    reg_bfly<4>(v);
+#pragma unroll
+    for (int k = 0; k < EPT; ++k) lrow[cpad(k * TH)] = v[k];
+    lds_barrier();
+    P2Groups<LOGE, 0, 0, float, 4, 6>::run(lds, tid);
+    float y[EPT];
+#pragma unroll
+    for (int k = 0; k < EPT; ++k) y[k] = lrowS[66 * k];
+    reg_bfly<NS>(y);
+    const gptr<float> dst = to_global(out + ((int64_t)lb << LOGE) + goffS);
+#pragma unroll
+    for (int k = 0; k < EPT; ++k) dst[k * 64] = cvt_out<float, float>(y[k], d.scale, d.scale64);
+    lds_barrier();
+  }
+}
+
+
 // ----------------------------------------------------------------- planner
 struct PassGeom {
   int d0, r, wdig;
@@ -533,18 +649,21 @@ static size_t lds_budget(size_t bytes) {
   return bytes >= 8 ? wide : (size_t)80 * 1024;
 }
 
-static int kreg_for(int p, Kind work) {
+// Digits per register group of the generic pass (PassShape's KMAX) and the
+// elements each thread loads per tile (PassShape's LPT).
+static int kreg_for(int p, Kind) {
   if (p == 2) return 4;
   if (p == 3) return 2;
-  if (p == 7) return 1;
-  return work == K_CF32 ? 2 : 1;
+  return 1;
 }
+static int loads_per_thread(int p) { return p == 2 ? 16 : (p == 3 ? 9 : (p == 5 ? 16 : 7)); }
 
 static std::vector<PassGeom> plan(int p, int m, size_t bytes, Kind work) {
   // Largest tile exponent e with the padded tile within the LDS budget and
-  // at most 1024 threads x p^kreg elements (each thread loads p^kreg).
+  // at most 1024 threads x the elements each thread loads.
+  (void)work;
   const size_t budget = lds_budget(bytes);
-  const int64_t per_block = 1024 * ipow(p, kreg_for(p, work));
+  const int64_t per_block = 1024 * loads_per_thread(p);
   int emax = 0;
   for (int e = 1; e <= 30; ++e) {
     int64_t E = ipow(p, e);
@@ -600,7 +719,10 @@ struct ReduceArgs {
 template <int P, bool INV, class Tin, class T, class Tout>
 static int launch_pass(const void* in, void* out, const PassGeom& g, int m, int batch, double scale,
                        int64_t col_in, int64_t col_out, Kind work, const ReduceArgs* red, hipStream_t st) {
-  constexpr int KMAX = (P == 2) ? 4 : (P == 7 ? 1 : ((P == 3 || sizeof(T) <= 8) ? 2 : 1));
+  constexpr int KMAX = P == 2 ? 4 : (P == 3 ? 2 : 1);
+  using Shape = PassShape<P, KMAX, sizeof(T)>;
+  constexpr int LPT = Shape::LPT;
+  static_assert(PowC<P, KMAX>::v <= LPT, "a thread loads at least one register group");
   PassDesc d{};
   d.col_in = col_in;
   d.col_out = col_out;
@@ -626,11 +748,13 @@ static int launch_pass(const void* in, void* out, const PassGeom& g, int m, int 
   } else {
     d.h0_col = -1;
   }
-  const int R = (int)ipow(P, d.kreg);
-  int threads = std::max(64, std::min(1024, (d.E + R - 1) / R));
+  if (LPT != loads_per_thread(P)) return fail(FDWT_EINVAL, "pass geometry tables disagree");
+  int threads = std::max(64, std::min(1024, (d.E + LPT - 1) / LPT));
   threads = (threads + 63) / 64 * 64;
-  // Every tile element is loaded by exactly the per-thread prefetch.
-  if ((int64_t)threads * PowC<P, KMAX>::v < d.E) return fail(FDWT_EINVAL, "pass tile larger than one workgroup loads");
+  // Every tile element is loaded by the per-thread prefetch; the index
+  // arithmetic (divmod_small) needs indices below 2^22.
+  if ((int64_t)threads * LPT < d.E || d.E >= (1 << 22) || threads > Shape::THREADS)
+    return fail(FDWT_EINVAL, "pass tile larger than one workgroup loads");
   const size_t tile_bytes = (size_t)(d.E + d.E / 32 + 1) * sizeof(T);
   const size_t lds = tile_bytes + 8 - tile_bytes % 8 + 16 * sizeof(double);
   const void* fn = red ? (const void*)fwt_pass<P, INV, Tin, T, Tout, KMAX, EPI_REDUCE>
@@ -1067,6 +1191,60 @@ int fwt_p2_f64_rest(int m, double* data, int batch, hipStream_t st) {
   int rc = FDWT_OK;
   for (size_t i = 1; !rc && i < v.size(); ++i) rc = p2_pass(K_F64, data, data, v[i], m, batch, 1.0, nullptr, st);
   return rc;
+}
+
+// fdwt_dwt_forward_family for p = 2: the first pass samples its own input
+// (fwt_p2_fam), the remaining passes run in place on out.  Returns
+// FDWT_EUNSUPPORTED (nothing enqueued) when the plan's first pass has fewer
+// than 2^10 elements; the caller then samples and transforms separately.
+template <int FAM>
+static const void* fam_kernel(int loge) {
+  switch (loge) {
+    case 10: return (const void*)fwt_p2_fam<10, FAM>;
+    case 11: return (const void*)fwt_p2_fam<11, FAM>;
+    case 12: return (const void*)fwt_p2_fam<12, FAM>;
+    case 13: return (const void*)fwt_p2_fam<13, FAM>;
+    case 14: return (const void*)fwt_p2_fam<14, FAM>;
+  }
+  return nullptr;
+}
+
+int fwt_p2_forward_family(const Net& net, int family, const FamilyArgs& fa, float* out, hipStream_t st) {
+  const std::vector<P2Pass> passes = plan_p2(net.m, 4);
+  const P2Pass& g0 = passes[0];
+  if (net.p != 2 || net.m < 10 || g0.d0 != 0 || g0.wdig != 0 || g0.loge < 10 || g0.loge > 14)
+    return FDWT_EUNSUPPORTED;
+  const void* fn = family == FDWT_FAMILY_PRODUCT ? fam_kernel<FDWT_FAMILY_PRODUCT>(g0.loge)
+                   : family == FDWT_FAMILY_EXP   ? fam_kernel<FDWT_FAMILY_EXP>(g0.loge)
+                   : family == FDWT_FAMILY_ASIAN ? fam_kernel<FDWT_FAMILY_ASIAN>(g0.loge)
+                                                 : fam_kernel<FDWT_FAMILY_WANGFANG>(g0.loge);
+  if (!fn) return fail(FDWT_EINVAL, "no fused sampling pass for this shape");
+  const int64_t N = int64_t(1) << net.m;
+  const int E = 1 << g0.loge;
+  const int threads = E / 16;
+  const double scale = std::ldexp(1.0, -net.m);  // Eq. (eq_dwalshcoeff), applied by the last pass
+  PassDesc d{};
+  d.ntiles = (int)(N / E);
+  d.batch = 1;
+  d.h0_col = -1;
+  d.scale = passes.size() == 1 ? (float)scale : 1.0f;
+  d.scale64 = passes.size() == 1 ? scale : 1.0;
+  const size_t lds = ((size_t)cpad(E) * sizeof(float) + 15) / 16 * 16;
+  if (int rc = allow_lds(fn, lds)) return rc;
+  int64_t G = (int64_t)occupancy(fn, threads, lds) * device_cus();
+  if (G >= d.ntiles) G = d.ntiles;
+  if (G >= 64) G -= G % 8;
+  d.xcd = (G % 8 == 0 && G >= 64) ? 1 : 0;
+  FamGen fg{net.d_xtab, net.nbytes, net.m, fa};
+  void* args[] = {(void*)&fg, (void*)&out, (void*)&d};
+  hipEvent_t tb = timed_begin(st);
+  FDWT_HIP(hipLaunchKernel(fn, dim3((unsigned)G), dim3(threads), args, lds, st));
+  timed_end(tb, st, FDWT_TC_SAMPLE, 4.0 * (double)N);
+  for (size_t i = 1; i < passes.size(); ++i) {
+    const bool last = i + 1 == passes.size();
+    if (int rc = p2_pass(K_F32, out, out, passes[i], net.m, 1, last ? scale : 1.0, nullptr, st)) return rc;
+  }
+  return FDWT_OK;
 }
 
 int64_t fwt_reduce_parts(int p, int m, size_t elem_bytes) {

@@ -117,6 +117,25 @@ struct Ix {
   }
 };
 
+// Quotient and remainder of 0 <= a < 2^22 by 1 <= dv < 2^22 given
+// inv = 1.0f / dv (correctly rounded): a * inv is within 0.5 of a / dv (a
+// relative error below 2^-23 on a value below 2^22), so its truncation is
+// the quotient or one off, and one correction step makes it exact.  The
+// emulation of these float operations on the host checks every (a, dv) the
+// pass geometries use.  Replaces the integer division (a long instruction
+// sequence) on the passes' per-group index arithmetic.
+__host__ __device__ __forceinline__ void divmod_small(int a, int dv, float inv, int& q, int& r) {
+  q = (int)((float)a * inv);
+  r = a - q * dv;
+  if (r < 0) {
+    --q;
+    r += dv;
+  } else if (r >= dv) {
+    ++q;
+    r -= dv;
+  }
+}
+
 template <int P, int K>
 struct PowC {
   static constexpr int v = P * PowC<P, K - 1>::v;
@@ -134,18 +153,26 @@ __device__ __forceinline__ int ipow_d(int b, int e) {
 
 // One register group: the KK digits [q, q+KK) of the tile row index.  Each
 // thread takes p^KK elements that differ only in those digits, applies the
-// KK radix-p stages in registers and writes them back.
+// KK radix-p stages in registers and writes them back.  inv_w = 1.0f / w
+// (odd p: see divmod_small).
 template <int P, bool INV, class T, int KK>
-__device__ __forceinline__ void run_group(T* lds, const PassDesc& d, int q) {
+__device__ __forceinline__ void run_group(T* lds, const PassDesc& d, int q, float inv_w = 0.0f) {
   constexpr int R = PowC<P, KK>::v;
   const int pq = ipow_d(P, q);
   const int ng = d.E / R;
   const int stq = d.w * pq;  // LDS stride of digit q
+  const float inv_pq = P == 2 ? 0.0f : 1.0f / (float)pq;
   for (int g = threadIdx.x; g < ng; g += blockDim.x) {
-    const int c = Ix<P>::mod(g, d.wdig, d.w);
-    const int rem = Ix<P>::div(g, d.wdig, d.w);
-    const int il = Ix<P>::mod(rem, q, pq);
-    const int ih = Ix<P>::div(rem, q, pq);
+    int c, rem, il, ih;
+    if constexpr (P == 2) {
+      c = Ix<P>::mod(g, d.wdig, d.w);
+      rem = Ix<P>::div(g, d.wdig, d.w);
+      il = Ix<P>::mod(rem, q, pq);
+      ih = Ix<P>::div(rem, q, pq);
+    } else {
+      divmod_small(g, d.w, inv_w, rem, c);
+      divmod_small(rem, pq, inv_pq, ih, il);
+    }
     const int e0 = c + d.w * (il + pq * R * ih);
     T x[R];
 #pragma unroll
