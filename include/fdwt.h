@@ -357,7 +357,15 @@ void fdwt_batch_free(fdwt_batch* batch);
  * job; either may be NULL) and forgets the job; it returns the job's status.
  * Times are seconds on the server's clock (from creation).  Any thread may
  * submit and wait.  fdwt_server_free finishes every submitted job, then
- * releases everything. */
+ * releases everything.
+ *
+ * A job that fails (on the device, or while its work is enqueued) completes
+ * with its error status; its memory returns to the arena once its lane is
+ * idle, cache entries it was computing are discarded (later jobs recompute
+ * them), and no other job is affected.  For testing that isolation,
+ * FDWT_SERVER_INJECT_ENOMEM (read by fdwt_server_create) lists job ids,
+ * comma-separated, whose work fails with FDWT_ENOMEM right after their
+ * kernel-spectrum step, as an allocation failure in mid-job would. */
 #define FDWT_JOB_INTERP 1
 #define FDWT_JOB_EFFDIM 2
 

@@ -32,6 +32,7 @@
 #include <string>
 #include <thread>
 #include <unordered_map>
+#include <unordered_set>
 
 #include "arena.h"
 #include "fdwt_internal.h"
@@ -205,6 +206,9 @@ struct fdwt_server {
   // Written by the scheduler thread only.
   std::atomic<int64_t> spec_hits{0}, spec_misses{0}, packed_hits{0}, packed_misses{0}, evictions{0}, nets_built{0};
   std::atomic<int> in_flight{0};
+  // Job ids whose device work fails with FDWT_ENOMEM after the kernel
+  // spectrum step (FDWT_SERVER_INJECT_ENOMEM; failure-isolation tests).
+  std::unordered_set<int64_t> inject_enomem;
   std::thread th;
   std::chrono::steady_clock::time_point t0;
 
@@ -417,6 +421,8 @@ int fdwt_server::enqueue(Job& j, Lane& L) {
   } else {
     FDWT_HIP(hipStreamWaitEvent(st, j.spec->ready, 0));
   }
+  if (inject_enomem.count(j.id))
+    return fail(FDWT_ENOMEM, "injected allocation failure (FDWT_SERVER_INJECT_ENOMEM) after the spectrum step");
   void* packed = nullptr;
   if (j.holds_packed) {
     CacheEntry& pe = j.net->packed;
@@ -600,6 +606,16 @@ int fdwt_server_create(const fdwt_server_config* cfg, fdwt_server** out) {
       (void)hipGetLastError();
       fdwt_server_free(sv.release());
       return fail(FDWT_EDEVICE, "stream creation failed");
+    }
+  }
+  if (const char* e = getenv("FDWT_SERVER_INJECT_ENOMEM")) {
+    // comma-separated job ids
+    for (const char* c = e; *c;) {
+      char* end = nullptr;
+      const long long v = strtoll(c, &end, 10);
+      if (end == c) break;
+      sv->inject_enomem.insert((int64_t)v);
+      c = *end == ',' ? end + 1 : end;
     }
   }
   sv->t0 = std::chrono::steady_clock::now();

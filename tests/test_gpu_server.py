@@ -180,3 +180,78 @@ def test_request_validation():
     with pytest.raises(fdwt.FdwtError):
         sv.submit(bad)
     sv.close()
+
+
+def test_invalid_requests_into_a_running_server():
+    """Invalid requests (alpha <= 1, a non-positive gamma, a generator entry
+    >= p, a conflicting net_key, a request beyond the budget) submitted
+    between valid ones while those run are refused at submission; every
+    valid job completes with the result of a clean run, bit for bit."""
+    announce("server invalid requests in the mix")
+    reqs = mixed_requests()[:10]
+    clean_sv = fdwt.Server(256 * MiB, lanes=4)
+    clean = [res for _, res in run_all(clean_sv, reqs)]
+    clean_sv.close()
+
+    def bad(kind):
+        r = make_request("interp", 2, 8, 3, 900 + len(kind))
+        if kind == "alpha":
+            r.alpha = 0.5
+        elif kind == "gamma":
+            r.gamma = r.gamma.copy()
+            r.gamma[1] = -1.0
+        elif kind == "entry":
+            r.C = r.C.copy()
+            r.C[0, 0, 0] = 2
+        elif kind == "key":
+            r.net_key = reqs[0].net_key  # same key, different net
+        elif kind == "budget":
+            r = make_request("eff_dim", 2, 24, 20, 950)
+        return r
+
+    sv = fdwt.Server(256 * MiB, lanes=4)
+    ids, codes = [], []
+    for i, r in enumerate(reqs):
+        ids.append(sv.submit(r))
+        if i % 2 == 1:
+            kind = ["alpha", "gamma", "entry", "key", "budget"][i // 2]
+            with pytest.raises(fdwt.FdwtError) as e:
+                sv.submit(bad(kind))
+            codes.append(e.value.code)
+    got = [sv.wait(i)[1] for i in ids]
+    st = sv.stats()
+    sv.close()
+    assert codes == [fdwt.EINVAL, fdwt.EINVAL, fdwt.EINVAL, fdwt.EINVAL, fdwt.EBUDGET]
+    assert st["rejected"] == 5 and st["completed"] == len(reqs) and st["failed"] == 0
+    assert all(same_result(a, b) for a, b in zip(got, clean))
+
+
+def test_injected_allocation_failure_is_isolated(monkeypatch):
+    """Jobs 2 and 5 of a running mix fail in mid-job (FDWT_ENOMEM injected
+    from the host after their kernel-spectrum step: job 2 had reused the
+    spectrum job 1 computed; job 5 was computing the spectrum that jobs 6..8
+    of its net then need, so it is discarded and recomputed).  They report
+    the failure; every other job completes with the result of a clean run,
+    bit for bit, and the server keeps serving afterwards."""
+    announce("server injected allocation failure")
+    reqs = mixed_requests()[:12]
+    clean_sv = fdwt.Server(256 * MiB, lanes=4)
+    clean = [res for _, res in run_all(clean_sv, reqs)]
+    clean_sv.close()
+    monkeypatch.setenv("FDWT_SERVER_INJECT_ENOMEM", "2,5")
+    sv = fdwt.Server(256 * MiB, lanes=4)
+    monkeypatch.delenv("FDWT_SERVER_INJECT_ENOMEM")
+    ids = [sv.submit(r) for r in reqs]
+    assert ids[:6] == [1, 2, 3, 4, 5, 6]
+    for jid, r, ref in zip(ids, reqs, clean):
+        if jid in (2, 5):
+            with pytest.raises(fdwt.FdwtError) as e:
+                sv.wait(jid)
+            assert e.value.code == fdwt.ENOMEM
+        else:
+            assert same_result(sv.wait(jid)[1], ref), jid
+    again = [sv.wait(sv.submit(r))[1] for r in reqs[:3]]
+    st = sv.stats()
+    sv.close()
+    assert st["failed"] == 2 and st["completed"] == len(reqs) - 2 + 3
+    assert all(same_result(a, b) for a, b in zip(again, clean[:3]))
