@@ -8,6 +8,8 @@
 #include <new>
 #include <unordered_set>
 
+#include <hip/hip_ext.h>
+
 #include "family.h"
 #include "fdwt_internal.h"
 
@@ -85,6 +87,36 @@ void timed_end(hipEvent_t begin, hipStream_t st, int cls, double work) {
   }
   std::lock_guard<std::mutex> g(g_tmu);
   g_recs.push_back({begin, e, cls, work});
+}
+
+int launch_timed(const void* fn, dim3 grid, dim3 block, void** args, size_t lds, hipStream_t st, int cls,
+                 double work) {
+  bool on;
+  {
+    std::lock_guard<std::mutex> g(g_tmu);
+    on = g_timing;
+  }
+  hipEvent_t a = nullptr, b = nullptr;
+  if (on && (hipEventCreate(&a) != hipSuccess || hipEventCreate(&b) != hipSuccess)) {
+    (void)hipGetLastError();
+    if (a) (void)hipEventDestroy(a);
+    if (b) (void)hipEventDestroy(b);
+    a = b = nullptr;
+    on = false;
+  }
+  if (!on) {
+    FDWT_HIP(hipLaunchKernel(fn, grid, block, args, lds, st));
+    return FDWT_OK;
+  }
+  const hipError_t e = hipExtLaunchKernel(fn, grid, block, args, lds, st, a, b, 0);
+  if (e != hipSuccess) {
+    (void)hipEventDestroy(a);
+    (void)hipEventDestroy(b);
+    return fail(FDWT_EDEVICE, std::string("hipExtLaunchKernel: ") + hipGetErrorString(e));
+  }
+  std::lock_guard<std::mutex> g(g_tmu);
+  g_recs.push_back({a, b, cls, work});
+  return FDWT_OK;
 }
 
 int query_depth(int p) { return p == 2 ? 32 : (p == 3 ? 20 : (p == 5 ? 13 : (p == 7 ? 11 : 0))); }

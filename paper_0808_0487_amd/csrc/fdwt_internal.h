@@ -103,6 +103,11 @@ struct DeviceGuard {
 // event and files the launch under class cls with its algorithmic work.
 hipEvent_t timed_begin(hipStream_t st);
 void timed_end(hipEvent_t begin, hipStream_t st, int cls, double work);
+// Launches one kernel (hipLaunchKernel arguments); while timing is on, with
+// start and stop events attached to the dispatch itself (hipExtLaunchKernel),
+// so the recorded duration is the kernel's alone, filed under cls.
+int launch_timed(const void* fn, dim3 grid, dim3 block, void** args, size_t lds, hipStream_t st, int cls,
+                 double work);
 // Allows a kernel more than the default 64 KiB of dynamic LDS (once per kernel).
 int allow_lds(const void* fn, size_t bytes);
 int ensure_ws(Scratch& sc, size_t bytes, hipStream_t st);

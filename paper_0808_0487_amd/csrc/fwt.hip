@@ -773,17 +773,10 @@ static int launch_pass(const void* in, void* out, const PassGeom& g, int m, int 
                          : elems * (sizeof(Tin) + sizeof(Tout));
   const int cls = sizeof(T) >= 16 || std::is_same<T, double>::value ? FDWT_TC_PASS_F64
                   : (sizeof(T) == 8 ? FDWT_TC_PASS_CF32 : FDWT_TC_PASS_F32);
-  hipEvent_t tb = timed_begin(st);
-  if (red) {
-    hipLaunchKernelGGL((fwt_pass<P, INV, Tin, T, Tout, KMAX, EPI_REDUCE>), dim3((unsigned)G), dim3(threads), lds,
-                       st, (const Tin*)in, (Tout*)out, d);
-  } else {
-    hipLaunchKernelGGL((fwt_pass<P, INV, Tin, T, Tout, KMAX, EPI_STORE>), dim3((unsigned)G), dim3(threads), lds,
-                       st, (const Tin*)in, (Tout*)out, d);
-  }
-  FDWT_HIP(hipGetLastError());
-  timed_end(tb, st, cls, alg);
-  return FDWT_OK;
+  const Tin* inp = (const Tin*)in;
+  Tout* outp = (Tout*)out;
+  void* args[] = {(void*)&inp, (void*)&outp, (void*)&d};
+  return launch_timed(fn, dim3((unsigned)G), dim3(threads), args, lds, st, cls, alg);
 }
 
 // Dispatch on (p, direction, in/work/out kinds).
@@ -992,10 +985,8 @@ static int launch_p2(const void* in, void* out, const P2Pass& g, int m, int batc
   void* args[] = {(void*)&in, (void*)&out, (void*)&d};
   const double elems = (double)N * batch;
   const double work = red ? elems * sizeof(Tin) + (double)N * sizeof(float2) : elems * (sizeof(Tin) + sizeof(Tout));
-  hipEvent_t tb = timed_begin(st);
-  FDWT_HIP(hipLaunchKernel(fn, dim3((unsigned)G), dim3(threads), args, lds, st));
-  timed_end(tb, st, wide ? FDWT_TC_PASS_F64 : FDWT_TC_PASS_F32, work);
-  return FDWT_OK;
+  return launch_timed(fn, dim3((unsigned)G), dim3(threads), args, lds, st, wide ? FDWT_TC_PASS_F64 : FDWT_TC_PASS_F32,
+                      work);
 }
 
 static int p2_pass(Kind k, const void* in, void* out, const P2Pass& g, int m, int batch, double scale,
@@ -1177,10 +1168,8 @@ int fwt_p2_gen_first(int m, int s, const uint32_t* xtab, int nbytes, const doubl
   d.xcd = (G % 8 == 0 && G >= 64) ? 1 : 0;
   ColGen cg{xtab, tab, nbytes, s, m, ktab, kcol ? 0 : d0, kcol ? s : d1};
   void* args[] = {(void*)&cg, (void*)&out, (void*)&d};
-  hipEvent_t tb = timed_begin(st);
-  FDWT_HIP(hipLaunchKernel(fn, dim3((unsigned)G), dim3(threads), args, lds, st));
-  timed_end(tb, st, FDWT_TC_PASS_F64, (double)N * ncol * sizeof(double));
-  return FDWT_OK;
+  return launch_timed(fn, dim3((unsigned)G), dim3(threads), args, lds, st, FDWT_TC_PASS_F64,
+                      (double)N * ncol * sizeof(double));
 }
 
 // The passes after the first of an unnormalised p = 2 float64 transform, in
@@ -1237,9 +1226,8 @@ int fwt_p2_forward_family(const Net& net, int family, const FamilyArgs& fa, floa
   d.xcd = (G % 8 == 0 && G >= 64) ? 1 : 0;
   FamGen fg{net.d_xtab, net.nbytes, net.m, fa};
   void* args[] = {(void*)&fg, (void*)&out, (void*)&d};
-  hipEvent_t tb = timed_begin(st);
-  FDWT_HIP(hipLaunchKernel(fn, dim3((unsigned)G), dim3(threads), args, lds, st));
-  timed_end(tb, st, FDWT_TC_SAMPLE, 4.0 * (double)N);
+  if (int rc = launch_timed(fn, dim3((unsigned)G), dim3(threads), args, lds, st, FDWT_TC_SAMPLE, 4.0 * (double)N))
+    return rc;
   for (size_t i = 1; i < passes.size(); ++i) {
     const bool last = i + 1 == passes.size();
     if (int rc = p2_pass(K_F32, out, out, passes[i], net.m, 1, last ? scale : 1.0, nullptr, st)) return rc;

@@ -460,12 +460,10 @@ static int kcols_launch(const Net& net, const double* tk, const double* tr, int 
                      (P == 2 ? (size_t)net.s * 257 * 4 : OddCoords<P == 2 ? 3 : P>::lds_bytes(net.s));
   if (int rc = allow_lds((const void*)k_kernel_cols<P, SMAX>, lds)) return rc;
   const unsigned grid = (unsigned)std::min<int64_t>((net.N + kChunk - 1) / kChunk, 2048);
-  hipEvent_t tb = timed_begin(st);
-  hipLaunchKernelGGL((k_kernel_cols<P, SMAX>), dim3(grid), dim3(kChunk), lds, st, net_args(net), tk, tr, c0,
-                     c1, out);
-  FDWT_HIP(hipGetLastError());
-  timed_end(tb, st, FDWT_TC_KCOLS, 8.0 * (double)net.N * (c1 - c0));
-  return FDWT_OK;
+  NetArgs na = net_args(net);
+  void* args[] = {(void*)&na, (void*)&tk, (void*)&tr, (void*)&c0, (void*)&c1, (void*)&out};
+  return launch_timed((const void*)k_kernel_cols<P, SMAX>, dim3(grid), dim3(kChunk), args, lds, st, FDWT_TC_KCOLS,
+                      8.0 * (double)net.N * (c1 - c0));
 }
 
 // SMAX: register length of the symmetric-polynomial state (>= s; 8 when only
