@@ -5,8 +5,9 @@ s = 20, seeded random non-singular upper-triangular generators,
 f(x) = exp(-sum_j 0.1^j x_j^2) in float32, plus an int32 run with values
 uniform in [-1000, 1000]; Walsh kernel alpha = 2, gamma_j = j^-2.
 
-One step runs the whole path on that input: net generation fused into the
-sampling of f, the forward transform (float32), the int32 forward transform,
+One step runs the whole path on that input: net generation and the sampling
+of f fused into the first pass of the forward transform (float32), the int32
+forward transform,
 the kernel spectrum, spectral solve and inverse transform (spline
 coefficients), and the effective-dimension variances.  Inputs are resident
 in device memory before timing starts.
@@ -40,6 +41,11 @@ CLASSES = ["pass_f32", "pass_cf32", "pass_f64", "sample", "kcols", "eval"]
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_c2_step.md")
 
 
+def progress(*msg):
+    """One line per finished leg on stderr (the JSON line alone goes to stdout)."""
+    print("[bench]", *msg, file=sys.stderr, flush=True)
+
+
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -53,11 +59,14 @@ def parse():
     ap.add_argument("--no-serve", action="store_true", help="skip the serving leg")
     ap.add_argument("--no-interp", action="store_true", help="skip the p = 3 interpolation leg")
     ap.add_argument("--no-table1", action="store_true", help="skip the Section 5.2 experiment")
+    ap.add_argument("--no-c1", action="store_true", help="skip the small-configuration leg")
     ap.add_argument("--serve-window", type=float, default=0.2,
                     help="seconds of Poisson arrivals (at --serve-rate) replayed in the serving leg")
     ap.add_argument("--serve-rate", type=float, default=200.0)
     ap.add_argument("--serve-budget-gb", type=float, default=200.0)
     ap.add_argument("--serve-lanes", type=int, default=8)
+    ap.add_argument("--serve-sustained", type=int, default=200,
+                    help="requests per sustained-load serving stream (0 skips those streams)")
     ap.add_argument("--m", type=int, default=24)
     ap.add_argument("--s", type=int, default=20)
     return ap.parse_args()
@@ -128,11 +137,92 @@ def cpu_baseline(p, m, s, C, budget_s=12.0, net_sample=1 << 21):
             done += 4
         t_coef = (time.perf_counter() - t1) / done
     full = t_net + N * t_coef
+    hi = host_info()
     return {"value": N / full, "unit": "points/s", "cores": 1, "kind": "oracle",
+            "host": hi,
             "sample": "oracle net+f at %d of %d points (extrapolated: %.1f s for all) and %d forward "
-                      "coefficients by the direct O(N) sum (%.3f s each), numpy on one thread, "
-                      "extrapolated to all N coefficients; spline and eff_dim (O(N^2) in the oracle) "
-                      "not included" % (ns, N, t_net, done, t_coef)}
+                      "coefficients by the direct O(N) sum (%.3f s each), numpy on one thread of a %d-core "
+                      "host (%s), extrapolated to all N coefficients; spline and eff_dim (O(N^2) in the "
+                      "oracle) not included; the full oracle is timed at the small configuration in the "
+                      "c1 leg" % (ns, N, t_net, done, t_coef, hi["usable_cores"], hi["cpu_model"])}
+
+
+def host_info():
+    """CPU model and core counts of the machine the bench runs on."""
+    model = ""
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    try:
+        usable = len(os.sched_getaffinity(0))
+    except AttributeError:
+        usable = os.cpu_count()
+    return {"cpu_model": model, "nproc": os.cpu_count(), "usable_cores": usable}
+
+
+def c1_leg(torch, fdwt, inputs, reps=20):
+    """The small configuration: p = 2, m = 10 (1024 points), s = 4, seeded
+    upper-triangular generators, f = prod_j (1 + 0.5 (x_j - 1/2)) (float64 on
+    the host, float32 on the device), kernel alpha = 2, gamma_j = j^-2.  The
+    whole step (forward and inverse transform, spline coefficients, effective
+    dimension) on the GPU, and the oracle's full definition of the same
+    outputs on the host (direct O(N^2) sums of the forward and inverse
+    transforms, dense Gram solve, direct double sums of the variances), both
+    timed in full."""
+    from threadpoolctl import threadpool_limits
+    from oracle import anova, families, kernel, net as onet, walsh
+    p, m, s = 2, 10, 4
+    N = p ** m
+    C = inputs.upper_triangular_generators(p, m, s, seed=1)
+    a = inputs.family_params("product", s, const=0.5)
+    gam = inputs.kernel_weights(s)
+    net = fdwt.Net(p, m, s, C)
+    kern = fdwt.Kernel(2.0, gam)
+    f = net.sample("product", a)
+    ft = torch.empty_like(f)
+    back = torch.empty_like(f)
+    c = torch.empty_like(f)
+
+    def gpu_step():
+        net.forward(f, out=ft)
+        net.inverse(ft, out=back)
+        net.spline_coef(kern, ft, out=c)
+        return net.eff_dim(kern, ft)  # synchronises
+
+    for _ in range(3):
+        gpu_step()
+    ts = []
+    for _ in range(reps):
+        t0 = time.perf_counter()
+        res = gpu_step()
+        ts.append(time.perf_counter() - t0)
+    gpu_ms = 1e3 * float(np.median(ts))
+    net.close()
+
+    def oracle_step():
+        X = onet.net_int(p, m, C)
+        fo = families.product(X / float(N), a)
+        fto = walsh.dwt_phase(p, m, fo, range(N)).real
+        walsh.idwt_phase(p, m, fto, range(N))
+        co = kernel.spline_coef_dense(p, m, 2.0, gam, X, fo)
+        trc, sup = anova.variances_direct(p, m, 2.0, gam, X, co)
+        return anova.effective_dims(trc, sup)
+
+    out = {"workload": "p=2 m=10 (N=1024) s=4, product family a_j=0.5, kernel alpha=2 gamma_j=j^-2; step = "
+                       "forward, inverse, spline coefficients, eff_dim",
+           "gpu_step_ms": gpu_ms, "gpu_d_trc_d_sup": [res["d_trc"], res["d_sup"]]}
+    for label, threads in (("oracle_1_thread", 1), ("oracle_all_threads", None)):
+        with threadpool_limits(limits=threads):
+            t0 = time.perf_counter()
+            dims = oracle_step()
+            out[label + "_s"] = time.perf_counter() - t0
+    out["oracle_d_trc_d_sup"] = [int(dims[0]), int(dims[1])]
+    out["oracle_over_gpu_1_thread"] = out["oracle_1_thread_s"] / (gpu_ms * 1e-3)
+    return out
 
 
 def batched_leg(torch, fdwt, inputs, n_jobs, reps=5):
@@ -242,18 +332,26 @@ def interp_leg(torch, fdwt, inputs, reps=3):
     torch.cuda.synchronize()
     ev = [torch.cuda.Event(enable_timing=True) for _ in range(4)]
     t_fi, t_all = [], []
-    fdwt.timing_enable(True)
-    for _ in range(reps):
+    for _ in range(23):  # forward + inverse: median of 20 after 3 warm-up rounds
         ev[0].record(stream)
         net.forward(f, out=ft)
         net.inverse(ft, out=back, real=True)
         ev[1].record(stream)
+        torch.cuda.synchronize()
+        t_fi.append(ev[0].elapsed_time(ev[1]))
+    t_fi = t_fi[3:]
+    fdwt.timing_enable(True)
+    for _ in range(reps):
+        net.forward(f, out=ft)
+        net.inverse(ft, out=back, real=True)
+        torch.cuda.synchronize()
+        ev[1].record(stream)
         net.walsh_interp(kern, f, q)
         ev[2].record(stream)
         torch.cuda.synchronize()
-        t_fi.append(ev[0].elapsed_time(ev[1]))
         t_all.append(ev[1].elapsed_time(ev[2]))
     tot, n, work = fdwt.timing_query("eval")
+    ptot, pn, pwork = fdwt.timing_query("pass_cf32")
     fdwt.timing_enable(False)
     N = p ** m
     err = float(torch.linalg.norm(back - f) / torch.linalg.norm(f))
@@ -265,6 +363,8 @@ def interp_leg(torch, fdwt, inputs, reps=3):
                               "ops_per_evaluation": "4.5 VALU (xor, ffbh, shift-add, multiply, half a min3) "
                                                     "+ 1 LDS table read"},
             "forward_inverse_ms": float(np.median(t_fi)), "points_per_s_fwd_inv": N / (np.median(t_fi) * 1e-3),
+            "complex_pass_kernels": {"launches": pn, "avg_launch_ms": ptot / pn if pn else None,
+                                     "alg_GBs": pwork / (ptot * 1e-3) / 1e9 if ptot else None},
             "interp_ms": float(np.median(t_all)), "eval_ms": tot / n,
             "eval_coordinates_per_s": work / (tot * 1e-3), "round_trip_rel_err": err}
 
@@ -335,16 +435,11 @@ def section53_leg(torch, fdwt, inputs):
             "seconds": time.perf_counter() - t0, "rows": rows}
 
 
-def serving_leg(fdwt, inputs, window, rate, budget_gb, lanes):
-    """Serving workload: Poisson arrivals at `rate` per second over `window`
-    seconds, requests drawn from a pool of 64 seeded nets (p in {2, 3, 5},
-    m log-uniform in [10, 26] capped at 2^26 points, s in 2..50), half
-    interpolation (4096 queries) and half effective dimension, product or
-    exponential family; the server runs with a `budget_gb` device budget.
-    Requests are generated before the clock starts and submitted at their
-    arrival times by a separate thread; latency = completion - submission."""
+def serve_stream(fdwt, inputs, nets, reqs, budget_gb, lanes):
+    """Submit the requests to a fresh server at their arrival times (a
+    separate thread; requests are built before the clock starts) and collect
+    every result; latency = completion - submission."""
     import threading
-    nets, reqs = inputs.serving_workload(window, rate, seed=5)
     built = []
     for r in reqs:
         p, m, s, cs = nets[r["net"]]
@@ -377,11 +472,32 @@ def serving_leg(fdwt, inputs, window, rate, budget_gb, lanes):
     que = np.array([x["t_admit"] - x["t_submit"] for x in infos])
     svc = np.array([x["t_done"] - x["t_admit"] for x in infos])
     span = max(x["t_done"] for x in infos) - min(x["t_submit"] for x in infos)
-    pts = float(sum(rq.p ** rq.m for rq in built))
-    evals = float(sum(rq.p ** rq.m * rq.s * rq.nq for rq in built))
 
     def pct(a):
         return {"p50": float(np.percentile(a, 50)), "p99": float(np.percentile(a, 99)), "mean": float(a.mean())}
+
+    return built, {"requests": len(built), "arrival_span_s": float(reqs[-1]["t"] - reqs[0]["t"]),
+                   "latency_s": pct(lat), "queue_s": pct(que), "service_s": pct(svc),
+                   "makespan_s": span, "throughput_req_per_s": len(built) / span,
+                   "kinds": {k: sum(1 for r in built if r.kind == k) for k in ("interp", "eff_dim")},
+                   "server": st}
+
+
+def serving_leg(fdwt, inputs, window, rate, budget_gb, lanes, sustained_requests=200):
+    """Serving workload: Poisson arrivals at `rate` per second over `window`
+    seconds, requests drawn from a pool of 64 seeded nets (p in {2, 3, 5},
+    m log-uniform in [10, 26] capped at 2^26 points, s in 2..50), half
+    interpolation (4096 queries) and half effective dimension, product or
+    exponential family; the server runs with a `budget_gb` device budget.
+    That window is far beyond one GPU's capacity (queueing latency); its
+    throughput is the capacity, and two sustained streams of the same recipe
+    (the same net pool) at 0.5 and 0.9 times that capacity, each of
+    `sustained_requests` requests, give latencies at loads the GPU sustains."""
+    nets, reqs = inputs.serving_workload(window, rate, seed=5)
+    built, win = serve_stream(fdwt, inputs, nets, reqs, budget_gb, lanes)
+    progress("serving window done: %.2f req/s" % win["throughput_req_per_s"])
+    pts = float(sum(rq.p ** rq.m for rq in built))
+    evals = float(sum(rq.p ** rq.m * rq.s * rq.nq for rq in built))
 
     # Plain: the same requests through the one-call library path, one at a
     # time (nets kept per key, spectra recomputed per call as the calls do).
@@ -403,17 +519,30 @@ def serving_leg(fdwt, inputs, window, rate, budget_gb, lanes):
     t_plain = time.perf_counter() - t0
     for net in pnets.values():
         net.close()
-    return {"requests": len(built), "offered_rate_per_s": rate, "arrival_window_s": window,
-            "plain_sequential_s": t_plain, "plain_throughput_req_per_s": len(built) / t_plain,
-            "served_vs_plain_throughput": (len(built) / span) / (len(built) / t_plain),
-            "budget_GB": budget_gb, "lanes": lanes,
-            "latency_s": pct(lat), "queue_s": pct(que), "service_s": pct(svc),
-            "makespan_s": span, "throughput_req_per_s": len(built) / span,
-            "points_per_s": pts / span, "eval_coordinates_per_s": evals / span,
-            "kinds": {k: sum(1 for r in built if r.kind == k) for k in ("interp", "eff_dim")},
-            "server": st,
-            "error": "each served result is bit-identical to the one-call library path on the same inputs "
-                     "(GPU tests), so served and plain accuracy are equal"}
+    out = dict(win)
+    out.update({"offered_rate_per_s": rate, "arrival_window_s": window,
+                "plain_sequential_s": t_plain, "plain_throughput_req_per_s": len(built) / t_plain,
+                "served_vs_plain_throughput": win["throughput_req_per_s"] / (len(built) / t_plain),
+                "budget_GB": budget_gb, "lanes": lanes,
+                "points_per_s": pts / win["makespan_s"], "eval_coordinates_per_s": evals / win["makespan_s"],
+                "error": "each served result is bit-identical to the one-call library path on the same inputs "
+                         "(GPU tests), so served and plain accuracy are equal"})
+    cap = win["throughput_req_per_s"]
+    sustained = {"capacity_req_per_s": cap}
+    for frac in (0.5, 0.9):
+        if sustained_requests <= 0:
+            break
+        r_off = frac * cap
+        snets, sreqs = inputs.serving_workload(1.3 * sustained_requests / r_off + 5.0, r_off, seed=5)
+        sreqs = sreqs[:sustained_requests]
+        _, res = serve_stream(fdwt, inputs, snets, sreqs, budget_gb, lanes)
+        res["offered_rate_per_s"] = r_off
+        res["offered_fraction_of_capacity"] = frac
+        sustained["at_%.1f_capacity" % frac] = res
+        progress("serving at %.1f of capacity: p50 %.3f s p99 %.3f s" % (frac, res["latency_s"]["p50"],
+                                                                          res["latency_s"]["p99"]))
+    out["sustained"] = sustained
+    return out
 
 
 def main():
@@ -442,10 +571,10 @@ def main():
 
     def step():
         # Every step computes the kernel spectrum afresh (once: spline_coef
-        # and eff_dim share it through the handle's cache).
+        # and eff_dim share it through the handle's cache).  f is sampled on
+        # the device inside the forward transform's first pass.
         net.drop_spectrum()
-        net.sample("exp", a, out=f)
-        net.forward(f, out=ft)
+        net.forward_family("exp", a, out=ft)
         net.forward(fi, out=gi)
         net.spline_coef(kern, ft, out=c)
         return net.eff_dim(kern, ft)  # synchronises
@@ -481,24 +610,47 @@ def main():
 
     # Plain forward float32 transform on its own (the two pass launches):
     # HIP events around each call, median of 50 after 10 warm-up calls, warm
-    # (back to back) and with a cold last-level cache (MALL, 256 MB: a 1 GiB
-    # buffer is written before each timed call).
-    def median_ms(flush):
+    # (back to back) and with a cold last-level cache (MALL, 256 MB): before
+    # each timed call a 1 GiB buffer is read (the MALL then holds clean lines
+    # of other data) or written (it then holds dirty lines of other data,
+    # which the transform's traffic has to write back first).  The library's
+    # launch events time each pass kernel alone: moved bytes (read + write of
+    # every pass) over the summed kernel time.
+    net.sample("exp", a, out=f)
+    flush = torch.ones(1 << 28, dtype=torch.float32, device="cuda")
+    flush_acc = torch.zeros(1, dtype=torch.float32, device="cuda")
+
+    def plain_forward(mode):
+        # Whole calls with the launch-timing hook off (its event bookkeeping
+        # between the two launches would show in the call time), then the
+        # pass kernels alone with the hook on, in separate iterations.
         e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        out_ms = []
-        for i in range(60):
-            if flush is not None:
+        out_ms, kern_ms = [], []
+        nl = 0
+        for i in range(110):
+            if mode == "read":
+                torch.sum(flush, dim=0, out=flush_acc[0])
+            elif mode == "write":
                 flush.fill_(float(i))
+            timed = i >= 60
+            if timed:
+                fdwt.timing_enable(True)
             e0.record(stream)
             net.forward(f, out=ft)
             e1.record(stream)
             torch.cuda.synchronize()
-            if i >= 10:
+            if timed:
+                tot, nl, _ = fdwt.timing_query("pass_f32")
+                fdwt.timing_enable(False)
+                kern_ms.append(tot)
+            elif i >= 10:
                 out_ms.append(e0.elapsed_time(e1))
-        return float(np.median(out_ms))
-    fwd_ms = median_ms(None)
-    flush = torch.empty(1 << 28, dtype=torch.float32, device="cuda")
-    fwd_cold_ms = median_ms(flush)
+        return float(np.median(out_ms)), float(np.median(kern_ms)), nl
+
+    fwd_ms, fwd_kern_ms, fn = plain_forward(None)
+    fwd_cold_ms, fwd_cold_kern_ms, _ = plain_forward("read")
+    fwd_dirty_ms, fwd_dirty_kern_ms, _ = plain_forward("write")
+    del flush, flush_acc
     # Device copy reference: 256 MiB each way.
     csrc = torch.empty(1 << 26, dtype=torch.float32, device="cuda")
     cdst = torch.empty_like(csrc)
@@ -512,13 +664,11 @@ def main():
         if i >= 5:
             cms.append(e0.elapsed_time(e1))
     copy_GBs = 2.0 * csrc.numel() * 4 / (float(np.median(cms)) * 1e-3) / 1e9
-    del flush, csrc, cdst
-    fdwt.timing_enable(True)
-    net.forward(f, out=ft)
-    torch.cuda.synchronize()
-    _, fn, _ = fdwt.timing_query("pass_f32")
-    fdwt.timing_enable(False)
+    del csrc, cdst
     fwd_alg = 8.0 * N / (fwd_ms * 1e-3) / 1e9
+
+    def moved(ms):
+        return 8.0 * fn * N / (ms * 1e-3) / 1e9
 
     if args.calib_copy:
         src = torch.empty(1 << 26, dtype=torch.float32, device="cuda")
@@ -541,7 +691,7 @@ def main():
         "dtype": "f32",
         "data": "synthetic",
         "config": {"workload": "plain at scale: p=2 m=%d (N=%d) s=%d, exp family f32 + int32 run, "
-                               "kernel alpha=2 gamma_j=j^-2; step = sample, forward f32, forward i32, "
+                               "kernel alpha=2 gamma_j=j^-2; step = sample + forward f32 (fused), forward i32, "
                                "spline coefficients, eff_dim" % (m, N, s),
                    "p": p, "m": m, "s": s, "points": N},
         "roofline": {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
@@ -551,27 +701,48 @@ def main():
         "classes": classes,
         "plain_forward_f32": {"ms": fwd_ms, "points_per_s": N / (fwd_ms * 1e-3),
                               "alg_GBs": fwd_alg, "frac_hbm_peak": fwd_alg / HBM_PEAK_GBS,
-                              "pass_launches": fn, "moved_GBs": 8.0 * fn * N / (fwd_ms * 1e-3) / 1e9,
+                              "pass_launches": fn, "moved_GBs": moved(fwd_ms),
+                              "kernel_ms": fwd_kern_ms, "kernel_moved_GBs": moved(fwd_kern_ms),
+                              "kernel_moved_frac_hbm_peak": moved(fwd_kern_ms) / HBM_PEAK_GBS,
                               "cold_mall_ms": fwd_cold_ms, "cold_mall_alg_GBs": 8.0 * N / (fwd_cold_ms * 1e-3) / 1e9,
-                              "timing": "HIP events per call, median of 50 after 10 warm-up calls"},
+                              "cold_mall_kernel_ms": fwd_cold_kern_ms,
+                              "cold_mall_kernel_moved_GBs": moved(fwd_cold_kern_ms),
+                              "cold_mall_kernel_moved_frac_hbm_peak": moved(fwd_cold_kern_ms) / HBM_PEAK_GBS,
+                              "dirty_mall_ms": fwd_dirty_ms, "dirty_mall_kernel_ms": fwd_dirty_kern_ms,
+                              "dirty_mall_kernel_moved_GBs": moved(fwd_dirty_kern_ms),
+                              "timing": "HIP events around each call with the launch-timing hook off (ms; median of 50 "
+                                        "after 10 warm-up calls), and the pass kernels alone, timed by events attached "
+                                        "to each dispatch, summed per call (kernel_ms; median of 50 further calls); "
+                                        "cold: a 1 GiB buffer read before each call "
+                                        "(clean MALL of other data); dirty: the same buffer written (the MALL "
+                                        "holds dirty lines that must be written back)"},
         "device_copy_GBs": copy_GBs,
         "eff_dim": {"d_trc": res["d_trc"], "d_sup": res["d_sup"], "var_total": res["var_total"]},
         "kernel_source_hash": kernel_source_hash(dom),
         "wall_s": wall,
     }
+    progress("step and plain forward done: %.3f ms/step" % ms)
+    if not args.no_c1:
+        out["c1"] = c1_leg(torch, fdwt, inputs)
+        progress("c1 done")
     if not args.no_batch:
         out["batched"] = batched_leg(torch, fdwt, inputs, args.batch_jobs)
+        progress("batched done")
     if not args.no_interp:
         out["interp_p3"] = interp_leg(torch, fdwt, inputs)
+        progress("interp_p3 done")
     if not args.no_table1:
         out["section52"] = section52_leg(torch, fdwt, inputs)
         out["section53"] = section53_leg(torch, fdwt, inputs)
+        progress("sections 5.2 / 5.3 done")
     torch.cuda.empty_cache()
     if not args.no_serve:
         out["serving"] = serving_leg(fdwt, inputs, args.serve_window, args.serve_rate, args.serve_budget_gb,
-                                     args.serve_lanes)
+                                     args.serve_lanes, args.serve_sustained)
+        progress("serving done")
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(p, m, s, C)
+        progress("cpu baseline done")
     print(json.dumps(out), flush=True)
     net.close()
 
