@@ -247,6 +247,14 @@ typedef struct {
 int fdwt_eff_dim(const fdwt_net* net, const fdwt_kernel* kern, int ft_type,
                  const void* ft_dev, fdwt_effdim* out, void* stream);
 
+/* The same from the data themselves, eff_dim(net, kernel, f) as Section 4
+ * states it: f_dev is float [N], f(x_n) at the net's points; the forward
+ * transform (Algorithm 1) runs first, into a stream-ordered allocation of
+ * this call.  Results equal fdwt_dwt_forward then fdwt_eff_dim bit for bit.
+ * Synchronises stream before returning. */
+int fdwt_eff_dim_data(const fdwt_net* net, const fdwt_kernel* kern, const float* f_dev,
+                      fdwt_effdim* out, void* stream);
+
 /* ------------------------------------------- kernel-parameter selection */
 
 /* Section 5.1, p = 2.  `net` has m + 1 digits (2N points) and its first N

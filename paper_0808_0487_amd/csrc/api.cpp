@@ -629,4 +629,28 @@ int fdwt_eff_dim(const fdwt_net* h, const fdwt_kernel* kern, int ft_type, const 
   FDWT_GUARD_END
 }
 
+int fdwt_eff_dim_data(const fdwt_net* h, const fdwt_kernel* kern, const float* f_dev, fdwt_effdim* out,
+                      void* stream) {
+  FDWT_GUARD_BEGIN
+  if (int rc = check_net(h)) return rc;
+  if (int rc = check_kernel(h->n, kern)) return rc;
+  if (!f_dev || !out || !out->var_trc || !out->var_sup) return fail(FDWT_EINVAL, "NULL argument");
+  Net& net = const_cast<Net&>(h->n);
+  DeviceGuard g(net.device);
+  hipStream_t st = (hipStream_t)stream;
+  // The transform of the data lives in a stream-ordered allocation of this
+  // call (the net's workspace holds eff_dim's own columns).
+  void* ft = nullptr;
+  if (hipMallocAsync(&ft, (size_t)net.N * (net.p == 2 ? 4 : 8), st) != hipSuccess) {
+    (void)hipGetLastError();
+    return fail(FDWT_ENOMEM, "eff_dim transform allocation failed");
+  }
+  const int ft_type = net.p == 2 ? FDWT_F32 : FDWT_CF32;
+  int rc = transform(net, false, FDWT_F32, f_dev, ft_type, ft, st);
+  if (!rc) rc = run_eff_dim(net, net.sc, kern, ft, out, st);
+  (void)hipFreeAsync(ft, st);
+  return rc;
+  FDWT_GUARD_END
+}
+
 }  // extern "C"

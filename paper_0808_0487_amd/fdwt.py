@@ -79,6 +79,7 @@ SIGNATURES = {
     "fdwt_spline_eval": (_i, [_vp, ctypes.POINTER(KernelC), _vp, _i64, _vp, _vp, _vp]),
     "fdwt_walsh_interp": (_i, [_vp, ctypes.POINTER(KernelC), _vp, _vp, _i64, _vp, _vp, _vp]),
     "fdwt_eff_dim": (_i, [_vp, ctypes.POINTER(KernelC), _i, _vp, ctypes.POINTER(EffDimC), _vp]),
+    "fdwt_eff_dim_data": (_i, [_vp, ctypes.POINTER(KernelC), _vp, ctypes.POINTER(EffDimC), _vp]),
     "fdwt_split_cost": (_i, [_vp, _vp, _d, _d, _d, _vp, ctypes.POINTER(_d)]),
     "fdwt_kernel_tune": (_i, [_vp, _vp, _vp, _i, ctypes.POINTER(KernelFitC), _vp]),
     "fdwt_batch_create": (_i, [_i, _vp, _i, ctypes.POINTER(_vp)]),
@@ -436,12 +437,27 @@ class Net:
         return {"alpha": out.alpha, "beta": out.beta, "q": out.q, "cost": out.cost, "evaluations": out.evaluations}
 
     def eff_dim(self, kern, ft, stream=None):
+        """Effective dimension from the forward transform ft of the data."""
         _need(ft, "ft", self.N, (self._coef_dtype(),), self.device)
         trc = np.zeros(self.s + 1)
         sup = np.zeros(self.s + 1)
         out = EffDimC(trc.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
                       sup.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), 0.0, 0.0, 0.0, 0, 0)
         _check(lib().fdwt_eff_dim(self.h, kern.c, _type_of(ft), _ptr(ft), ctypes.byref(out), _stream(stream)))
+        return self._effdim_dict(trc, sup, out)
+
+    def eff_dim_data(self, kern, f, stream=None):
+        """Effective dimension from the data f (float32 [N]) (fdwt_eff_dim_data)."""
+        _need(f, "f", self.N, ("float32",), self.device)
+        trc = np.zeros(self.s + 1)
+        sup = np.zeros(self.s + 1)
+        out = EffDimC(trc.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                      sup.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), 0.0, 0.0, 0.0, 0, 0)
+        _check(lib().fdwt_eff_dim_data(self.h, kern.c, _ptr(f), ctypes.byref(out), _stream(stream)))
+        return self._effdim_dict(trc, sup, out)
+
+    @staticmethod
+    def _effdim_dict(trc, sup, out):
         return {"var_trc": trc, "var_sup": sup, "var_total": out.var_total, "var_total_h0": out.var_total_h0,
                 "var_qmc": out.var_qmc, "d_trc": out.d_trc, "d_sup": out.d_sup}
 

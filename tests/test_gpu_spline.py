@@ -268,3 +268,17 @@ def test_effdim_layout_switches_bit_identical(monkeypatch):
         assert on["var_total"] == r["var_total"]
     assert np.all(np.isfinite(on["var_trc"])) and on["var_total"] > 0
     net.close()
+
+
+@pytest.mark.parametrize("p,m,s", [(2, 12, 6), (2, 17, 4), (3, 7, 5), (5, 5, 3)])
+def test_effdim_from_data_equals_two_calls(p, m, s):
+    """fdwt_eff_dim_data (eff_dim of the data, Section 4 as stated) equals
+    the forward transform followed by fdwt_eff_dim, bit for bit."""
+    announce("eff_dim from data", p, m, s)
+    net = fdwt.Net(p, m, s, inputs.upper_triangular_generators(p, m, s, 61))
+    kern = fdwt.Kernel(2.0, inputs.kernel_weights(s))
+    f = net.sample("product", inputs.family_params("product", s, alpha=2.0))
+    a = net.eff_dim_data(kern, f)
+    b = net.eff_dim(kern, net.forward(f))
+    assert np.array_equal(a["var_trc"], b["var_trc"]) and np.array_equal(a["var_sup"], b["var_sup"])
+    assert (a["var_total"], a["var_qmc"], a["d_trc"], a["d_sup"]) == (b["var_total"], b["var_qmc"], b["d_trc"], b["d_sup"])
