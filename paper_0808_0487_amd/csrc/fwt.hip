@@ -182,6 +182,136 @@ __global__ void __launch_bounds__((PassShape<P, KMAX, sizeof(T)>::THREADS))
   }
 }
 
+// -------------------------------------------- p = 3 passes, static shape
+// Float-complex passes of p = 3 with the tile geometry fixed at compile time:
+// every tile holds 3^8 = 6561 elements, 3^RD rows (the RD digits of the
+// pass) of W = 3^(8 - RD) contiguous elements (the lowest digits), 52.5 KiB
+// of LDS.  Each of TH = 3^(8 - KT) threads takes 3^KT elements: element
+// e = tid + k TH lies in row tid / W + k 3^(RD - KT), so the values a thread
+// loads differ exactly in the KT top digits of the pass (k = j0 + 3 j1 + ...),
+// whose radix-3 stages run in registers before the tile goes to LDS; the
+// other digits go through LDS in groups of up to KT digits.  With KT = 3
+// (243 threads, 27 elements each) three workgroups share a CU, so the 729
+// tiles of a 3^14-point transform run in one round; KT = 2 (729 threads)
+// serves passes of two digits.  All LDS offsets of a group are compile-time
+// strides from a per-thread base; the strides W 3^q are odd multiples of the
+// row length, so the tile needs no padding.
+template <int RD, int KT>
+struct P3Shape {
+  static constexpr int E = 6561;
+  static constexpr int EPT = PowC<3, KT>::v;  // elements per thread
+  static constexpr int TH = E / EPT;
+  static constexpr int WDIG = 8 - RD;
+  static constexpr int W = PowC<3, WDIG>::v;
+  static constexpr int RSTEP = TH / W;         // rows between a thread's elements, 3^(RD - KT)
+  static_assert(RD >= KT && RD <= 8 && RD != 7 && TH % W == 0, "unsupported p = 3 shape");
+};
+
+// Radix-3 stages over the digits 0..KG-1 of the index of x (3^KG values).
+template <int KG, bool INV, class T, int N>
+__device__ __forceinline__ void dft3_digits(T (&x)[N]) {
+  static_assert(PowC<3, KG>::v == N, "3^KG values");
+#pragma unroll
+  for (int t = 0, st = 1; t < KG; ++t, st *= 3) {
+#pragma unroll
+    for (int j0 = 0; j0 < N; ++j0)
+      if ((j0 / st) % 3 == 0) Dft<3, INV>::run(x + j0, st);
+  }
+}
+
+// Register groups over row digits [Q, Q + KG) for Q < LIM, then the next.
+template <int RD, int KT, int Q, bool INV, class T, int LIM = RD - KT, bool DONE = (Q >= LIM)>
+struct P3Groups {
+  static __device__ __forceinline__ void run(T* lds, int tid) {
+    using S = P3Shape<RD, KT>;
+    constexpr int KG = (LIM - Q) >= KT ? KT : (LIM - Q);
+    constexpr int R = PowC<3, KG>::v;
+    constexpr int PQ = PowC<3, Q>::v;
+    constexpr int STQ = S::W * PQ;          // element stride of digit Q
+    constexpr int GPT = S::E / R / S::TH;   // groups per thread
+    const int c = tid % S::W;
+    const int u0 = tid / S::W;
+#pragma unroll
+    for (int g = 0; g < GPT; ++g) {
+      // group tid + g TH: rows u = lo + PQ (j + R hi), lo < PQ
+      const int u = u0 + g * S::RSTEP;
+      const int lo = u % PQ, hi = u / PQ;
+      T* base = lds + c + S::W * (lo + PQ * R * hi);
+      T x[R];
+#pragma unroll
+      for (int j = 0; j < R; ++j) x[j] = base[j * STQ];
+      dft3_digits<KG, INV>(x);
+#pragma unroll
+      for (int j = 0; j < R; ++j) base[j * STQ] = x[j];
+    }
+    lds_barrier();
+    P3Groups<RD, KT, Q + KG, INV, T, LIM>::run(lds, tid);
+  }
+};
+template <int RD, int KT, int Q, bool INV, class T, int LIM>
+struct P3Groups<RD, KT, Q, INV, T, LIM, true> {
+  static __device__ __forceinline__ void run(T*, int) {}
+};
+
+template <bool INV, class Tin, class T, class Tout, int RD, int KT>
+__global__ void __launch_bounds__((P3Shape<RD, KT>::TH)) fwt_p3s(const Tin* __restrict__ in, Tout* out, PassDesc d) {
+  using S = P3Shape<RD, KT>;
+  constexpr int TH = S::TH, EPT = S::EPT;
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  T* lds = reinterpret_cast<T*>(smem_raw);
+  const int G = gridDim.x;
+  const int nb = d.ntiles * d.batch;
+  const int hw = blockIdx.x;
+  int lb = d.xcd ? ((hw & 7) * (G >> 3) + (hw >> 3)) : hw;
+  const int tid = threadIdx.x;
+  // Global offset of element tid + k TH: goff0 + k gstep.
+  const uint32_t sd0 = (uint32_t)d.sd0;
+  const uint32_t goff0 = (uint32_t)(tid % S::W) + (uint32_t)(tid / S::W) * sd0;
+  const uint32_t gstep = (uint32_t)S::RSTEP * sd0;
+  auto locate = [&](int l, int& col, int& tile) {
+    col = l / d.ntiles;
+    tile = l % d.ntiles;
+  };
+  auto tile_base = [&](int tile) {
+    const int lo = tile % d.nlo;
+    const int hi = tile / d.nlo;
+    return (int64_t)lo * S::W + (int64_t)hi * d.shi;
+  };
+  Tin pre[EPT];
+  auto prefetch = [&](int l) {
+    int col, tile;
+    locate(l, col, tile);
+    const Tin* src = in + (int64_t)col * d.col_in + tile_base(tile) + goff0;
+#pragma unroll
+    for (int k = 0; k < EPT; ++k) pre[k] = src[k * gstep];
+  };
+  if (lb < nb) prefetch(lb);
+  for (; lb < nb; lb += G) {
+    T v[EPT];
+#pragma unroll
+    for (int k = 0; k < EPT; ++k) v[k] = cvt_in<Tin, T>(pre[k]);
+    dft3_digits<KT, INV>(v);  // the KT top digits of the pass
+    int col, tile;
+    locate(lb, col, tile);
+    Tout* dst = out + (int64_t)col * d.col_out + tile_base(tile) + goff0;
+    if constexpr (RD == KT) {
+      // The pass has no other digits: straight back to memory.
+      prefetch(lb + G < nb ? lb + G : lb);  // unconditional: exact wait counts
+#pragma unroll
+      for (int k = 0; k < EPT; ++k) dst[k * gstep] = cvt_out<T, Tout>(v[k], d.scale, d.scale64);
+    } else {
+#pragma unroll
+      for (int k = 0; k < EPT; ++k) lds[tid + k * TH] = v[k];
+      lds_barrier();
+      prefetch(lb + G < nb ? lb + G : lb);  // unconditional: exact wait counts
+      P3Groups<RD, KT, 0, INV, T>::run(lds, tid);
+#pragma unroll
+      for (int k = 0; k < EPT; ++k) dst[k * gstep] = cvt_out<T, Tout>(lds[tid + k * TH], d.scale, d.scale64);
+      lds_barrier();
+    }
+  }
+}
+
 // -------------------------------------------- p = 2 passes, static shape
 // For p = 2 the tile shape (2^LOGE elements, rows of 2^WDIG contiguous
 // elements) is a template parameter, so every LDS and global offset inside a
@@ -900,6 +1030,133 @@ static int occupancy(const void* fn, int threads, size_t lds) {
   return n;
 }
 
+// ---------------------------------------------- p = 3 static-shape passes
+// FDWT_P3_STATIC = 0 sends p = 3 float-complex transforms through the
+// generic pass instead (read once per process).
+static bool p3_static_enabled() {
+  static const bool on = [] {
+    const char* e = getenv("FDWT_P3_STATIC");
+    return e ? atoi(e) != 0 : true;
+  }();
+  return on;
+}
+
+// Whether a pass has a shape of fwt_p3s: the first pass of 8 digits, or a
+// strided pass of 2..6 digits over rows of 3^(8 - r) elements.
+static bool p3s_shape(const PassGeom& g) {
+  return (g.d0 == 0 && g.r == 8 && g.wdig == 0) || (g.d0 >= 8 && g.r >= 2 && g.r <= 6 && g.wdig == 8 - g.r);
+}
+
+// The generic plan's digit split (a first pass of 8 digits, the rest split
+// evenly into passes of at most 6), with every strided pass of two or more
+// digits taking rows of 3^(8 - r) elements, so that its tiles hold 3^8.
+static std::vector<PassGeom> plan_p3s(int m) {
+  std::vector<PassGeom> v = plan(3, m, sizeof(float2), K_CF32);
+  for (PassGeom& g : v)
+    if (g.d0 > 0 && g.r >= 2) g.wdig = 8 - g.r;
+  return v;
+}
+
+// FDWT_P3_KT = 2 or 3 fixes the register digits of every static pass of
+// three or more digits (read once per process); 0 or unset: chosen per launch.
+static int p3s_kt_forced() {
+  static const int kt = [] {
+    const char* e = getenv("FDWT_P3_KT");
+    const int v = e ? atoi(e) : 0;
+    return v == 2 || v == 3 ? v : 0;
+  }();
+  return kt;
+}
+
+template <bool INV, class Tin, class Tout, int RD>
+static const void* p3s_kernel(int kt) {
+  if constexpr (RD >= 3) {
+    if (kt == 3) return (const void*)fwt_p3s<INV, Tin, float2, Tout, RD, 3>;
+    return (const void*)fwt_p3s<INV, Tin, float2, Tout, RD, 2>;
+  } else {
+    return kt == 2 ? (const void*)fwt_p3s<INV, Tin, float2, Tout, RD, 2> : nullptr;
+  }
+}
+
+template <bool INV, class Tin, class Tout>
+static const void* p3s_kernel_for(int rd, int kt) {
+  if (rd == 8) return p3s_kernel<INV, Tin, Tout, 8>(kt);
+  if constexpr (std::is_same<Tin, float2>::value) {
+    switch (rd) {
+      case 2: return p3s_kernel<INV, Tin, Tout, 2>(kt);
+      case 3: return p3s_kernel<INV, Tin, Tout, 3>(kt);
+      case 4: return p3s_kernel<INV, Tin, Tout, 4>(kt);
+      case 5: return p3s_kernel<INV, Tin, Tout, 5>(kt);
+      case 6: return p3s_kernel<INV, Tin, Tout, 6>(kt);
+    }
+  }
+  return nullptr;
+}
+
+template <bool INV, class Tin, class Tout>
+static int launch_p3s(const void* in, void* out, const PassGeom& g, int m, int batch, double scale, hipStream_t st) {
+  if (!p3s_shape(g)) return fail(FDWT_EINVAL, "not a static p = 3 pass shape");
+  const int64_t N = ipow(3, m);
+  const int64_t ntiles = N / 6561;
+  const int64_t nb = ntiles * batch;
+  const size_t lds = (size_t)6561 * sizeof(float2);
+  // Two register digits (729 threads, two workgroups per CU) hide memory
+  // latency best; three (243 threads, three per CU) pay when they let every
+  // tile run in one round and two digits would not (3^14 points: 729 tiles).
+  const void* fn = p3s_kernel_for<INV, Tin, Tout>(g.r, 2);
+  int kt = 2;
+  if (!fn) return fail(FDWT_EINVAL, "static p = 3 pass not built for these element types");
+  if (g.r >= 3) {
+    const void* fn3 = p3s_kernel_for<INV, Tin, Tout>(g.r, 3);
+    if (int rc = allow_lds(fn, lds)) return rc;
+    if (int rc = allow_lds(fn3, lds)) return rc;
+    const int64_t g2 = (int64_t)occupancy(fn, 729, lds) * device_cus();
+    const int64_t g3 = (int64_t)occupancy(fn3, 243, lds) * device_cus();
+    const int forced = p3s_kt_forced();
+    if (forced ? forced == 3 : (nb > g2 && nb <= g3)) {
+      fn = fn3;
+      kt = 3;
+    }
+  }
+  PassDesc d{};
+  d.col_in = N;
+  d.col_out = N;
+  d.sd0 = ipow(3, g.d0);
+  d.shi = ipow(3, g.d0 + g.r);
+  d.r = g.r;
+  d.wdig = g.wdig;
+  d.w = (int)ipow(3, g.wdig);
+  d.nlo = (int)ipow(3, g.d0 - g.wdig);
+  d.E = 6561;
+  d.kreg = kt;
+  d.scale = (float)scale;
+  d.scale64 = scale;
+  d.h0_col = -1;
+  d.ntiles = (int)ntiles;
+  d.batch = batch;
+  const int threads = kt == 3 ? 243 : 729;
+  if (int rc = allow_lds(fn, lds)) return rc;
+  int64_t G = (int64_t)occupancy(fn, threads, lds) * device_cus();
+  if (G >= nb) G = nb;
+  if (G >= 64) G -= G % 8;
+  d.xcd = (G % 8 == 0 && G >= 64) ? 1 : 0;
+  const Tin* inp = (const Tin*)in;
+  Tout* outp = (Tout*)out;
+  void* args[] = {(void*)&inp, (void*)&outp, (void*)&d};
+  return launch_timed(fn, dim3((unsigned)G), dim3(threads), args, lds, st, FDWT_TC_PASS_CF32,
+                      (double)N * batch * (sizeof(Tin) + sizeof(Tout)));
+}
+
+template <bool INV>
+static int p3s_pass_dir(Kind ik, Kind ok, const void* in, void* out, const PassGeom& g, int m, int batch,
+                        double scale, hipStream_t st) {
+  if (ik == K_F32 && ok == K_CF32) return launch_p3s<INV, float, float2>(in, out, g, m, batch, scale, st);
+  if (ik == K_F32 && ok == K_F32) return launch_p3s<INV, float, float>(in, out, g, m, batch, scale, st);
+  if (ik == K_CF32 && ok == K_CF32) return launch_p3s<INV, float2, float2>(in, out, g, m, batch, scale, st);
+  if (ik == K_CF32 && ok == K_F32) return launch_p3s<INV, float2, float>(in, out, g, m, batch, scale, st);
+  return fail(FDWT_EINVAL, "unsupported transform element types");
+}
+
 // Partial sums per column written by a reducing static pass: one per wave of
 // every tile.
 static int64_t p2_reduce_parts(int m, const P2Pass& g) {
@@ -1023,28 +1280,33 @@ static int run_passes(int p, int m, bool inverse, Kind in_kind, const void* in, 
   if (p2_static_ok(p, m, in_kind, work_kind, out_kind))
     return run_p2(m, work_kind, in, out, tmp, batch, scale, red, last_parts, st);
   const int64_t N = ipow(p, m);
-  std::vector<PassGeom> passes = plan(p, m, kind_bytes(work_kind), work_kind);
+  // p = 3 float-complex store passes take the static shapes where the plan
+  // has them (every pass but a strided one of a single digit, for m >= 8).
+  const bool p3s = p == 3 && work_kind == K_CF32 && !red && p3_static_enabled();
+  std::vector<PassGeom> passes = p3s ? plan_p3s(m) : plan(p, m, kind_bytes(work_kind), work_kind);
   const size_t np = passes.size();
   if (last_parts) {
     const PassGeom& g = passes.back();
     *last_parts = N / (ipow(p, g.r) * ipow(p, g.wdig));
   }
-  if (np == 1)
-    return pass_any(p, inverse, in_kind, work_kind, out_kind, in, out, passes[0], m, batch, scale, N, N,
-                    red, st);
+  auto one = [&](Kind ik, Kind ok, const void* src, void* dst, const PassGeom& g, double sc,
+                 const ReduceArgs* rd) {
+    if (p3s && p3s_shape(g))
+      return inverse ? p3s_pass_dir<true>(ik, ok, src, dst, g, m, batch, sc, st)
+                     : p3s_pass_dir<false>(ik, ok, src, dst, g, m, batch, sc, st);
+    return pass_any(p, inverse, ik, work_kind, ok, src, dst, g, m, batch, sc, N, N, rd, st);
+  };
+  if (np == 1) return one(in_kind, out_kind, in, out, passes[0], scale, red);
   // Intermediate buffer: the output itself when it holds the working type.
   void* mid = (!red && kind_bytes(out_kind) == kind_bytes(work_kind)) ? out : tmp;
   if (!mid) return fail(FDWT_EINVAL, "transform needs a workspace for its intermediate passes");
-  int rc = pass_any(p, inverse, in_kind, work_kind, work_kind, in, mid, passes[0], m, batch, 1.0f, N, N,
-                    nullptr, st);
+  int rc = one(in_kind, work_kind, in, mid, passes[0], 1.0, nullptr);
   if (rc) return rc;
   for (size_t i = 1; i + 1 < np; ++i) {
-    rc = pass_any(p, inverse, work_kind, work_kind, work_kind, mid, mid, passes[i], m, batch, 1.0f, N, N,
-                  nullptr, st);
+    rc = one(work_kind, work_kind, mid, mid, passes[i], 1.0, nullptr);
     if (rc) return rc;
   }
-  return pass_any(p, inverse, work_kind, work_kind, out_kind, mid, out, passes[np - 1], m, batch, scale,
-                  N, N, red, st);
+  return one(work_kind, out_kind, mid, out, passes[np - 1], scale, red);
 }
 
 int fwt_run_tmp(int p, int m, bool inverse, Kind in_kind, const void* in, Kind work_kind,

@@ -77,7 +77,7 @@ def test_p2_int32_bit_exact(m):
     assert np.array_equal(back, (N * f.astype(np.int64) + 2 ** 31) % 2 ** 32 - 2 ** 31)
 
 
-@pytest.mark.parametrize("p,m", [(3, 1), (3, 2), (3, 7), (3, 8), (3, 9), (3, 12), (3, 15),
+@pytest.mark.parametrize("p,m", [(3, 1), (3, 2), (3, 7), (3, 8), (3, 9), (3, 10), (3, 11), (3, 12), (3, 15),
                                  (5, 1), (5, 2), (5, 5), (5, 6), (5, 8), (5, 10),
                                  (7, 1), (7, 2), (7, 4), (7, 5), (7, 7), (7, 9)])
 def test_odd_p_complex_sizes(p, m):
