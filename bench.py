@@ -232,7 +232,7 @@ def batched_leg(torch, fdwt, inputs, n_jobs, reps=5):
     batch of grouped static passes with autotuned plans, (c) through the
     generic persistent launch per pass level in float32 and (d) with the
     bfloat16-split matrix-core low stages, (e) batch (b) replayed from a
-    captured graph.
+    captured graph, (f) every pass of every job in one persistent launch.
     Accuracy of each path: normwise error per job against the library's
     float64 transform of the same data."""
     specs = inputs.batch_jobs(n_jobs, seed=4)
@@ -248,6 +248,7 @@ def batched_leg(torch, fdwt, inputs, n_jobs, reps=5):
     y32 = [torch.empty_like(x) for x in xs]
     y32g = [torch.empty_like(x) for x in xs]
     y16 = [torch.empty_like(x) for x in xs]
+    y1 = [torch.empty_like(x) for x in xs]
     b32 = fdwt.Batch([(sp[0], x, y) for sp, x, y in zip(specs, xs, y32)], "f32")
     t0 = time.perf_counter()
     b32.autotune(reps=3)
@@ -255,6 +256,7 @@ def batched_leg(torch, fdwt, inputs, n_jobs, reps=5):
     t_tune = time.perf_counter() - t0
     b32g = fdwt.Batch([(sp[0], x, y) for sp, x, y in zip(specs, xs, y32g)], "f32_generic")
     b16 = fdwt.Batch([(sp[0], x, y) for sp, x, y in zip(specs, xs, y16)], "bf16x2")
+    b1 = fdwt.Batch([(sp[0], x, y) for sp, x, y in zip(specs, xs, y1)], "f32_one_launch")
     stream = torch.cuda.current_stream()
 
     def timed(fn):
@@ -278,6 +280,8 @@ def batched_leg(torch, fdwt, inputs, n_jobs, reps=5):
     t32 = timed(b32.run)
     t32g = timed(b32g.run)
     t16 = timed(b16.run)
+    t1 = timed(b1.run)
+    b1.check()
     g = torch.cuda.CUDAGraph()
     gs = torch.cuda.Stream()
     torch.cuda.synchronize()
@@ -285,11 +289,11 @@ def batched_leg(torch, fdwt, inputs, n_jobs, reps=5):
         b32.run(stream=gs)
     t_graph = timed(g.replay)
     b32.check()
-    errs = {"plain": [], "f32": [], "f32_generic": [], "bf16x2": []}
-    for net, x, yp, ya, yg, yb in zip(nets, xs, y_plain, y32, y32g, y16):
+    errs = {"plain": [], "f32": [], "f32_generic": [], "bf16x2": [], "f32_one_launch": []}
+    for net, x, yp, ya, yg, yb, yo in zip(nets, xs, y_plain, y32, y32g, y16, y1):
         ref = net.forward(x.double())
         den = float(torch.linalg.norm(ref))
-        for k, y in (("plain", yp), ("f32", ya), ("f32_generic", yg), ("bf16x2", yb)):
+        for k, y in (("plain", yp), ("f32", ya), ("f32_generic", yg), ("bf16x2", yb), ("f32_one_launch", yo)):
             errs[k].append(float(torch.linalg.norm(y.double() - ref)) / den)
     for net in nets:
         net.close()
@@ -297,6 +301,7 @@ def batched_leg(torch, fdwt, inputs, n_jobs, reps=5):
     b32.close()
     b32g.close()
     b16.close()
+    b1.close()
 
     def path(t, key):
         e = np.array(errs[key])
@@ -308,6 +313,7 @@ def batched_leg(torch, fdwt, inputs, n_jobs, reps=5):
                       "seed 4; sampling untimed; median of %d runs" % reps,
             "plain_per_job": path(t_plain, "plain"), "batch_f32": path(t32, "f32"),
             "batch_f32_generic": path(t32g, "f32_generic"), "batch_bf16x2": path(t16, "bf16x2"),
+            "batch_f32_one_launch": path(t1, "f32_one_launch"),
             "tuned_plans_m_emax_jobs": plans, "autotune_s": t_tune,
             "batch_f32_graph": {"ms": t_graph, "points_per_s": total / (t_graph * 1e-3)},
             "speedup_batch_vs_plain": t_plain / t32}
@@ -340,6 +346,22 @@ def interp_leg(torch, fdwt, inputs, reps=3):
         torch.cuda.synchronize()
         t_fi.append(ev[0].elapsed_time(ev[1]))
     t_fi = t_fi[3:]
+    # Back to back: 20 forward + inverse pairs between two events (the host
+    # launches run ahead of the device, so no call waits for its launch).
+    ev[0].record(stream)
+    for _ in range(20):
+        net.forward(f, out=ft)
+        net.inverse(ft, out=back, real=True)
+    ev[1].record(stream)
+    torch.cuda.synchronize()
+    t_b2b = ev[0].elapsed_time(ev[1]) / 20
+    fdwt.timing_enable(True)
+    for _ in range(5):
+        net.forward(f, out=ft)
+        net.inverse(ft, out=back, real=True)
+    torch.cuda.synchronize()
+    ftot, fn, fwork = fdwt.timing_query("pass_cf32")
+    fdwt.timing_enable(False)
     fdwt.timing_enable(True)
     for _ in range(reps):
         net.forward(f, out=ft)
@@ -363,6 +385,9 @@ def interp_leg(torch, fdwt, inputs, reps=3):
                               "ops_per_evaluation": "4.5 VALU (xor, ffbh, shift-add, multiply, half a min3) "
                                                     "+ 1 LDS table read"},
             "forward_inverse_ms": float(np.median(t_fi)), "points_per_s_fwd_inv": N / (np.median(t_fi) * 1e-3),
+            "forward_inverse_ms_back_to_back": t_b2b,
+            "forward_inverse_kernels": {"launches_per_pair": fn / 5, "kernel_ms_per_pair": ftot / 5,
+                                        "alg_GBs": fwork / (ftot * 1e-3) / 1e9 if ftot else None},
             "complex_pass_kernels": {"launches": pn, "avg_launch_ms": ptot / pn if pn else None,
                                      "alg_GBs": pwork / (ptot * 1e-3) / 1e9 if ptot else None},
             "interp_ms": float(np.median(t_all)), "eval_ms": tot / n,

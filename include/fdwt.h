@@ -55,6 +55,7 @@ extern "C" {
 #define FDWT_EDEVICE      -3   /* a HIP runtime call failed                   */
 #define FDWT_EBUDGET      -4   /* request exceeds a configured memory budget  */
 #define FDWT_EUNSUPPORTED -5   /* valid math, not supported here (e.g. p = 11)*/
+#define FDWT_ETIMEOUT     -6   /* a bounded device-side wait gave up          */
 
 /* Element types of transform inputs and outputs. */
 #define FDWT_F32  1   /* float                                               */
@@ -302,12 +303,26 @@ int fdwt_kernel_tune(const fdwt_net* net, const float* f2_dev, const double* sta
  *                          Walsh-Hadamard blocks) run on the matrix cores as
  *                          H16 (hi + lo), x split into two bfloat16 terms,
  *                          float32 accumulation (relative error about 2^-18
- *                          per element from the split).
- * Jobs with m < 7 always take the generic path.  No workgroup waits on
- * another in any of them.  fdwt_batch_create copies the job list to the
- * device (buffers are fixed at creation); fdwt_batch_run enqueues the
+ *                          per element from the split);
+ *   FDWT_PREC_F32_ONE_LAUNCH  float32, every pass of every job in one
+ *                          persistent launch: workgroups take the work items
+ *                          (job, pass, tile) in the order fdwt_batch_schedule
+ *                          reports from a ticket counter, and an item of pass
+ *                          k > 0 waits (device-scope acquire) until its job's
+ *                          pass k-1 is complete (device-scope release by each
+ *                          finished tile).  Every wait is on items with earlier
+ *                          tickets, which running workgroups hold, so the
+ *                          launch completes whatever the number of resident
+ *                          workgroups.  Waits give up after 2 s of device
+ *                          time; fdwt_batch_check then returns FDWT_ETIMEOUT
+ *                          (outputs incomplete).
+ * Jobs with m < 7 always take the generic path (with FDWT_PREC_F32).
+ * Except in FDWT_PREC_F32_ONE_LAUNCH no workgroup waits on another (the
+ * kernel boundaries order the passes).  fdwt_batch_create copies the job list
+ * to the device (buffers are fixed at creation); fdwt_batch_run enqueues the
  * launches (nothing else; it can be captured in a HIP graph);
- * fdwt_batch_check waits for the stream and reports any HIP error.
+ * fdwt_batch_check waits for the stream and reports any HIP error and, for
+ * FDWT_PREC_F32_ONE_LAUNCH, a wait that gave up.
  * fdwt_batch_autotune times every distinct plan of every group (first pass
  * of 2^10 .. 2^14 elements) `reps` times on `stream` and keeps the fastest
  * (median); it overwrites the outputs and skips groups with a job in place.
@@ -323,6 +338,7 @@ typedef struct {
 #define FDWT_PREC_F32         0
 #define FDWT_PREC_BF16X2      1
 #define FDWT_PREC_F32_GENERIC 2
+#define FDWT_PREC_F32_ONE_LAUNCH 3
 
 typedef struct fdwt_batch fdwt_batch;
 
@@ -332,6 +348,16 @@ int fdwt_batch_check(fdwt_batch* batch, void* stream);
 int fdwt_batch_autotune(fdwt_batch* batch, int reps, void* stream);
 int fdwt_batch_describe(const fdwt_batch* batch, int cap, int* m, int* emax, int* njobs, int* n_groups);
 void fdwt_batch_free(fdwt_batch* batch);
+
+/* The work items of FDWT_PREC_F32_ONE_LAUNCH (and of the level launches of
+ * FDWT_PREC_F32_GENERIC) for jobs of sizes m[0..n_jobs) in ticket order,
+ * computed on the host (no device is used): item i is tile tile[i] of pass
+ * pass[i] of job job[i] (index into m), and need[i] is the number of tiles
+ * of that job's pass pass[i] - 1 that must be done first (0 for pass 0).
+ * Writes the first min(cap, total) items into each non-NULL array, the total
+ * into *n_items and the items per ticket into *chunk (if non-NULL). */
+int fdwt_batch_schedule(int n_jobs, const int* m, int cap, int* job, int* pass, int* tile, int* need, int* n_items,
+                        int* chunk);
 
 /* ------------------------------------------------------------- serving */
 

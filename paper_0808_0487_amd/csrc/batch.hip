@@ -13,19 +13,21 @@
 //  * generic (FDWT_PREC_BF16X2, FDWT_PREC_F32_GENERIC, and jobs with m < 7):
 //    level k of the batch is the list of all tiles of pass k of every job;
 //    each level is one persistent launch whose workgroups take the level's
-//    tiles with a fixed stride (largest jobs first).
+//    tiles with a fixed stride (largest jobs first);
+//  * one launch (FDWT_PREC_F32_ONE_LAUNCH): the same items, all levels, in
+//    one persistent launch with a ticket counter and per-job pass counters
+//    (k_batch_one below).
 //
-// In both no workgroup ever waits for another: the kernel boundary between
-// passes orders pass k before pass k+1.  An earlier design ran all passes of
-// the batch in one launch, workgroups spinning on per-job pass counters that
-// other workgroups advanced; it did not finish on the device and was
-// replaced before its cause was established.  Two causes fit what was seen
-// and neither was shown: counter updates and reads without device-scope
-// release/acquire ordering (each XCD has its own L2), and waits on producer
-// workgroups that were not yet resident (a fixed-stride item order gives no
-// forward-progress guarantee).  A single-launch version would need both
-// ruled out first, by emulating its item order and counter protocol on the
-// host.
+// In the first two no workgroup ever waits for another: the kernel boundary
+// between passes orders pass k before pass k+1.  A first one-launch design
+// (fixed-stride item order, plain counter stores and loads) did not finish on
+// the device; two causes fit what was seen and neither was shown: counter
+// updates and reads without device-scope release/acquire ordering (each XCD
+// has its own L2), and waits on producer workgroups that were not yet
+// resident (a fixed-stride order gives no forward-progress guarantee).
+// k_batch_one removes both: tickets in dependency order (a wait is always on
+// an item a running workgroup holds, checked by a host emulation of the
+// schedule), release/acquire at device scope, and bounded waits.
 //
 // Precision FDWT_PREC_BF16X2: in each job's first pass the stages of index
 // digits 0..3 (16-point Walsh-Hadamard blocks) run on the matrix cores as
@@ -97,51 +99,160 @@ __device__ void mfma_low4(float* lds, int E) {
   }
 }
 
+// One tile of one pass of one job (runtime geometry): load into LDS, the
+// pass's stages in register groups, store (scaled by 2^-m in the last pass).
+// Ends with a workgroup barrier.  With COHERENT, a tile written by an earlier
+// pass of the same launch (pass > 0) is loaded, and a tile that a later pass
+// of the launch reads (not the last pass) is stored, with device-scope
+// (relaxed atomic) accesses, which read and write at the point of coherence
+// of all XCDs instead of through this XCD's L2.
+template <bool COHERENT>
+__device__ __forceinline__ void batch_tile(const BJob& J, const BItem I, int prec, float* blds) {
+  const int ps = I.pass;
+  PassDesc d{};
+  d.r = J.r[ps];
+  d.wdig = J.wdig[ps];
+  d.w = 1 << d.wdig;
+  d.sd0 = int64_t(1) << J.d0[ps];
+  d.shi = int64_t(1) << (J.d0[ps] + d.r);
+  d.nlo = 1 << (J.d0[ps] - d.wdig);
+  d.E = 1 << (d.r + d.wdig);
+  d.kreg = 4;
+  const int lo = I.tile % d.nlo, hi = I.tile / d.nlo;
+  const int64_t base = (int64_t)lo * d.w + (int64_t)hi * d.shi;
+  const gptr<const float> src = to_global((ps == 0 ? J.in : J.out) + base);
+  for (int e = threadIdx.x; e < d.E; e += blockDim.x) {
+    const int c = e & (d.w - 1), i = e >> d.wdig;
+    if (COHERENT && ps > 0)
+      blds[pad(e)] = __hip_atomic_load(to_global(const_cast<float*>((ps == 0 ? J.in : J.out) + base)) + c +
+                                           (int64_t)i * d.sd0,
+                                       __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    else
+      blds[pad(e)] = src[c + (int64_t)i * d.sd0];
+  }
+  __syncthreads();
+  int q0 = 0;
+  if (prec == FDWT_PREC_BF16X2 && ps == 0 && d.wdig == 0 && d.r >= 8) {
+    mfma_low4(blds, d.E);
+    __syncthreads();
+    q0 = 4;
+  }
+  for (int q = q0; q < d.r; q += 4) {
+    const int kk = min(4, d.r - q);
+    if (kk == 4) run_group<2, false, float, 4>(blds, d, q);
+    else if (kk == 3) run_group<2, false, float, 3>(blds, d, q);
+    else if (kk == 2) run_group<2, false, float, 2>(blds, d, q);
+    else run_group<2, false, float, 1>(blds, d, q);
+    __syncthreads();
+  }
+  const float sc = (ps == J.npass - 1) ? J.scale : 1.0f;
+  const gptr<float> dst = to_global(J.out + base);
+  for (int e = threadIdx.x; e < d.E; e += blockDim.x) {
+    const int c = e & (d.w - 1), i = e >> d.wdig;
+    if (COHERENT && ps < J.npass - 1)
+      __hip_atomic_store(dst + c + (int64_t)i * d.sd0, blds[pad(e)] * sc, __ATOMIC_RELAXED,
+                         __HIP_MEMORY_SCOPE_AGENT);
+    else
+      dst[c + (int64_t)i * d.sd0] = blds[pad(e)] * sc;
+  }
+  __syncthreads();
+}
+
+// Level launch of the generic path: items of one pass level, fixed stride.
 __global__ void __launch_bounds__(kBThreads) k_batch_fwd(const BJob* __restrict__ jobs, const BItem* __restrict__ items,
                                                        int n_items, int prec) {
   extern __shared__ __align__(16) float blds[];
   for (int it = blockIdx.x; it < n_items; it += gridDim.x) {
     const BItem I = items[it];
-    const BJob& J = jobs[I.job];
-    const int ps = I.pass;
-    PassDesc d{};
-    d.r = J.r[ps];
-    d.wdig = J.wdig[ps];
-    d.w = 1 << d.wdig;
-    d.sd0 = int64_t(1) << J.d0[ps];
-    d.shi = int64_t(1) << (J.d0[ps] + d.r);
-    d.nlo = 1 << (J.d0[ps] - d.wdig);
-    d.E = 1 << (d.r + d.wdig);
-    d.kreg = 4;
-    const int lo = I.tile % d.nlo, hi = I.tile / d.nlo;
-    const int64_t base = (int64_t)lo * d.w + (int64_t)hi * d.shi;
-    const gptr<const float> src = to_global((ps == 0 ? J.in : J.out) + base);
-    for (int e = threadIdx.x; e < d.E; e += blockDim.x) {
-      const int c = e & (d.w - 1), i = e >> d.wdig;
-      blds[pad(e)] = src[c + (int64_t)i * d.sd0];
+    batch_tile<false>(jobs[I.job], I, prec, blds);
+  }
+}
+
+// ------------------------------------------------ one launch for the batch
+// FDWT_PREC_F32_ONE_LAUNCH runs every pass of every job in one persistent
+// launch.  Work items (job, pass, tile) are numbered level by level (every
+// job's pass 0, then every pass 1, ...), and a workgroup takes the next
+// kBChunk of them from a ticket counter and runs them in order.  An item of
+// pass k > 0 waits until all ntiles[k-1] tiles of its job's pass k-1 are
+// done.  Those items have smaller numbers, so their tickets were taken
+// before and are held by workgroups that are running (a workgroup takes a
+// ticket only while it runs and keeps running until its items are done);
+// by induction on the item number every wait ends, whatever the number of
+// workgroups resident at once.  Each XCD has its own L2, so data must not
+// pass between workgroups through it: tiles are loaded and stored with
+// device-scope accesses (relaxed atomics, which the hardware serves at the
+// point of coherence of all XCDs) where another pass of the launch reads or
+// wrote them, every thread waits for its stores to be acknowledged, and only
+// then, after a workgroup barrier, is the job's pass counter incremented
+// (device scope); a waiting workgroup polls the counter with device-scope
+// loads before it loads the tile.  A job's input is read only by its first
+// pass and its last pass's output by no one in the launch: those accesses
+// stay ordinary, and the last pass counts nothing.  (Release and acquire
+// fences would do the same by writing back and invalidating the whole L2
+// around every tile: a batch of 512 jobs took 58 ms that way.)  Waits are
+// bounded: after `timeout` ticks of the wall clock, or once another
+// workgroup has given up, a workgroup raises the error flag and exits, so
+// the launch always ends (fdwt_batch_check then reports the failure).
+constexpr int kBChunk = 4;  // items per ticket
+
+struct BCtl {
+  int next;   // next ticket (item number)
+  int error;  // set when a wait gave up
+};
+
+__global__ void k_batch_reset(BCtl* ctl, int* done, int n) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i == 0) {
+    ctl->next = 0;
+    ctl->error = 0;
+  }
+  if (i < n) done[i] = 0;
+}
+
+// Thread 0 of a workgroup: spin until *cnt >= need; 1 if it gave up (after
+// `timeout` wall-clock ticks, or 2^26 polls, whichever comes first).
+__device__ int wait_count(int* cnt, int need, BCtl* ctl, uint64_t timeout) {
+  if (__hip_atomic_load(cnt, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) >= need) return 0;
+  const uint64_t t0 = wall_clock64();
+  for (int polls = 0;; ++polls) {
+    __builtin_amdgcn_s_sleep(2);
+    if (__hip_atomic_load(cnt, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) >= need) return 0;
+    if (__hip_atomic_load(&ctl->error, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) return 1;
+    if (wall_clock64() - t0 > timeout || polls >= (1 << 26)) {
+      __hip_atomic_store(&ctl->error, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      return 1;
     }
+  }
+}
+
+__global__ void __launch_bounds__(kBThreads) k_batch_one(const BJob* __restrict__ jobs, const BItem* __restrict__ items,
+                                                       int n_items, int prec, BCtl* ctl, int* done, uint64_t timeout) {
+  extern __shared__ __align__(16) float blds[];
+  __shared__ int s_first, s_abort;
+  for (;;) {
+    if (threadIdx.x == 0)
+      s_first = __hip_atomic_fetch_add(&ctl->next, kBChunk, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     __syncthreads();
-    int q0 = 0;
-    if (prec == FDWT_PREC_BF16X2 && ps == 0 && d.wdig == 0 && d.r >= 8) {
-      mfma_low4(blds, d.E);
-      __syncthreads();
-      q0 = 4;
+    const int first = s_first;
+    if (first >= n_items) return;
+    const int last = min(first + kBChunk, n_items);
+    for (int it = first; it < last; ++it) {
+      const BItem I = items[it];
+      const BJob& J = jobs[I.job];
+      if (I.pass > 0) {
+        if (threadIdx.x == 0)
+          s_abort = wait_count(done + I.job * kBMaxPass + I.pass - 1, J.ntiles[I.pass - 1], ctl, timeout);
+        __syncthreads();
+        if (s_abort) return;
+      }
+      batch_tile<true>(J, I, prec, blds);
+      if (I.pass < J.npass - 1) {  // a later pass of the job reads this tile
+        __builtin_amdgcn_s_waitcnt(0);  // this thread's stores acknowledged
+        __syncthreads();
+        if (threadIdx.x == 0)
+          __hip_atomic_fetch_add(done + I.job * kBMaxPass + I.pass, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      }
     }
-    for (int q = q0; q < d.r; q += 4) {
-      const int kk = min(4, d.r - q);
-      if (kk == 4) run_group<2, false, float, 4>(blds, d, q);
-      else if (kk == 3) run_group<2, false, float, 3>(blds, d, q);
-      else if (kk == 2) run_group<2, false, float, 2>(blds, d, q);
-      else run_group<2, false, float, 1>(blds, d, q);
-      __syncthreads();
-    }
-    const float sc = (ps == J.npass - 1) ? J.scale : 1.0f;
-    const gptr<float> dst = to_global(J.out + base);
-    for (int e = threadIdx.x; e < d.E; e += blockDim.x) {
-      const int c = e & (d.w - 1), i = e >> d.wdig;
-      dst[c + (int64_t)i * d.sd0] = blds[pad(e)] * sc;
-    }
-    __syncthreads();
   }
 }
 
@@ -156,6 +267,12 @@ struct fdwt_batch {
   int level_begin[fdwt::kBMaxPass + 1] = {0};  // items of level k: [begin[k], begin[k+1])
   int n_levels = 0;
   int grid_per_level[fdwt::kBMaxPass] = {0};
+  // one-launch path: control block, per-job pass counters, grid, wait limit
+  bool one_launch = false;
+  fdwt::BCtl* d_ctl = nullptr;
+  int* d_done = nullptr;
+  int n_items = 0, one_grid = 0;
+  uint64_t timeout_ticks = 0;
   // grouped path: one entry per distinct m
   struct Group {
     int m = 0, emax = 14, njobs = 0;
@@ -200,6 +317,31 @@ static int batch_plan_job(int m, BJob& J) {
   return 0;
 }
 
+// Work items of the generic and one-launch paths: level k holds every tile
+// of pass k of every job, jobs largest first (stable), tiles in order;
+// level_begin[k] is the first item of level k (maxpass + 1 entries).
+static int build_items(const std::vector<int>& ms, std::vector<BJob>& hj, std::vector<BItem>& hi,
+                       int* level_begin, int& maxpass) {
+  hj.assign(ms.size(), BJob{});
+  hi.clear();
+  maxpass = 0;
+  for (size_t i = 0; i < ms.size(); ++i) {
+    if (batch_plan_job(ms[i], hj[i])) return -1;
+    maxpass = std::max(maxpass, hj[i].npass);
+  }
+  std::vector<int> order(hj.size());
+  for (size_t j = 0; j < hj.size(); ++j) order[j] = (int)j;
+  std::stable_sort(order.begin(), order.end(), [&](int x, int y) { return hj[x].m > hj[y].m; });
+  for (int ps = 0; ps < maxpass; ++ps) {
+    level_begin[ps] = (int)hi.size();
+    for (int j : order)
+      if (ps < hj[j].npass)
+        for (int t = 0; t < hj[j].ntiles[ps]; ++t) hi.push_back({j, ps, t, 0});
+  }
+  level_begin[maxpass] = (int)hi.size();
+  return 0;
+}
+
 }  // namespace fdwt
 
 using namespace fdwt;
@@ -235,7 +377,8 @@ extern "C" {
 int fdwt_batch_create(int n_jobs, const fdwt_batch_job* jobs, int precision, fdwt_batch** out) {
   if (!out || !jobs || n_jobs < 1 || n_jobs > (1 << 20)) return fail(FDWT_EINVAL, "bad batch arguments");
   *out = nullptr;
-  if (precision != FDWT_PREC_F32 && precision != FDWT_PREC_BF16X2 && precision != FDWT_PREC_F32_GENERIC)
+  if (precision != FDWT_PREC_F32 && precision != FDWT_PREC_BF16X2 && precision != FDWT_PREC_F32_GENERIC &&
+      precision != FDWT_PREC_F32_ONE_LAUNCH)
     return fail(FDWT_EINVAL, "unknown precision");
   for (int j = 0; j < n_jobs; ++j) {
     if (jobs[j].m < 1 || jobs[j].m > kMaxLog2N) return fail(FDWT_EINVAL, "job m must be in 1..26");
@@ -283,31 +426,19 @@ int fdwt_batch_create(int n_jobs, const fdwt_batch_job* jobs, int precision, fdw
       return bail(FDWT_EDEVICE, "batch upload failed");
   }
   if (!generic.empty()) {
-    std::vector<BJob> hj(generic.size());
+    std::vector<BJob> hj;
     std::vector<BItem> hi;
+    std::vector<int> ms;
+    for (int j : generic) ms.push_back(jobs[j].m);
     int maxpass = 0;
+    if (build_items(ms, hj, hi, b->level_begin, maxpass)) return bail(FDWT_EUNSUPPORTED, "job needs too many passes");
     for (size_t i = 0; i < generic.size(); ++i) {
-      const fdwt_batch_job& u = jobs[generic[i]];
-      BJob& J = hj[i];
-      std::memset(&J, 0, sizeof(J));
-      if (batch_plan_job(u.m, J)) return bail(FDWT_EUNSUPPORTED, "job needs too many passes");
-      J.in = u.in_dev;
-      J.out = u.out_dev;
-      maxpass = std::max(maxpass, J.npass);
+      hj[i].in = jobs[generic[i]].in_dev;
+      hj[i].out = jobs[generic[i]].out_dev;
     }
-    // Level k: every tile of pass k of every job (largest jobs first).
-    std::vector<int> order(hj.size());
-    for (size_t j = 0; j < hj.size(); ++j) order[j] = (int)j;
-    std::stable_sort(order.begin(), order.end(), [&](int x, int y) { return hj[x].m > hj[y].m; });
-    for (int ps = 0; ps < maxpass; ++ps) {
-      b->level_begin[ps] = (int)hi.size();
-      for (int j : order)
-        if (ps < hj[j].npass)
-          for (int t = 0; t < hj[j].ntiles[ps]; ++t) hi.push_back({j, ps, t, 0});
-    }
-    b->level_begin[maxpass] = (int)hi.size();
     b->n_levels = maxpass;
-    if (hi.size() > (size_t)INT32_MAX) return bail(FDWT_EINVAL, "batch too large");
+    b->n_items = (int)hi.size();
+    if (hi.size() > (size_t)(INT32_MAX - kBChunk)) return bail(FDWT_EINVAL, "batch too large");
     if (hipMalloc(&b->d_jobs, hj.size() * sizeof(BJob)) != hipSuccess ||
         hipMalloc(&b->d_items, hi.size() * sizeof(BItem)) != hipSuccess)
       return bail(FDWT_ENOMEM, "batch allocation failed");
@@ -322,6 +453,23 @@ int fdwt_batch_create(int n_jobs, const fdwt_batch_job* jobs, int precision, fdw
     for (int k = 0; k < maxpass; ++k)
       b->grid_per_level[k] =
           std::max(1, std::min(b->level_begin[k + 1] - b->level_begin[k], std::max(1, per_cu) * cus));
+    if (precision == FDWT_PREC_F32_ONE_LAUNCH) {
+      b->one_launch = true;
+      if (hipMalloc((void**)&b->d_ctl, sizeof(BCtl)) != hipSuccess ||
+          hipMalloc((void**)&b->d_done, hj.size() * kBMaxPass * sizeof(int)) != hipSuccess)
+        return bail(FDWT_ENOMEM, "batch allocation failed");
+      int occ = 0;
+      if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, (const void*)k_batch_one, kBThreads, generic_lds()) !=
+          hipSuccess)
+        return bail(FDWT_EDEVICE, "occupancy query failed");
+      const int tickets = (b->n_items + kBChunk - 1) / kBChunk;
+      b->one_grid = std::max(1, std::min(tickets, std::max(1, occ) * cus));
+      // Wait limit: 2 s of the device wall clock (kHz rate reported by HIP).
+      int khz = 0;
+      if (hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, b->device) != hipSuccess || khz <= 0)
+        khz = 100000;
+      b->timeout_ticks = (uint64_t)khz * 2000;
+    }
   }
   *out = b;
   return FDWT_OK;
@@ -333,11 +481,19 @@ int fdwt_batch_run(fdwt_batch* b, void* stream) {
   hipEvent_t tb = timed_begin(st);
   for (const auto& g : b->groups)
     if (int rc = run_group(g, st)) return rc;
-  for (int k = 0; k < b->n_levels; ++k) {
-    const int n = b->level_begin[k + 1] - b->level_begin[k];
-    hipLaunchKernelGGL(k_batch_fwd, dim3(b->grid_per_level[k]), dim3(kBThreads), generic_lds(), st, b->d_jobs,
-                       b->d_items + b->level_begin[k], n, b->prec);
+  if (b->one_launch) {
+    const int nc = b->n_jobs * kBMaxPass;
+    hipLaunchKernelGGL(k_batch_reset, dim3((nc + 255) / 256), dim3(256), 0, st, b->d_ctl, b->d_done, nc);
+    hipLaunchKernelGGL(k_batch_one, dim3(b->one_grid), dim3(kBThreads), generic_lds(), st, b->d_jobs, b->d_items,
+                       b->n_items, FDWT_PREC_F32, b->d_ctl, b->d_done, b->timeout_ticks);
     FDWT_HIP(hipGetLastError());
+  } else {
+    for (int k = 0; k < b->n_levels; ++k) {
+      const int n = b->level_begin[k + 1] - b->level_begin[k];
+      hipLaunchKernelGGL(k_batch_fwd, dim3(b->grid_per_level[k]), dim3(kBThreads), generic_lds(), st, b->d_jobs,
+                         b->d_items + b->level_begin[k], n, b->prec);
+      FDWT_HIP(hipGetLastError());
+    }
   }
   timed_end(tb, st, FDWT_TC_BATCH, b->alg_bytes);
   return FDWT_OK;
@@ -408,16 +564,44 @@ int fdwt_batch_describe(const fdwt_batch* b, int cap, int* m, int* emax, int* nj
 int fdwt_batch_check(fdwt_batch* b, void* stream) {
   if (!b) return fail(FDWT_EINVAL, "NULL batch");
   FDWT_HIP(hipStreamSynchronize((hipStream_t)stream));
+  if (b->one_launch) {
+    BCtl c{};
+    FDWT_HIP(hipMemcpy(&c, b->d_ctl, sizeof(c), hipMemcpyDeviceToHost));
+    if (c.error) return fail(FDWT_ETIMEOUT, "a wait of the one-launch batch gave up (outputs incomplete)");
+  }
+  return FDWT_OK;
+}
+
+int fdwt_batch_schedule(int n_jobs, const int* m, int cap, int* job, int* pass, int* tile, int* need, int* n_items,
+                        int* chunk) {
+  if (n_jobs < 1 || n_jobs > (1 << 20) || !m || !n_items || cap < 0) return fail(FDWT_EINVAL, "bad schedule arguments");
+  std::vector<int> ms(m, m + n_jobs);
+  for (int v : ms)
+    if (v < 1 || v > kMaxLog2N) return fail(FDWT_EINVAL, "job m must be in 1..26");
+  std::vector<BJob> hj;
+  std::vector<BItem> hi;
+  int lb[kBMaxPass + 1] = {0}, maxpass = 0;
+  if (build_items(ms, hj, hi, lb, maxpass)) return fail(FDWT_EUNSUPPORTED, "job needs too many passes");
+  *n_items = (int)hi.size();
+  if (chunk) *chunk = kBChunk;
+  for (int i = 0; i < cap && i < (int)hi.size(); ++i) {
+    if (job) job[i] = hi[i].job;
+    if (pass) pass[i] = hi[i].pass;
+    if (tile) tile[i] = hi[i].tile;
+    if (need) need[i] = hi[i].pass > 0 ? hj[hi[i].job].ntiles[hi[i].pass - 1] : 0;
+  }
   return FDWT_OK;
 }
 
 void fdwt_batch_free(fdwt_batch* b) {
   if (!b) return;
-  bool any = b->d_jobs || b->d_items;
+  bool any = b->d_jobs || b->d_items || b->d_ctl || b->d_done;
   for (auto& g : b->groups) any |= g.d_in || g.d_out;
   if (any) (void)hipDeviceSynchronize();
   if (b->d_jobs) (void)hipFree(b->d_jobs);
   if (b->d_items) (void)hipFree(b->d_items);
+  if (b->d_ctl) (void)hipFree(b->d_ctl);
+  if (b->d_done) (void)hipFree(b->d_done);
   for (auto& g : b->groups) {
     if (g.d_in) (void)hipFree(g.d_in);
     if (g.d_out) (void)hipFree(g.d_out);

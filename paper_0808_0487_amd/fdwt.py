@@ -13,7 +13,7 @@ import numpy as np
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libfdwt.so")
 
-OK, EINVAL, ENOMEM, EDEVICE, EBUDGET, EUNSUPPORTED = 0, -1, -2, -3, -4, -5
+OK, EINVAL, ENOMEM, EDEVICE, EBUDGET, EUNSUPPORTED, ETIMEOUT = 0, -1, -2, -3, -4, -5, -6
 F32, I32, CF32, F64, CF64 = 1, 2, 3, 4, 5
 FAMILY = {"product": 1, "exp": 2, "wangfang": 3, "asian": 4}
 
@@ -88,6 +88,7 @@ SIGNATURES = {
     "fdwt_batch_autotune": (_i, [_vp, _i, _vp]),
     "fdwt_batch_describe": (_i, [_vp, _i, _vp, _vp, _vp, ctypes.POINTER(_i)]),
     "fdwt_batch_free": (None, [_vp]),
+    "fdwt_batch_schedule": (_i, [_i, _vp, _i, _vp, _vp, _vp, _vp, ctypes.POINTER(_i), ctypes.POINTER(_i)]),
     "fdwt_server_request_bytes": (_i, [ctypes.POINTER(RequestC), ctypes.c_size_t,
                                        ctypes.POINTER(ctypes.c_size_t), ctypes.POINTER(ctypes.c_size_t)]),
     "fdwt_server_create": (_i, [ctypes.POINTER(ServerConfigC), ctypes.POINTER(_vp)]),
@@ -184,13 +185,28 @@ class BatchJobC(ctypes.Structure):
     _fields_ = [("m", ctypes.c_int), ("in_dev", ctypes.c_void_p), ("out_dev", ctypes.c_void_p)]
 
 
-PREC = {"f32": 0, "bf16x2": 1, "f32_generic": 2}
+PREC = {"f32": 0, "bf16x2": 1, "f32_generic": 2, "f32_one_launch": 3}
+
+
+def batch_schedule(ms):
+    """Work items of the one-launch batch for jobs of sizes ms, in ticket
+    order (fdwt_batch_schedule, host only): arrays job, pass, tile, need and
+    the items per ticket."""
+    ms = np.ascontiguousarray(ms, dtype=np.int32)
+    n, chunk = ctypes.c_int(), ctypes.c_int()
+    _check(lib().fdwt_batch_schedule(len(ms), ms.ctypes.data, 0, None, None, None, None, ctypes.byref(n),
+                                     ctypes.byref(chunk)))
+    out = [np.zeros(max(n.value, 1), dtype=np.int32) for _ in range(4)]
+    _check(lib().fdwt_batch_schedule(len(ms), ms.ctypes.data, n.value, *[o.ctypes.data for o in out],
+                                     ctypes.byref(n), ctypes.byref(chunk)))
+    return tuple(o[:n.value] for o in out) + (chunk.value,)
 
 
 class Batch:
     """A ragged batch of p = 2 forward transforms (fdwt_batch_*).
     jobs: list of (m, in_tensor, out_tensor); precision 'f32' (grouped static
-    passes), 'f32_generic' or 'bf16x2' (persistent launch per pass level)."""
+    passes), 'f32_generic' or 'bf16x2' (persistent launch per pass level) or
+    'f32_one_launch' (every pass of every job in one persistent launch)."""
 
     def __init__(self, jobs, precision="f32"):
         arr = (BatchJobC * len(jobs))()

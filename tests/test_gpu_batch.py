@@ -1,6 +1,7 @@
-"""Ragged batches of p = 2 transforms (grouped static passes, and the generic
-persistent launch per pass level with float32 or bfloat16-split low stages),
-against the oracle, alone vs in the mix, tuned, and under HIP-graph capture."""
+"""Ragged batches of p = 2 transforms (grouped static passes, the generic
+persistent launch per pass level with float32 or bfloat16-split low stages,
+and every pass of every job in one persistent launch), against the oracle,
+alone vs in the mix, tuned, and under HIP-graph capture."""
 import numpy as np
 import pytest
 import torch
@@ -31,7 +32,7 @@ def check_against_oracle(jobs, tol, seed):
 MS = [7, 9, 12, 13, 14, 15, 17, 20, 22, 8, 16, 19, 21, 13, 10, 3, 1, 6, 23]
 
 
-@pytest.mark.parametrize("prec,tol", [("f32", 1e-5), ("f32_generic", 1e-5), ("bf16x2", 2e-5)])
+@pytest.mark.parametrize("prec,tol", [("f32", 1e-5), ("f32_generic", 1e-5), ("bf16x2", 2e-5), ("f32_one_launch", 1e-5)])
 def test_ragged_batch_against_oracle(prec, tol):
     announce("batch", prec)
     jobs = make_jobs(MS, 500)
@@ -40,6 +41,56 @@ def test_ragged_batch_against_oracle(prec, tol):
     b.check()
     check_against_oracle(jobs, tol, 500)
     b.close()
+
+
+def test_one_launch_equals_level_launches_bit_identical():
+    """Every pass of every job in one launch (ticket order, per-job pass
+    counters) gives the level launches' results bit for bit (same tile code),
+    on consecutive runs (counters reset per run), with jobs in place too."""
+    announce("batch one launch")
+    ms = MS + [18, 18, 11]
+    jobs = make_jobs(ms, 1000)
+    ref = [(m, x, torch.empty_like(x)) for m, x, _ in jobs]
+    fdwt.Batch(ref, "f32_generic").run()
+    b = fdwt.Batch(jobs, "f32_one_launch")
+    for rep in range(3):
+        for _, _, y in jobs:
+            y.fill_(float(rep))
+        b.run()
+        b.check()
+        for i, ((_, _, y), (_, _, r)) in enumerate(zip(jobs, ref)):
+            assert torch.equal(y, r), (rep, i)
+    b.close()
+    inplace = [(m, x.clone(), None) for m, x, _ in jobs[:4]]
+    ip = fdwt.Batch([(m, x, x) for m, x, _ in inplace], "f32_one_launch")
+    ip.run()
+    ip.check()
+    for (m, x, _), (_, _, r) in zip(inplace, ref[:4]):
+        assert torch.equal(x, r), m
+    ip.close()
+
+
+def test_one_launch_graph_replays_match_eager():
+    announce("batch one launch graph")
+    jobs = make_jobs([12, 16, 19, 9], 1100)
+    b = fdwt.Batch(jobs, "f32_one_launch")
+    b.run()
+    b.check()
+    eager = [y.clone() for _, _, y in jobs]
+    s = torch.cuda.Stream()
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g, stream=s):
+        b.run(stream=s)
+    for rep in range(3):
+        for _, _, y in jobs:
+            y.fill_(float(rep + 1))
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        b.check()
+        for e, (_, _, y) in zip(eager, jobs):
+            assert torch.equal(e, y), rep
 
 
 def test_bf16_split_error_is_reported_scale():
