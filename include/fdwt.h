@@ -314,7 +314,10 @@ int fdwt_kernel_tune(const fdwt_net* net, const float* f2_dev, const double* sta
  *                          tickets, which running workgroups hold, so the
  *                          launch completes whatever the number of resident
  *                          workgroups.  Waits give up after 2 s of device
- *                          time; fdwt_batch_check then returns FDWT_ETIMEOUT
+ *                          time (the environment variable FDWT_BATCH_WAIT_MS,
+ *                          read at creation, sets another limit; 0 makes
+ *                          every wait give up, for tests of this path);
+ *                          fdwt_batch_check then returns FDWT_ETIMEOUT
  *                          (outputs incomplete).
  * Jobs with m < 7 always take the generic path (with FDWT_PREC_F32).
  * Except in FDWT_PREC_F32_ONE_LAUNCH no workgroup waits on another (the

@@ -211,7 +211,13 @@ __global__ void k_batch_reset(BCtl* ctl, int* done, int n) {
 
 // Thread 0 of a workgroup: spin until *cnt >= need; 1 if it gave up (after
 // `timeout` wall-clock ticks, or 2^26 polls, whichever comes first).
+// timeout 0 gives up at every wait (the host's test setting for the
+// failure path).
 __device__ int wait_count(int* cnt, int need, BCtl* ctl, uint64_t timeout) {
+  if (timeout == 0) {
+    __hip_atomic_store(&ctl->error, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    return 1;
+  }
   if (__hip_atomic_load(cnt, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) >= need) return 0;
   const uint64_t t0 = wall_clock64();
   for (int polls = 0;; ++polls) {
@@ -464,11 +470,14 @@ int fdwt_batch_create(int n_jobs, const fdwt_batch_job* jobs, int precision, fdw
         return bail(FDWT_EDEVICE, "occupancy query failed");
       const int tickets = (b->n_items + kBChunk - 1) / kBChunk;
       b->one_grid = std::max(1, std::min(tickets, std::max(1, occ) * cus));
-      // Wait limit: 2 s of the device wall clock (kHz rate reported by HIP).
+      // Wait limit: FDWT_BATCH_WAIT_MS (default 2000) of the device wall clock
+      // (kHz rate reported by HIP); 0 makes every wait give up (tests).
       int khz = 0;
       if (hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, b->device) != hipSuccess || khz <= 0)
         khz = 100000;
-      b->timeout_ticks = (uint64_t)khz * 2000;
+      const char* e = getenv("FDWT_BATCH_WAIT_MS");
+      const long ms = e ? std::max(0L, std::min(60000L, atol(e))) : 2000L;
+      b->timeout_ticks = (uint64_t)khz * (uint64_t)ms;
     }
   }
   *out = b;

@@ -70,6 +70,43 @@ def test_one_launch_equals_level_launches_bit_identical():
     ip.close()
 
 
+def test_one_launch_at_the_largest_sizes():
+    """Jobs of 2^24..2^26 points (three passes: waits on the first and the
+    second pass) beside tiny ones, bit-identical to the level launches."""
+    announce("batch one launch max sizes")
+    ms = [26, 1, 25, 2, 24, 13]
+    jobs = make_jobs(ms, 1200)
+    ref = [(m, x, torch.empty_like(x)) for m, x, _ in jobs]
+    fdwt.Batch(ref, "f32_generic").run()
+    b = fdwt.Batch(jobs, "f32_one_launch")
+    b.run()
+    b.check()
+    for (m, _, y), (_, _, r) in zip(jobs, ref):
+        assert torch.equal(y, r), m
+    b.close()
+
+
+def test_one_launch_wait_failure_is_reported(monkeypatch):
+    """With the wait limit set to zero on the host every dependency wait gives
+    up: each workgroup leaves the launch, the launch ends, and check reports
+    FDWT_ETIMEOUT; a batch created without the setting then runs normally."""
+    announce("batch one launch forced give-up")
+    jobs = make_jobs([18, 20, 12], 1300)
+    monkeypatch.setenv("FDWT_BATCH_WAIT_MS", "0")
+    b = fdwt.Batch(jobs, "f32_one_launch")
+    monkeypatch.delenv("FDWT_BATCH_WAIT_MS")
+    b.run()
+    with pytest.raises(fdwt.FdwtError) as ei:
+        b.check()
+    assert ei.value.code == fdwt.ETIMEOUT
+    b.close()
+    ok = fdwt.Batch(jobs, "f32_one_launch")
+    ok.run()
+    ok.check()
+    check_against_oracle(jobs, 1e-5, 1300)
+    ok.close()
+
+
 def test_one_launch_graph_replays_match_eager():
     announce("batch one launch graph")
     jobs = make_jobs([12, 16, 19, 9], 1100)
