@@ -75,9 +75,9 @@ def parse():
 # Source files of each kernel class (a class's committed traffic figure is
 # valid only while these files are unchanged).
 CLASS_SOURCES = {
-    "pass_f32": ["fwt.hip", "pass_core.h", "dev_math.h"],
+    "pass_f32": ["fwt.hip", "p2_stages.h", "pass_core.h", "dev_math.h"],
     "pass_cf32": ["fwt.hip", "pass_core.h", "dev_math.h"],
-    "pass_f64": ["fwt.hip", "pass_core.h", "dev_math.h"],
+    "pass_f64": ["fwt.hip", "p2_stages.h", "pass_core.h", "dev_math.h"],
     "kcols": ["spline.hip", "coords.h", "dev_math.h"],
     "eval": ["spline.hip", "coords.h", "dev_math.h"],
     "sample": ["net.hip", "coords.h", "dev_math.h"],

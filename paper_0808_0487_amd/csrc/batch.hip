@@ -35,6 +35,7 @@
 // entries exact in bfloat16 and float32 accumulation: one
 // v_mfma_f32_16x16x32_bf16 per 16 vectors of 16 points, A = [H16 | H16],
 // B = [hi ; lo].  All other stages stay in float32.
+#include "p2_stages.h"
 #include "pass_core.h"
 
 #include <algorithm>
@@ -168,6 +169,121 @@ __global__ void __launch_bounds__(kBThreads) k_batch_fwd(const BJob* __restrict_
   }
 }
 
+// ------------------------------------------ static tile of the one launch
+// A tile of 2^13 floats, rows of W = 2^WDIG contiguous elements (WDIG 0 for
+// a contiguous first pass; 13 - WDIG digits transformed), 512 threads with
+// 16 elements each, all offsets compile-time strides from a per-thread base:
+//  1. element e = tid + 512 k: the stages of e bits [max(9, WDIG), 13) (the
+//     register index k) run in registers; with WDIG >= 9 that is every digit
+//     and the tile goes straight back to memory;
+//  2. for WDIG < 6, the stages of e bits [WDIG, 6) through LDS (register
+//     groups as fwt_p2);
+//  3. read back as e = lane + 64 k + 1024 w: the stages of e bits
+//     [max(6, WDIG), 9) in registers, then the store.
+// coh_in: the tile was written by an earlier pass of the launch, and is read
+// with device-coherent buffer loads (sc1: served at the point of coherence of
+// all XCDs); coh_out: a later pass reads it, and it is stored with
+// device-scope relaxed atomic stores.
+template <int WDIG>
+__device__ __noinline__ void tile13(const float* src, float* dst, uint32_t sd0, uint32_t nbytes, float sc, bool coh_in,
+                                       bool coh_out, float* lds) {
+  constexpr int TH = kBThreads, EPT = 16, W = 1 << WDIG;
+  static_assert(TH * EPT == 8192, "2^13-element tiles");
+  const int tid = threadIdx.x;
+  // load mapping e = tid + 512 k
+  // Offsets within a job's buffer fit in 32 bits (at most 2^26 elements).
+  auto off1 = [&](int k) -> uint32_t {
+    if constexpr (WDIG <= 9)
+      return (uint32_t)(tid & (W - 1)) + ((uint32_t)(tid >> WDIG) + (uint32_t)k * (TH >> WDIG)) * sd0;
+    else
+      return (uint32_t)tid + TH * (k & ((W / TH) - 1)) + (uint32_t)(k >> (WDIG - 9)) * sd0;
+  };
+  float v[EPT];
+  if (coh_in) {
+    const __amdgpu_buffer_rsrc_t r = __builtin_amdgcn_make_buffer_rsrc((void*)src, (short)0, (int)nbytes, 0x00020000);
+#pragma unroll
+    for (int k = 0; k < EPT; ++k)
+      v[k] = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, (int)(off1(k) * 4u), 0, 16));
+  } else {
+    const gptr<const float> g = to_global(src);
+#pragma unroll
+    for (int k = 0; k < EPT; ++k) v[k] = g[off1(k)];
+  }
+  reg_bfly_bits<(WDIG > 9 ? WDIG - 9 : 0), 4>(v);
+  if constexpr (WDIG >= 9) {
+    if (coh_out) {
+#pragma unroll
+      for (int k = 0; k < EPT; ++k)
+        __hip_atomic_store(to_global(dst) + off1(k), v[k] * sc, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    } else {
+#pragma unroll
+      for (int k = 0; k < EPT; ++k) to_global(dst)[off1(k)] = v[k] * sc;
+    }
+    (void)lds;
+  } else {
+    float* lrow = lds + cpad(tid);
+#pragma unroll
+    for (int k = 0; k < EPT; ++k) lrow[cpad(k * TH)] = v[k];
+    lds_barrier();
+    if constexpr (WDIG < 6) P2Groups<13, WDIG, 0, float, 4, 6 - WDIG>::run(lds, tid);
+    const int lane = tid & 63, wv = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const float* lrowS = lds + cpad(lane + 1024 * wv);
+    float y[EPT];
+#pragma unroll
+    for (int k = 0; k < EPT; ++k) y[k] = lrowS[66 * k];
+    reg_bfly_bits<(WDIG > 6 ? WDIG - 6 : 0), 3>(y);
+    // store mapping e = lane + 64 k + 1024 wv
+    auto off2 = [&](int k) -> uint32_t {
+      if constexpr (WDIG <= 6)
+        return (uint32_t)(lane & (W - 1)) +
+               ((uint32_t)(lane >> WDIG) + (uint32_t)wv * (1024 >> WDIG) + (uint32_t)k * (64 >> WDIG)) * sd0;
+      else
+        return (uint32_t)lane + 64 * (k & ((W >> 6) - 1)) +
+               ((uint32_t)(k >> (WDIG - 6)) + (uint32_t)wv * (1024 >> WDIG)) * sd0;
+    };
+    if (coh_out) {
+#pragma unroll
+      for (int k = 0; k < EPT; ++k)
+        __hip_atomic_store(to_global(dst) + off2(k), y[k] * sc, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    } else {
+#pragma unroll
+      for (int k = 0; k < EPT; ++k) to_global(dst)[off2(k)] = y[k] * sc;
+    }
+    lds_barrier();
+  }
+}
+
+// One item of the one launch: the job's pass geometry picks the tile.
+__device__ __forceinline__ void one_item(const BJob& J, const BItem I, float* blds) {
+  const int ps = I.pass;
+  if (J.m < 13) {
+    batch_tile<true>(J, I, FDWT_PREC_F32, blds);
+    return;
+  }
+  const int wd = J.wdig[ps], d0 = J.d0[ps];
+  const uint32_t sd0 = 1u << d0;
+  const int nlo = 1 << (d0 - wd);
+  const int lo = I.tile % nlo, hi = I.tile / nlo;
+  const int64_t base = ((int64_t)lo << wd) + ((int64_t)hi << (d0 + J.r[ps]));
+  const float* src = (ps == 0 ? J.in : J.out) + base;
+  float* dst = J.out + base;
+  const uint32_t nbytes = (uint32_t)((uint64_t(4) << J.m) - (uint64_t)base * 4);
+  const float sc = (ps == J.npass - 1) ? J.scale : 1.0f;
+  const bool ci = ps > 0, co = ps < J.npass - 1;
+  switch (wd) {
+    case 0: tile13<0>(src, dst, sd0, nbytes, sc, ci, co, blds); break;
+    case 4: tile13<4>(src, dst, sd0, nbytes, sc, ci, co, blds); break;
+    case 5: tile13<5>(src, dst, sd0, nbytes, sc, ci, co, blds); break;
+    case 6: tile13<6>(src, dst, sd0, nbytes, sc, ci, co, blds); break;
+    case 7: tile13<7>(src, dst, sd0, nbytes, sc, ci, co, blds); break;
+    case 8: tile13<8>(src, dst, sd0, nbytes, sc, ci, co, blds); break;
+    case 9: tile13<9>(src, dst, sd0, nbytes, sc, ci, co, blds); break;
+    case 10: tile13<10>(src, dst, sd0, nbytes, sc, ci, co, blds); break;
+    case 11: tile13<11>(src, dst, sd0, nbytes, sc, ci, co, blds); break;
+    case 12: tile13<12>(src, dst, sd0, nbytes, sc, ci, co, blds); break;
+  }
+}
+
 // ------------------------------------------------ one launch for the batch
 // FDWT_PREC_F32_ONE_LAUNCH runs every pass of every job in one persistent
 // launch.  Work items (job, pass, tile) are numbered level by level (every
@@ -251,7 +367,7 @@ __global__ void __launch_bounds__(kBThreads) k_batch_one(const BJob* __restrict_
         __syncthreads();
         if (s_abort) return;
       }
-      batch_tile<true>(J, I, prec, blds);
+      one_item(J, I, blds);
       if (I.pass < J.npass - 1) {  // a later pass of the job reads this tile
         __builtin_amdgcn_s_waitcnt(0);  // this thread's stores acknowledged
         __syncthreads();
@@ -323,16 +439,49 @@ static int batch_plan_job(int m, BJob& J) {
   return 0;
 }
 
+// Pass split of one job in the one-launch batch: m >= 13 gives tiles of
+// exactly 2^13 elements in every pass (tile13): a contiguous first pass of
+// 13 digits, then the other m - 13 digits split evenly into strided passes of
+// at most 9 digits, each over rows of 2^(13 - r) elements; m < 13 one
+// generic pass.
+static int batch_plan_one(int m, BJob& J) {
+  J.m = m;
+  J.d0[0] = 0;
+  J.wdig[0] = 0;
+  if (m < 13) {
+    J.npass = 1;
+    J.r[0] = m;
+    J.ntiles[0] = 1;
+  } else {
+    const int rem = m - 13, nstr = (rem + 8) / 9;
+    if (1 + nstr > kBMaxPass) return -1;
+    J.npass = 1 + nstr;
+    J.r[0] = 13;
+    int d = 13;
+    for (int i = 0; i < nstr; ++i) {
+      const int r = (rem - (d - 13) + (nstr - i) - 1) / (nstr - i);
+      J.d0[1 + i] = d;
+      J.r[1 + i] = r;
+      J.wdig[1 + i] = 13 - r;
+      d += r;
+    }
+    for (int k = 0; k < J.npass; ++k) J.ntiles[k] = (int)((int64_t(1) << m) >> 13);
+  }
+  J.scale = (float)std::ldexp(1.0, -m);
+  return 0;
+}
+
 // Work items of the generic and one-launch paths: level k holds every tile
 // of pass k of every job, jobs largest first (stable), tiles in order;
-// level_begin[k] is the first item of level k (maxpass + 1 entries).
+// level_begin[k] is the first item of level k (maxpass + 1 entries).  one:
+// the one-launch plan (batch_plan_one) instead of batch_plan_job.
 static int build_items(const std::vector<int>& ms, std::vector<BJob>& hj, std::vector<BItem>& hi,
-                       int* level_begin, int& maxpass) {
+                       int* level_begin, int& maxpass, bool one) {
   hj.assign(ms.size(), BJob{});
   hi.clear();
   maxpass = 0;
   for (size_t i = 0; i < ms.size(); ++i) {
-    if (batch_plan_job(ms[i], hj[i])) return -1;
+    if (one ? batch_plan_one(ms[i], hj[i]) : batch_plan_job(ms[i], hj[i])) return -1;
     maxpass = std::max(maxpass, hj[i].npass);
   }
   std::vector<int> order(hj.size());
@@ -437,7 +586,8 @@ int fdwt_batch_create(int n_jobs, const fdwt_batch_job* jobs, int precision, fdw
     std::vector<int> ms;
     for (int j : generic) ms.push_back(jobs[j].m);
     int maxpass = 0;
-    if (build_items(ms, hj, hi, b->level_begin, maxpass)) return bail(FDWT_EUNSUPPORTED, "job needs too many passes");
+    if (build_items(ms, hj, hi, b->level_begin, maxpass, precision == FDWT_PREC_F32_ONE_LAUNCH))
+      return bail(FDWT_EUNSUPPORTED, "job needs too many passes");
     for (size_t i = 0; i < generic.size(); ++i) {
       hj[i].in = jobs[generic[i]].in_dev;
       hj[i].out = jobs[generic[i]].out_dev;
@@ -590,7 +740,7 @@ int fdwt_batch_schedule(int n_jobs, const int* m, int cap, int* job, int* pass, 
   std::vector<BJob> hj;
   std::vector<BItem> hi;
   int lb[kBMaxPass + 1] = {0}, maxpass = 0;
-  if (build_items(ms, hj, hi, lb, maxpass)) return fail(FDWT_EUNSUPPORTED, "job needs too many passes");
+  if (build_items(ms, hj, hi, lb, maxpass, true)) return fail(FDWT_EUNSUPPORTED, "job needs too many passes");
   *n_items = (int)hi.size();
   if (chunk) *chunk = kBChunk;
   for (int i = 0; i < cap && i < (int)hi.size(); ++i) {

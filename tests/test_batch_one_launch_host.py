@@ -25,19 +25,36 @@ from paper_0808_0487_amd import fdwt
 KBLOGE, KBMAXPASS = 13, 3
 
 
+def plan_passes(m):
+    """Passes (d0, r, wdig) of a job in the one-launch batch (batch.hip,
+    batch_plan_one): m < 13 one pass; otherwise a contiguous first pass of 13
+    digits, then the other m - 13 digits split evenly into strided passes of
+    at most 9 digits over rows of 2^(13 - r) elements."""
+    if m < KBLOGE:
+        return [(0, m, 0)]
+    rem = m - KBLOGE
+    nstr = (rem + 8) // 9
+    out, d = [(0, KBLOGE, 0)], KBLOGE
+    for i in range(nstr):
+        r = (rem - (d - KBLOGE) + (nstr - i) - 1) // (nstr - i)
+        out.append((d, r, KBLOGE - r))
+        d += r
+    return out
+
+
 def plan_tiles(m):
-    """Tiles per pass of a job (batch.hip, batch_plan_job): a contiguous first
-    pass of at most 2^13 elements, then strided passes over rows of 16."""
-    emax, wd = KBLOGE, 4
-    if m <= emax:
-        return [1]
-    rem, cap = m - emax, emax - wd
-    nstr = (rem + cap - 1) // cap
-    rd = max((rem + nstr - 1) // nstr, 1)
-    first = m - nstr * rd
-    r = [first] + [rd] * nstr
-    w = [0] + [min(wd, first + i * rd) for i in range(nstr)]
-    return [2 ** m >> (r[k] + w[k]) for k in range(len(r))]
+    return [2 ** m >> (r + w) for d0, r, w in plan_passes(m)]
+
+
+@pytest.mark.parametrize("m", range(1, 27))
+def test_one_launch_plan_covers_the_digits_in_2_13_tiles(m):
+    done = 0
+    for d0, r, w in plan_passes(m):
+        assert d0 == done and w <= d0 and r >= 1
+        if m >= KBLOGE:
+            assert r + w == KBLOGE and (d0 == 0 or w >= 4)
+        done += r
+    assert done == m and len(plan_passes(m)) <= KBMAXPASS
 
 
 def ragged(n, lo, hi, seed):
