@@ -352,11 +352,12 @@ int fdwt_batch_autotune(fdwt_batch* batch, int reps, void* stream);
 int fdwt_batch_describe(const fdwt_batch* batch, int cap, int* m, int* emax, int* njobs, int* n_groups);
 void fdwt_batch_free(fdwt_batch* batch);
 
-/* The work items of FDWT_PREC_F32_ONE_LAUNCH (and of the level launches of
- * FDWT_PREC_F32_GENERIC) for jobs of sizes m[0..n_jobs) in ticket order,
- * computed on the host (no device is used): item i is tile tile[i] of pass
- * pass[i] of job job[i] (index into m), and need[i] is the number of tiles
- * of that job's pass pass[i] - 1 that must be done first (0 for pass 0).
+/* The work items of FDWT_PREC_F32_ONE_LAUNCH for jobs of sizes m[0..n_jobs)
+ * in ticket order, computed on the host (no device is used): item i is tile
+ * tile[i] of pass pass[i] of job job[i] (index into m), and need[i] is the
+ * number of tiles of that job's pass pass[i] - 1 that must be done first (0
+ * for pass 0).  Jobs with m >= 13 have tiles of 2^13 points in every pass
+ * (2^(m-13) per pass); smaller jobs one pass of one tile.
  * Writes the first min(cap, total) items into each non-NULL array, the total
  * into *n_items and the items per ticket into *chunk (if non-NULL). */
 int fdwt_batch_schedule(int n_jobs, const int* m, int cap, int* job, int* pass, int* tile, int* need, int* n_items,
