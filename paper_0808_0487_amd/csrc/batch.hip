@@ -295,10 +295,11 @@ __device__ __forceinline__ void one_item(const BJob& J, const BItem I, float* bl
 // ticket only while it runs and keeps running until its items are done);
 // by induction on the item number every wait ends, whatever the number of
 // workgroups resident at once.  Each XCD has its own L2, so data must not
-// pass between workgroups through it: tiles are loaded and stored with
-// device-scope accesses (relaxed atomics, which the hardware serves at the
-// point of coherence of all XCDs) where another pass of the launch reads or
-// wrote them, every thread waits for its stores to be acknowledged, and only
+// pass between workgroups through it: where another pass of the launch wrote
+// or reads a tile, it is loaded with device-coherent buffer loads and stored
+// with device-scope relaxed atomic stores (both served at the point of
+// coherence of all XCDs), every thread waits for its stores to be
+// acknowledged, and only
 // then, after a workgroup barrier, is the job's pass counter incremented
 // (device scope); a waiting workgroup polls the counter with device-scope
 // loads before it loads the tile.  A job's input is read only by its first
@@ -348,10 +349,11 @@ __device__ int wait_count(int* cnt, int need, BCtl* ctl, uint64_t timeout) {
 }
 
 __global__ void __launch_bounds__(kBThreads) k_batch_one(const BJob* __restrict__ jobs, const BItem* __restrict__ items,
-                                                       int n_items, int prec, BCtl* ctl, int* done, uint64_t timeout) {
+                                                       int n_items, BCtl* ctl, int* done, uint64_t timeout) {
   extern __shared__ __align__(16) float blds[];
   __shared__ int s_first, s_abort;
   for (;;) {
+    __syncthreads();  // every thread has read the previous ticket
     if (threadIdx.x == 0)
       s_first = __hip_atomic_fetch_add(&ctl->next, kBChunk, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     __syncthreads();
@@ -644,7 +646,7 @@ int fdwt_batch_run(fdwt_batch* b, void* stream) {
     const int nc = b->n_jobs * kBMaxPass;
     hipLaunchKernelGGL(k_batch_reset, dim3((nc + 255) / 256), dim3(256), 0, st, b->d_ctl, b->d_done, nc);
     hipLaunchKernelGGL(k_batch_one, dim3(b->one_grid), dim3(kBThreads), generic_lds(), st, b->d_jobs, b->d_items,
-                       b->n_items, FDWT_PREC_F32, b->d_ctl, b->d_done, b->timeout_ticks);
+                       b->n_items, b->d_ctl, b->d_done, b->timeout_ticks);
     FDWT_HIP(hipGetLastError());
   } else {
     for (int k = 0; k < b->n_levels; ++k) {
