@@ -218,6 +218,16 @@ int fdwt_walsh_interp(const fdwt_net* net, const fdwt_kernel* kern, const float*
                       float* c_dev, int64_t nq, const uint32_t* q_dev, float* sf_dev,
                       void* stream);
 
+/* As fdwt_walsh_interp, with the queries given as q_depth-digit integers
+ * (q = Q p^-q_depth, 1 <= q_depth <= D, every entry below p^q_depth; larger
+ * entries are outside [0, 1) and give undefined results); they are lifted
+ * on the device to D digits (Q p^(D - q_depth)), the same points.
+ * q_depth == D is fdwt_walsh_interp itself.  FDWT_EINVAL for a q_depth out
+ * of range. */
+int fdwt_walsh_interp_depth(const fdwt_net* net, const fdwt_kernel* kern, const float* f_dev,
+                            float* c_dev, int64_t nq, const uint32_t* q_dev, int q_depth,
+                            float* sf_dev, void* stream);
+
 /* ------------------------------------------------- effective dimension */
 
 /* ANOVA variances of the spline and effective dimensions (Section 4):

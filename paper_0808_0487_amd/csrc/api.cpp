@@ -557,6 +557,30 @@ int fdwt_spline_eval(const fdwt_net* h, const fdwt_kernel* kern, const float* c_
   FDWT_GUARD_END
 }
 
+int fdwt_walsh_interp_depth(const fdwt_net* h, const fdwt_kernel* kern, const float* f_dev, float* c_dev,
+                            int64_t nq, const uint32_t* q_dev, int q_depth, float* sf_dev, void* stream) {
+  FDWT_GUARD_BEGIN
+  if (int rc = check_net(h)) return rc;
+  const Net& net = h->n;
+  const int D = query_depth(net.p);
+  if (q_depth < 1 || q_depth > D) return fail(FDWT_EINVAL, "q_depth must be in 1.." + std::to_string(D));
+  if (nq < 0 || nq > (int64_t(1) << 28)) return fail(FDWT_EINVAL, "nq must be in 0..2^28");
+  if (q_depth == D || nq == 0) return fdwt_walsh_interp(h, kern, f_dev, c_dev, nq, q_dev, sf_dev, stream);
+  if (!q_dev) return fail(FDWT_EINVAL, "NULL query pointer");
+  DeviceGuard g(net.device);
+  hipStream_t st = (hipStream_t)stream;
+  uint32_t* ql = nullptr;
+  if (hipMallocAsync((void**)&ql, (size_t)nq * net.s * sizeof(uint32_t), st) != hipSuccess) {
+    (void)hipGetLastError();
+    return fail(FDWT_ENOMEM, "query allocation failed");
+  }
+  int rc = lift_queries(net, q_dev, nq, q_depth, ql, st);
+  if (!rc) rc = fdwt_walsh_interp(h, kern, f_dev, c_dev, nq, ql, sf_dev, stream);
+  (void)hipFreeAsync(ql, st);
+  return rc;
+  FDWT_GUARD_END
+}
+
 int fdwt_walsh_interp(const fdwt_net* h, const fdwt_kernel* kern, const float* f_dev, float* c_dev,
                       int64_t nq, const uint32_t* q_dev, float* sf_dev, void* stream) {
   FDWT_GUARD_BEGIN

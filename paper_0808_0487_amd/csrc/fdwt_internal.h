@@ -196,5 +196,7 @@ int kernel_tune_call(const Net& n2, const float* f2, const double start[3], int 
 double kprime(int p, double alpha, int i);
 double rprime(int p, double alpha, int i);
 int query_depth(int p);
+// Queries of q_depth digits lifted to the full depth (spline.hip).
+int lift_queries(const Net& net, const uint32_t* q, int64_t nq, int q_depth, uint32_t* out, hipStream_t st);
 
 }  // namespace fdwt

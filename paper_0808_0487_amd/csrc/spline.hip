@@ -940,6 +940,29 @@ int run_eff_dim(Net& net, Scratch& sc, const fdwt_kernel* kern, const void* ft, 
   return FDWT_OK;
 }
 
+// ------------------------------------------------------ query depth
+// Queries of q_depth digits, Q p^-q_depth, as queries of the full depth D:
+// Q p^(D - q_depth) (the same point; its digits past q_depth are zero).
+__global__ void __launch_bounds__(256) k_lift_queries(const uint32_t* __restrict__ q, int64_t n, uint32_t mul,
+                                                      uint32_t* __restrict__ out) {
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) out[i] = q[i] * mul;
+}
+
+int lift_queries(const Net& net, const uint32_t* q, int64_t nq, int q_depth, uint32_t* out, hipStream_t st) {
+  const int D = query_depth(net.p);
+  if (q_depth < 1 || q_depth > D) return fail(FDWT_EINVAL, "q_depth must be in 1.." + std::to_string(D));
+  uint32_t mul = 1;
+  for (int i = q_depth; i < D; ++i) mul *= (uint32_t)net.p;
+  const int64_t n = nq * net.s;
+  if (n > 0) {
+    const unsigned grid = (unsigned)std::min<int64_t>((n + 255) / 256, 4096);
+    hipLaunchKernelGGL(k_lift_queries, dim3(grid), dim3(256), 0, st, q, n, mul, out);
+    FDWT_HIP(hipGetLastError());
+  }
+  return FDWT_OK;
+}
+
 // ------------------------------------------------------- split cost
 int run_split_cost(Net& tr, Scratch& sc, const uint32_t* delta, const float* ft, const float* fval,
                    const fdwt_kernel* kern, float* sf_out, double* cost, hipStream_t st) {

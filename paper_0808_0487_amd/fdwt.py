@@ -78,6 +78,7 @@ SIGNATURES = {
     "fdwt_spline_coef": (_i, [_vp, ctypes.POINTER(KernelC), _i, _vp, _vp, _vp]),
     "fdwt_spline_eval": (_i, [_vp, ctypes.POINTER(KernelC), _vp, _i64, _vp, _vp, _vp]),
     "fdwt_walsh_interp": (_i, [_vp, ctypes.POINTER(KernelC), _vp, _vp, _i64, _vp, _vp, _vp]),
+    "fdwt_walsh_interp_depth": (_i, [_vp, ctypes.POINTER(KernelC), _vp, _vp, _i64, _vp, _i, _vp, _vp]),
     "fdwt_eff_dim": (_i, [_vp, ctypes.POINTER(KernelC), _i, _vp, ctypes.POINTER(EffDimC), _vp]),
     "fdwt_eff_dim_data": (_i, [_vp, ctypes.POINTER(KernelC), _vp, ctypes.POINTER(EffDimC), _vp]),
     "fdwt_split_cost": (_i, [_vp, _vp, _d, _d, _d, _vp, ctypes.POINTER(_d)]),
@@ -418,7 +419,9 @@ class Net:
         _check(lib().fdwt_spline_eval(self.h, kern.c, _ptr(c), nq, _ptr(q), _ptr(out), _stream(stream)))
         return out
 
-    def walsh_interp(self, kern, f, q=None, c_out=None, sf_out=None, stream=None):
+    def walsh_interp(self, kern, f, q=None, c_out=None, sf_out=None, stream=None, q_depth=None):
+        """Spline coefficients of f and Sf at the queries q (uint32/int32
+        [s][nq] digit integers of q_depth digits; None: the full depth D)."""
         import torch
         if c_out is None:
             c_out = torch.empty(self.N, dtype=torch.float32, device=f.device)
@@ -429,8 +432,13 @@ class Net:
         _need(c_out, "c_out", self.N, ("float32",), self.device)
         if nq:
             _need(sf_out, "sf_out", nq, ("float32",), self.device)
-        _check(lib().fdwt_walsh_interp(self.h, kern.c, _ptr(f), _ptr(c_out), nq, _ptr(q) if nq else None,
-                                       _ptr(sf_out) if nq else None, _stream(stream)))
+        if q_depth is None:
+            _check(lib().fdwt_walsh_interp(self.h, kern.c, _ptr(f), _ptr(c_out), nq, _ptr(q) if nq else None,
+                                           _ptr(sf_out) if nq else None, _stream(stream)))
+        else:
+            _check(lib().fdwt_walsh_interp_depth(self.h, kern.c, _ptr(f), _ptr(c_out), nq,
+                                                 _ptr(q) if nq else None, int(q_depth),
+                                                 _ptr(sf_out) if nq else None, _stream(stream)))
         return c_out, sf_out
 
     # ------------------------------------------ kernel-parameter selection

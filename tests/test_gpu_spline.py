@@ -71,6 +71,32 @@ def test_interpolant_at_queries(p, m, s, seed):
     assert nrel(sf[-len(idx):], fo[idx]) <= 1e-5
 
 
+@pytest.mark.parametrize("p,m,s,qd,seed", [(2, 8, 4, 12, 31), (3, 5, 3, 7, 32), (5, 3, 3, 4, 33),
+                                         (2, 7, 3, 5, 34), (3, 4, 2, 20, 35)])
+def test_interpolant_at_queries_of_given_depth(p, m, s, qd, seed):
+    """fdwt_walsh_interp_depth: queries of qd digits, Q p^-qd, against the
+    oracle's direct sum (at depth qd when qd >= m, and at the full depth D
+    on the same points), and bit for bit the full-depth call on the queries
+    lifted by p^(D - qd); a depth beyond D is refused."""
+    announce("spline eval at depth", p, m, s, qd)
+    C, X, gam, fo, net, kern, f = setup_case(p, m, s, seed)
+    D = inputs.QUERY_DEPTH[p]
+    Q = np.random.default_rng(seed).integers(0, p ** qd, size=(s, 200))
+    qdev = torch.from_numpy(Q.astype(np.uint32).view(np.int32)).cuda()
+    c, sf = net.walsh_interp(kern, f, qdev, q_depth=qd)
+    sf = sf.cpu().numpy().astype(np.float64)
+    co = kernel.spline_coef_dense(p, m, 2.0, gam, X, fo)
+    lifted = Q * p ** (D - qd)
+    assert nrel(sf, kernel.spline_eval(p, m, 2.0, gam, X, co, lifted, D)) <= 1e-5
+    if qd >= m:
+        assert nrel(sf, kernel.spline_eval(p, m, 2.0, gam, X, co, Q, qd)) <= 1e-5
+    full = torch.from_numpy(lifted.astype(np.uint32).view(np.int32)).cuda()
+    _, sf_full = net.walsh_interp(kern, f, full)
+    assert np.array_equal(sf, sf_full.cpu().numpy().astype(np.float64))
+    with pytest.raises(fdwt.FdwtError):
+        net.walsh_interp(kern, f, qdev, q_depth=D + 1)
+
+
 @pytest.mark.parametrize("p,m,s,seed", CASES + WIDE)
 def test_effective_dimension_variances(p, m, s, seed):
     """var_trc, var_sup (Section 4) against the direct double sums with the
