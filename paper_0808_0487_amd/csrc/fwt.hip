@@ -24,6 +24,17 @@
 
 namespace fdwt {
 
+// First logical block of workgroup hw.  Workgroups are dispatched round-robin
+// over the 8 XCDs (hw mod 8); XCD x gets the contiguous range of the
+// ceil((G - x) / 8) logical blocks starting at x floor(G/8) + min(x, G mod 8),
+// so neighbouring tiles (which share cache lines and DRAM pages) meet in the
+// same L2.  A bijection of [0, G) for any G, so a grid need not be a multiple
+// of 8 (3^14 points make 729 tiles: one round, not two).
+__device__ __forceinline__ int xcd_first(int hw, int G) {
+  const int x = hw & 7, q = G >> 3, r = G & 7;
+  return x * q + (x < r ? x : r) + (hw >> 3);
+}
+
 size_t kind_bytes(Kind k) {
   switch (k) {
     case K_F32: return 4;
@@ -75,7 +86,7 @@ __global__ void __launch_bounds__((PassShape<P, KMAX, sizeof(T)>::THREADS))
   // neighbouring tiles (which share cache lines and DRAM pages, and for the
   // grouped-sum epilogue the weights of a tile) meet in the same L2.
   const int hw = blockIdx.x;
-  int lb = d.xcd ? ((hw & 7) * (G >> 3) + (hw >> 3)) : hw;
+  int lb = d.xcd ? xcd_first(hw, G) : hw;
 
   auto locate = [&](int l, int& col, int& tile) {
     if (EPI == EPI_REDUCE) {
@@ -263,7 +274,7 @@ __global__ void __launch_bounds__((P3Shape<RD, KT>::TH)) fwt_p3s(const Tin* __re
   const int G = gridDim.x;
   const int nb = d.ntiles * d.batch;
   const int hw = blockIdx.x;
-  int lb = d.xcd ? ((hw & 7) * (G >> 3) + (hw >> 3)) : hw;
+  int lb = d.xcd ? xcd_first(hw, G) : hw;
   const int tid = threadIdx.x;
   // Global offset of element tid + k TH: goff0 + k gstep.
   const uint32_t sd0 = (uint32_t)d.sd0;
@@ -279,14 +290,17 @@ __global__ void __launch_bounds__((P3Shape<RD, KT>::TH)) fwt_p3s(const Tin* __re
     return (int64_t)lo * S::W + (int64_t)hi * d.shi;
   };
   Tin pre[EPT];
-  auto prefetch = [&](int l) {
+  // live false: every load reads the tile's first element (one cache line), a
+  // stand-in that keeps the loads unconditional when there is no next tile.
+  auto prefetch = [&](int l, bool live) {
     int col, tile;
     locate(l, col, tile);
-    const Tin* src = in + (int64_t)col * d.col_in + tile_base(tile) + goff0;
+    const Tin* src = in + (int64_t)col * d.col_in + tile_base(tile) + (live ? goff0 : 0u);
+    const uint32_t st = live ? gstep : 0u;
 #pragma unroll
-    for (int k = 0; k < EPT; ++k) pre[k] = src[k * gstep];
+    for (int k = 0; k < EPT; ++k) pre[k] = src[k * st];
   };
-  if (lb < nb) prefetch(lb);
+  if (lb < nb) prefetch(lb, true);
   for (; lb < nb; lb += G) {
     T v[EPT];
 #pragma unroll
@@ -297,14 +311,14 @@ __global__ void __launch_bounds__((P3Shape<RD, KT>::TH)) fwt_p3s(const Tin* __re
     Tout* dst = out + (int64_t)col * d.col_out + tile_base(tile) + goff0;
     if constexpr (RD == KT) {
       // The pass has no other digits: straight back to memory.
-      prefetch(lb + G < nb ? lb + G : lb);  // unconditional: exact wait counts
+      prefetch(lb + G < nb ? lb + G : lb, lb + G < nb);  // unconditional: exact wait counts
 #pragma unroll
       for (int k = 0; k < EPT; ++k) dst[k * gstep] = cvt_out<T, Tout>(v[k], d.scale, d.scale64);
     } else {
 #pragma unroll
       for (int k = 0; k < EPT; ++k) lds[tid + k * TH] = v[k];
       lds_barrier();
-      prefetch(lb + G < nb ? lb + G : lb);  // unconditional: exact wait counts
+      prefetch(lb + G < nb ? lb + G : lb, lb + G < nb);  // unconditional: exact wait counts
       P3Groups<RD, KT, 0, INV, T>::run(lds, tid);
 #pragma unroll
       for (int k = 0; k < EPT; ++k) dst[k * gstep] = cvt_out<T, Tout>(lds[tid + k * TH], d.scale, d.scale64);
@@ -326,7 +340,7 @@ __global__ void __launch_bounds__((P2Shape<LOGE, WDIG>::THREADS))
   const int G = gridDim.x;
   const int nb = d.ntiles * d.batch;
   const int hw = blockIdx.x;
-  int lb = d.xcd ? ((hw & 7) * (G >> 3) + (hw >> 3)) : hw;
+  int lb = d.xcd ? xcd_first(hw, G) : hw;
   const int tid = threadIdx.x;
   // Element e = tid + k*TH of a tile: row i = e >> WDIG, column e & (W-1);
   // global offset goff0 + k*gstep, LDS index pad(tid) + pad(k*TH).
@@ -534,7 +548,7 @@ __global__ void __launch_bounds__((P2Shape<LOGE, 0>::THREADS)) fwt_p2_gen(ColGen
   }
   __syncthreads();
   const int G = gridDim.x, hw = blockIdx.x;
-  int lb = d.xcd ? ((hw & 7) * (G >> 3) + (hw >> 3)) : hw;
+  int lb = d.xcd ? xcd_first(hw, G) : hw;
   double* lrow = lds + cpad(tid);
   double* lrowS = lds + cpad(lane + 1024 * wv);
   const uint32_t goffS = (uint32_t)(lane + 1024 * wv);
@@ -635,7 +649,7 @@ __global__ void __launch_bounds__((P2Shape<LOGE, 0>::THREADS)) fwt_p2_fam(FamGen
   float* lrowS = lds + cpad(lane + 1024 * wv);
   const uint32_t goffS = (uint32_t)(lane + 1024 * wv);
   const int G = gridDim.x, hw = blockIdx.x;
-  int lb = d.xcd ? ((hw & 7) * (G >> 3) + (hw >> 3)) : hw;
+  int lb = d.xcd ? xcd_first(hw, G) : hw;
   for (; lb < d.ntiles; lb += G) {
     const uint32_t n0 = (uint32_t)lb << LOGE;
     typename FamState<FAM>::T acc[EPT];
@@ -816,8 +830,7 @@ static int launch_pass(const void* in, void* out, const PassGeom& g, int m, int 
   FDWT_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, threads, lds));
   int64_t G = (int64_t)std::max(1, per_cu) * device_cus();
   if (G >= nb) G = nb;
-  if (G >= 64) G -= G % 8;
-  d.xcd = (G % 8 == 0 && G >= 64) ? 1 : 0;
+  d.xcd = G >= 64 ? 1 : 0;
   const double elems = (double)ipow(P, m) * batch;
   const double alg = red ? elems * sizeof(Tin) + (double)ipow(P, m) * sizeof(float2)
                          : elems * (sizeof(Tin) + sizeof(Tout));
@@ -1058,8 +1071,7 @@ static int launch_p3s(const void* in, void* out, const PassGeom& g, int m, int b
   if (int rc = allow_lds(fn, lds)) return rc;
   int64_t G = (int64_t)occupancy(fn, threads, lds) * device_cus();
   if (G >= nb) G = nb;
-  if (G >= 64) G -= G % 8;
-  d.xcd = (G % 8 == 0 && G >= 64) ? 1 : 0;
+  d.xcd = G >= 64 ? 1 : 0;
   const Tin* inp = (const Tin*)in;
   Tout* outp = (Tout*)out;
   void* args[] = {(void*)&inp, (void*)&outp, (void*)&d};
@@ -1154,8 +1166,7 @@ static int launch_p2(const void* in, void* out, const P2Pass& g, int m, int batc
   if (int rc = allow_lds(fn, lds)) return rc;
   int64_t G = (int64_t)occupancy(fn, threads, lds) * device_cus();
   if (G >= nb) G = nb;
-  if (G >= 64) G -= G % 8;
-  d.xcd = (G % 8 == 0 && G >= 64) ? 1 : 0;
+  d.xcd = G >= 64 ? 1 : 0;
   // Grouped sums over several columns: a workgroup keeps one tile's weights
   // for all its columns when the tiles split evenly over the grid.
   d.wkeep = (red && g.loge >= 10 && batch > 1 && ntiles % G == 0 && wkeep_enabled()) ? 1 : 0;
@@ -1346,8 +1357,7 @@ int fwt_p2_gen_first(int m, int s, const uint32_t* xtab, int nbytes, const doubl
   if (int rc = allow_lds(fn, lds)) return rc;
   int64_t G = (int64_t)occupancy(fn, threads, lds) * device_cus();
   if (G >= d.ntiles) G = d.ntiles;
-  if (G >= 64) G -= G % 8;
-  d.xcd = (G % 8 == 0 && G >= 64) ? 1 : 0;
+  d.xcd = G >= 64 ? 1 : 0;
   ColGen cg{xtab, tab, nbytes, s, m, ktab, kcol ? 0 : d0, kcol ? s : d1};
   void* args[] = {(void*)&cg, (void*)&out, (void*)&d};
   return launch_timed(fn, dim3((unsigned)G), dim3(threads), args, lds, st, FDWT_TC_PASS_F64,
@@ -1404,8 +1414,7 @@ int fwt_p2_forward_family(const Net& net, int family, const FamilyArgs& fa, floa
   if (int rc = allow_lds(fn, lds)) return rc;
   int64_t G = (int64_t)occupancy(fn, threads, lds) * device_cus();
   if (G >= d.ntiles) G = d.ntiles;
-  if (G >= 64) G -= G % 8;
-  d.xcd = (G % 8 == 0 && G >= 64) ? 1 : 0;
+  d.xcd = G >= 64 ? 1 : 0;
   FamGen fg{net.d_xtab, net.nbytes, net.m, fa};
   void* args[] = {(void*)&fg, (void*)&out, (void*)&d};
   if (int rc = launch_timed(fn, dim3((unsigned)G), dim3(threads), args, lds, st, FDWT_TC_SAMPLE, 4.0 * (double)N))
