@@ -147,6 +147,56 @@ def cpu_baseline(p, m, s, C, budget_s=12.0, net_sample=1 << 21):
                       "c1 leg" % (ns, N, t_net, done, t_coef, hi["usable_cores"], hi["cpu_model"])}
 
 
+def cpu_fast_reference(p, m, s, C, small_m=20):
+    """The fast CPU reference (oracle/fast: Algorithms 1 and 2 and the spectral
+    routes of Sections 3.2 and 4 as plain float64 loops in C, OpenMP) timed on
+    the headline step's work: the exponential family sampled at the net, its
+    forward transform, the forward transform of the integer data, the spline
+    coefficients (spectral solve + Algorithm 2) and the ANOVA variances at
+    every d (2s + 1 kernel columns and their transforms).  The net is built
+    once beforehand, as the device keeps it in its handle.  On all OpenMP
+    threads at the full size, and on one thread at m = small_m (one thread at
+    the full size would take about a minute); rates in points/s."""
+    from oracle import fast
+    from paper_0808_0487_amd import inputs
+    a = inputs.family_params("exp", s, ratio=0.1)
+    gam = inputs.kernel_weights(s)
+    fi = inputs.uniform_int32(p ** m, -1000, 1000, seed=3).astype(np.float64)
+
+    def step(mm, Cm, ints):
+        X = fast.net_int(p, mm, Cm)
+        t0 = time.perf_counter()
+        ft = fast.fwt(p, mm, fast.sample("exp", p, mm, a, X))
+        fast.fwt(p, mm, ints)
+        fast.spline_coef(p, mm, 2.0, gam, X, ft)
+        vt, vs = fast.variances(p, mm, 2.0, gam, X, ft)
+        return time.perf_counter() - t0, anova_dims(vt, vs)
+
+    nthreads = fast.threads()
+    t_all, dims = step(m, C, fi)
+    C_small = inputs.upper_triangular_generators(p, small_m, s, seed=2)
+    fast.set_threads(1)
+    try:
+        t_one, _ = step(small_m, C_small, fi[:p ** small_m].copy())
+    finally:
+        fast.set_threads(nthreads)
+    hi = host_info()
+    return {"all_threads": {"value": p ** m / t_all, "unit": "points/s", "cores": nthreads, "step_s": t_all,
+                            "m": m, "s": s, "d_trc_d_sup": dims},
+            "one_thread": {"value": p ** small_m / t_one, "unit": "points/s", "cores": 1, "step_s": t_one,
+                           "m": small_m, "s": s},
+            "kind": "fast CPU reference (float64, C + OpenMP)", "host": hi,
+            "sample": "the whole step (sampling, forward of the float and integer data, spline coefficients, "
+                      "variances at every d) at p=2 m=%d s=%d on %d threads, and at m=%d on one thread"
+                      % (m, s, nthreads, small_m)}
+
+
+def anova_dims(vt, vs):
+    from oracle import anova
+    d = anova.effective_dims(vt, vs)
+    return [int(d[0]), int(d[1])]
+
+
 def host_info():
     """CPU model and core counts of the machine the bench runs on."""
     model = ""
@@ -768,6 +818,8 @@ def main():
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(p, m, s, C)
         progress("cpu baseline done")
+        out["cpu_fast_reference"] = cpu_fast_reference(p, m, s, C)
+        progress("fast CPU reference done")
     print(json.dumps(out), flush=True)
     net.close()
 
