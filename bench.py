@@ -188,7 +188,90 @@ def cpu_fast_reference(p, m, s, C, small_m=20):
             "kind": "fast CPU reference (float64, C + OpenMP)", "host": hi,
             "sample": "the whole step (sampling, forward of the float and integer data, spline coefficients, "
                       "variances at every d) at p=2 m=%d s=%d on %d threads, and at m=%d on one thread"
-                      % (m, s, nthreads, small_m)}
+                      % (m, s, nthreads, small_m),
+            "configs": cpu_reference_configs(fi, nthreads)}
+
+
+def cpu_reference_configs(fi24, nthreads):
+    """The fast CPU reference on each configuration's own work, on all
+    OpenMP threads and on one thread (seconds; median of `reps` runs where
+    stated, else one run; extrapolations say what was sampled):
+      C1  p=2 m=10 s=4: forward, inverse, spline coefficients, variances
+      C2  p=2 m=24: forward of float data, forward of integer data
+      C3  p=3 m=14 s=10: forward + inverse; the interpolant at 65536 queries
+          (16 queries timed, scaled to 65536, plus the coefficients once)
+      C4  the 512-job batch (m 12..22): forward of every job; one thread on
+          every 8th job, scaled by sum N m."""
+    from oracle import fast
+    from paper_0808_0487_amd import inputs
+
+    def timed(fn, threads, reps=1):
+        fast.set_threads(threads)
+        try:
+            ts = []
+            for _ in range(reps):
+                t0 = time.perf_counter()
+                fn()
+                ts.append(time.perf_counter() - t0)
+        finally:
+            fast.set_threads(nthreads)
+        return float(np.median(ts))
+
+    out = {}
+    # C1
+    p, m, s = 2, 10, 4
+    C = inputs.upper_triangular_generators(p, m, s, seed=1)
+    X = fast.net_int(p, m, C)
+    f = fast.sample("product", p, m, inputs.family_params("product", s, const=0.5), X)
+    gam = inputs.kernel_weights(s)
+
+    def c1():
+        ft = fast.fwt(p, m, f)
+        fast.fwt(p, m, ft, inverse=True)
+        fast.spline_coef(p, m, 2.0, gam, X, ft)
+        fast.variances(p, m, 2.0, gam, X, ft)
+    out["C1_step"] = {"all_threads_s": timed(c1, nthreads, 10), "one_thread_s": timed(c1, 1, 10), "reps": 10}
+    # C2 transforms
+    f24 = fast.sample("exp", 2, 24, inputs.family_params("exp", 20, ratio=0.1),
+                      fast.net_int(2, 24, inputs.upper_triangular_generators(2, 24, 20, seed=2)))
+    out["C2_forward_f32"] = {"all_threads_s": timed(lambda: fast.fwt(2, 24, f24), nthreads, 3),
+                             "one_thread_s": timed(lambda: fast.fwt(2, 24, f24), 1)}
+    out["C2_forward_i32"] = {"all_threads_s": timed(lambda: fast.fwt(2, 24, fi24), nthreads, 3),
+                             "one_thread_s": timed(lambda: fast.fwt(2, 24, fi24), 1)}
+    del f24
+    # C3
+    p, m, s = 3, 14, 10
+    C = inputs.upper_triangular_generators(p, m, s, seed=3)
+    X = fast.net_int(p, m, C)
+    f = fast.sample("product", p, m, inputs.family_params("product", s, alpha=2.0), X)
+    gam = inputs.kernel_weights(s)
+
+    def c3():
+        fast.fwt(p, m, fast.fwt(p, m, f), inverse=True)
+    out["C3_forward_inverse"] = {"all_threads_s": timed(c3, nthreads, 3), "one_thread_s": timed(c3, 1)}
+    D = inputs.QUERY_DEPTH[p]
+    Q = inputs.queries(p, s, 16, 3).astype(np.int64)
+    t0 = time.perf_counter()
+    c = fast.spline_coef(p, m, 2.0, gam, X, fast.fwt(p, m, f))
+    t_coef = time.perf_counter() - t0
+    t_q = timed(lambda: fast.spline_eval(p, m, 2.0, gam, X, c, Q, D), nthreads)
+    out["C3_interp_65536_queries"] = {"all_threads_s": t_coef + t_q * 65536 / 16,
+                                      "sample": "coefficients once, 16 queries timed and scaled to 65536"}
+    # C4
+    specs = inputs.batch_jobs(512, seed=4)
+    xs = [inputs.uniform_float(2 ** mm, 7000 + i).astype(np.float64) for i, (mm, _, _, _) in enumerate(specs)]
+
+    def c4(sel):
+        for i in sel:
+            fast.fwt(2, specs[i][0], xs[i])
+    allj = range(len(specs))
+    some = range(0, len(specs), 8)
+    work = lambda sel: sum((2 ** specs[i][0]) * specs[i][0] for i in sel)
+    out["C4_batch_512_jobs"] = {"all_threads_s": timed(lambda: c4(allj), nthreads),
+                                "one_thread_s": timed(lambda: c4(some), 1) * work(allj) / work(some),
+                                "sample": "one thread: every 8th job, scaled by sum of N m"}
+    del xs
+    return out
 
 
 def anova_dims(vt, vs):
