@@ -131,10 +131,22 @@ def _check(rc):
         raise FdwtError(rc, lib().fdwt_last_error().decode())
 
 
+_RAW = None  # (current device, raw current stream of a device) readers, set on first use
+
+
 def _stream(stream):
-    import torch
+    """The HIP stream of a call: the given one (a torch stream or a raw
+    handle), else torch's current stream on the current device.  The raw
+    readers skip building a torch Stream object per call (a few
+    microseconds, which a call's first kernel would wait for)."""
+    global _RAW
     if stream is None:
-        return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+        if _RAW is None:
+            import torch
+            dev = getattr(torch._C, "_cuda_getDevice", None)
+            raw = getattr(torch._C, "_cuda_getCurrentRawStream", None)
+            _RAW = (dev, raw) if dev and raw else (lambda: 0, lambda d: torch.cuda.current_stream().cuda_stream)
+        return ctypes.c_void_p(_RAW[1](_RAW[0]()))
     return ctypes.c_void_p(stream.cuda_stream if hasattr(stream, "cuda_stream") else int(stream))
 
 
@@ -157,7 +169,7 @@ def _need(t, name, numel, dtypes, device=None):
     call has passed these checks)."""
     if t is None:
         raise ValueError("%s is required" % name)
-    dt = str(t.dtype).replace("torch.", "")
+    dt = _dtname(t.dtype)
     if dt not in dtypes:
         raise ValueError("%s must be %s, got %s" % (name, " or ".join(dtypes), dt))
     if t.numel() != numel:
@@ -176,10 +188,31 @@ def _need_params(a, n, name="a"):
     return a
 
 
+# Element types of dwt_inverse: (inputs, input -> outputs), for p odd and p = 2.
+_INV_TYPES = {True: (("float32", "int32", "float64"),
+                     {"float32": ("float32",), "int32": ("int32",), "float64": ("float64",)}),
+              False: (("complex64", "complex128"),
+                      {"complex64": ("complex64", "float32"), "complex128": ("complex128", "float64")})}
+
+_DT = None  # torch dtype -> (name, ABI element type), built on first use
+
+
+def _dtypes():
+    global _DT
+    if _DT is None:
+        import torch
+        _DT = {torch.float32: ("float32", F32), torch.int32: ("int32", I32), torch.complex64: ("complex64", CF32),
+               torch.float64: ("float64", F64), torch.complex128: ("complex128", CF64)}
+    return _DT
+
+
+def _dtname(dt):
+    e = _dtypes().get(dt)
+    return e[0] if e else str(dt).replace("torch.", "")
+
+
 def _type_of(t):
-    import torch
-    return {torch.float32: F32, torch.int32: I32, torch.complex64: CF32,
-            torch.float64: F64, torch.complex128: CF64}[t.dtype]
+    return _dtypes()[t.dtype][1]
 
 
 class BatchJobC(ctypes.Structure):
@@ -362,7 +395,7 @@ class Net:
             out = torch.empty(self.N, dtype=dt, device=x.device)
         ins = ("float32", "int32", "float64") if self.p == 2 else ("float32", "complex64", "float64", "complex128")
         _need(x, "x", self.N, ins, self.device)
-        _need(out, "out", self.N, (self._fwd_out_dtype(str(x.dtype).replace("torch.", "")),), self.device)
+        _need(out, "out", self.N, (self._fwd_out_dtype(_dtname(x.dtype)),), self.device)
         _check(lib().fdwt_dwt_forward(self.h, _type_of(x), _ptr(x), _type_of(out), _ptr(out), _stream(stream)))
         return out
 
@@ -388,14 +421,9 @@ class Net:
             elif real and x.dtype == torch.complex128:
                 dt = torch.float64
             out = torch.empty(self.N, dtype=dt, device=x.device)
-        if self.p == 2:
-            ins, outs = ("float32", "int32", "float64"), {"float32": ("float32",), "int32": ("int32",),
-                                                           "float64": ("float64",)}
-        else:
-            ins, outs = ("complex64", "complex128"), {"complex64": ("complex64", "float32"),
-                                                      "complex128": ("complex128", "float64")}
+        ins, outs = _INV_TYPES[self.p == 2]
         _need(x, "x", self.N, ins, self.device)
-        _need(out, "out", self.N, outs[str(x.dtype).replace("torch.", "")], self.device)
+        _need(out, "out", self.N, outs[_dtname(x.dtype)], self.device)
         _check(lib().fdwt_dwt_inverse(self.h, _type_of(x), _ptr(x), _type_of(out), _ptr(out), _stream(stream)))
         return out
 
