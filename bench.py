@@ -19,7 +19,10 @@ Prints one JSON line.  `value` is points per second through one step.  The
 (timed by the library's launch-timing hook: HIP events recorded on the
 stream each kernel is launched on, during the timed steps), with its
 algorithmic bytes per launch.  `cpu_baseline` times the oracle's direct
-definition on a bounded sample of coefficients.
+definition on a bounded sample of coefficients; inside it, the oracle's full
+definition of the small configuration (c1_full_definition) and the fast CPU
+reference on the step's and each configuration's own work (fast_reference).
+Only this leg imports the oracle.
 """
 import argparse
 import hashlib
@@ -109,7 +112,10 @@ def committed_traffic(cls, alg_per_launch):
     return float(m.group(1)) if m else None
 
 
-def cpu_baseline(p, m, s, C, budget_s=12.0, net_sample=1 << 21):
+C1_SHAPE = (2, 10, 4)  # p, m, s of the small configuration
+
+
+def cpu_baseline(p, m, s, C, c1_gpu_ms=None, budget_s=12.0, net_sample=1 << 21):
     """Oracle (direct definition, numpy, one thread) on a bounded sample of
     the step: the net and f at the first ``net_sample`` indices (the per-point
     cost is the same for every index), then as many coefficients of the
@@ -138,13 +144,18 @@ def cpu_baseline(p, m, s, C, budget_s=12.0, net_sample=1 << 21):
         t_coef = (time.perf_counter() - t1) / done
     full = t_net + N * t_coef
     hi = host_info()
-    return {"value": N / full, "unit": "points/s", "cores": 1, "kind": "oracle",
+    res = {"value": N / full, "unit": "points/s", "cores": 1, "kind": "oracle",
             "host": hi,
             "sample": "oracle net+f at %d of %d points (extrapolated: %.1f s for all) and %d forward "
                       "coefficients by the direct O(N) sum (%.3f s each), numpy on one thread of a %d-core "
                       "host (%s), extrapolated to all N coefficients; spline and eff_dim (O(N^2) in the "
-                      "oracle) not included; the full oracle is timed at the small configuration in the "
-                      "c1 leg" % (ns, N, t_net, done, t_coef, hi["usable_cores"], hi["cpu_model"])}
+                      "oracle) not included; the full oracle is timed at the small configuration in "
+                      "c1_full_definition" % (ns, N, t_net, done, t_coef, hi["usable_cores"], hi["cpu_model"])}
+    # The oracle's full definition at the small configuration, and the fast
+    # CPU reference on the step's and each configuration's own work.
+    res["c1_full_definition"] = c1_oracle(c1_gpu_ms)
+    res["fast_reference"] = cpu_fast_reference(p, m, s, C)
+    return res
 
 
 def cpu_fast_reference(p, m, s, C, small_m=20):
@@ -299,17 +310,12 @@ def host_info():
 
 def c1_leg(torch, fdwt, inputs, reps=20):
     """The small configuration: p = 2, m = 10 (1024 points), s = 4, seeded
-    upper-triangular generators, f = prod_j (1 + 0.5 (x_j - 1/2)) (float64 on
-    the host, float32 on the device), kernel alpha = 2, gamma_j = j^-2.  The
-    whole step (forward and inverse transform, spline coefficients, effective
-    dimension) on the GPU, and the oracle's full definition of the same
-    outputs on the host (direct O(N^2) sums of the forward and inverse
-    transforms, dense Gram solve, direct double sums of the variances), both
-    timed in full."""
-    from threadpoolctl import threadpool_limits
-    from oracle import anova, families, kernel, net as onet, walsh
-    p, m, s = 2, 10, 4
-    N = p ** m
+    upper-triangular generators, f = prod_j (1 + 0.5 (x_j - 1/2)) sampled on
+    the device (float32), kernel alpha = 2, gamma_j = j^-2: the whole step
+    (forward and inverse transform, spline coefficients, effective dimension)
+    on the GPU, timed in full.  The oracle's full definition of the same
+    outputs is timed in the CPU baseline (c1_full_definition)."""
+    p, m, s = C1_SHAPE
     C = inputs.upper_triangular_generators(p, m, s, seed=1)
     a = inputs.family_params("product", s, const=0.5)
     gam = inputs.kernel_weights(s)
@@ -335,6 +341,24 @@ def c1_leg(torch, fdwt, inputs, reps=20):
         ts.append(time.perf_counter() - t0)
     gpu_ms = 1e3 * float(np.median(ts))
     net.close()
+    return {"workload": "p=2 m=10 (N=1024) s=4, product family a_j=0.5, kernel alpha=2 gamma_j=j^-2; step = "
+                        "forward, inverse, spline coefficients, eff_dim",
+            "gpu_step_ms": gpu_ms, "gpu_d_trc_d_sup": [res["d_trc"], res["d_sup"]]}
+
+
+def c1_oracle(c1_gpu_ms):
+    """The oracle's full definition of the C1 step's outputs on the host
+    (direct O(N^2) sums of the forward and inverse transforms, dense Gram
+    solve, direct double sums of the variances), on one thread and on all
+    threads, beside the GPU's C1 step time when the c1 leg ran."""
+    from threadpoolctl import threadpool_limits
+    from oracle import anova, families, kernel, net as onet, walsh
+    from paper_0808_0487_amd import inputs
+    p, m, s = C1_SHAPE
+    N = p ** m
+    C = inputs.upper_triangular_generators(p, m, s, seed=1)
+    a = inputs.family_params("product", s, const=0.5)
+    gam = inputs.kernel_weights(s)
 
     def oracle_step():
         X = onet.net_int(p, m, C)
@@ -345,16 +369,15 @@ def c1_leg(torch, fdwt, inputs, reps=20):
         trc, sup = anova.variances_direct(p, m, 2.0, gam, X, co)
         return anova.effective_dims(trc, sup)
 
-    out = {"workload": "p=2 m=10 (N=1024) s=4, product family a_j=0.5, kernel alpha=2 gamma_j=j^-2; step = "
-                       "forward, inverse, spline coefficients, eff_dim",
-           "gpu_step_ms": gpu_ms, "gpu_d_trc_d_sup": [res["d_trc"], res["d_sup"]]}
+    out = {"workload": "the c1 leg's step (p=2 m=10 s=4)"}
     for label, threads in (("oracle_1_thread", 1), ("oracle_all_threads", None)):
         with threadpool_limits(limits=threads):
             t0 = time.perf_counter()
             dims = oracle_step()
             out[label + "_s"] = time.perf_counter() - t0
     out["oracle_d_trc_d_sup"] = [int(dims[0]), int(dims[1])]
-    out["oracle_over_gpu_1_thread"] = out["oracle_1_thread_s"] / (gpu_ms * 1e-3)
+    if c1_gpu_ms:
+        out["oracle_over_gpu_1_thread"] = out["oracle_1_thread_s"] / (c1_gpu_ms * 1e-3)
     return out
 
 
@@ -899,10 +922,8 @@ def main():
                                      args.serve_lanes, args.serve_sustained)
         progress("serving done")
     if not args.no_cpu:
-        out["cpu_baseline"] = cpu_baseline(p, m, s, C)
+        out["cpu_baseline"] = cpu_baseline(p, m, s, C, out.get("c1", {}).get("gpu_step_ms"))
         progress("cpu baseline done")
-        out["cpu_fast_reference"] = cpu_fast_reference(p, m, s, C)
-        progress("fast CPU reference done")
     print(json.dumps(out), flush=True)
     net.close()
 

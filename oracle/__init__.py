@@ -2,8 +2,7 @@
 
 TEST INFRASTRUCTURE ONLY.  Nothing in the product path may import, call or
 execute anything in this package: only ``tests/``, ``__graft_entry__.smoke()``
-and the CPU legs of ``bench.py`` (``cpu_baseline``, ``cpu_fast_reference``,
-``c1``) use it.  It shares no code with the
+and the ``cpu_baseline`` leg of ``bench.py`` use it.  It shares no code with the
 HIP library (no headers, tables, helpers or generated constants) and imports
 nothing from it.
 
