@@ -120,6 +120,100 @@ __global__ void __launch_bounds__(kChunk) k_kernel_cols(NetArgs na, const double
   }
 }
 
+// p = 2, N a multiple of 512: the same columns as k_kernel_cols with two
+// adjacent points per thread, stored 16 bytes per lane (a store-bound
+// kernel: about 4% faster than one point per thread at 2^24 points, s = 20).
+// A 512-point group is two 256-point halves, each with its own XOR of the
+// upper-byte tables.
+template <int SMAX>
+__global__ void __launch_bounds__(kChunk) k_kernel_cols2(NetArgs na, const double* __restrict__ tk,
+                                                         const double* __restrict__ tr, int c0, int c1,
+                                                         double* __restrict__ out) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  const int s = na.s;
+  double* ltk = reinterpret_cast<double*>(smem);
+  double* ltr = ltk + s * kTab;
+  uint32_t* lt0 = reinterpret_cast<uint32_t*>(ltr + s * kTab);  // [s][256]
+  uint32_t* lu = lt0 + s * 256;                                  // [2][s]
+  for (int i = threadIdx.x; i < s * kTab; i += blockDim.x) {
+    ltk[i] = tk[i];
+    ltr[i] = tr[i];
+  }
+  P2Coords pc{na.xtab, na.nbytes, s, lt0, lu};
+  pc.stage_tables();
+  const bool need_r = c1 > 1;
+  const bool need_q = c1 > s + 1;
+  const int64_t N = na.N;
+  const int m = na.m;
+  const int half = threadIdx.x >> 7;
+  const int lo = (2 * threadIdx.x) & 255;
+  for (int64_t base = (int64_t)blockIdx.x * 512; base < N; base += (int64_t)gridDim.x * 512) {
+    __syncthreads();
+    for (int i = threadIdx.x; i < 2 * s; i += blockDim.x) {
+      const int h = i / s, j = i - h * s;
+      const int64_t b = base + 256 * h;
+      const uint32_t* tj = na.xtab + (int64_t)j * na.nbytes * 256;
+      uint32_t v = 0;
+      for (int bb = 1; bb < na.nbytes; ++bb) v ^= tj[bb * 256 + (int)((b >> (8 * bb)) & 255)];
+      lu[h * s + j] = v;
+    }
+    __syncthreads();
+    const int64_t n = base + 2 * threadIdx.x;
+    double K0 = 1.0, K1 = 1.0, u0 = 0.0, u1 = 0.0;
+    double e0[SMAX + 1], e1[SMAX + 1];
+#pragma unroll
+    for (int i = 0; i <= SMAX; ++i) e0[i] = e1[i] = i == 0 ? 1.0 : 0.0;
+#pragma unroll
+    for (int q = 0; q < SMAX / 4; ++q) {
+      const int je = (q == SMAX / 4 - 1 || 4 * q + 4 > s) ? s : 4 * q + 4;
+      for (int j = 4 * q; j < je; ++j) {
+        const uint32_t uj = lu[half * s + j];
+        const int t0 = lead_p2(lt0[j * 256 + lo] ^ uj, m);
+        const int t1 = lead_p2(lt0[j * 256 + lo + 1] ^ uj, m);
+        K0 *= ltk[j * kTab + t0];
+        K1 *= ltk[j * kTab + t1];
+        if (need_r) {
+          const double r0 = ltr[j * kTab + t0], r1 = ltr[j * kTab + t1];
+          u0 = u0 + r0 + u0 * r0;
+          u1 = u1 + r1 + u1 * r1;
+          const int c = 1 + j;
+          if (c >= c0 && c < c1) {
+            double2 w;
+            w.x = u0;
+            w.y = u1;
+            *reinterpret_cast<double2*>(out + (int64_t)(c - c0) * N + n) = w;
+          }
+          if (need_q) {
+#pragma unroll
+            for (int i = 4 * q + 4; i >= 1; --i) {
+              e0[i] += r0 * e0[i - 1];
+              e1[i] += r1 * e1[i - 1];
+            }
+          }
+        }
+      }
+    }
+    if (c0 == 0) {
+      double2 w;
+      w.x = K0;
+      w.y = K1;
+      *reinterpret_cast<double2*>(out + n) = w;
+    }
+    if (need_q) {
+#pragma unroll
+      for (int j = 1; j <= SMAX; ++j) {
+        const int c = s + j;
+        if (j <= s && c >= c0 && c < c1) {
+          double2 w;
+          w.x = e0[j];
+          w.y = e1[j];
+          *reinterpret_cast<double2*>(out + (int64_t)(c - c0) * N + n) = w;
+        }
+      }
+    }
+  }
+}
+
 // ---------------------------------------------------- spectral division
 template <int P>
 __global__ void __launch_bounds__(256) k_spec_div(const void* __restrict__ ft, const void* __restrict__ gk,
@@ -459,9 +553,18 @@ static int kcols_launch(const Net& net, const double* tk, const double* tr, int 
   const size_t lds = (size_t)2 * net.s * kTab * 8 +
                      (P == 2 ? (size_t)net.s * 257 * 4 : OddCoords<P == 2 ? 3 : P>::lds_bytes(net.s));
   if (int rc = allow_lds((const void*)k_kernel_cols<P, SMAX>, lds)) return rc;
-  const unsigned grid = (unsigned)std::min<int64_t>((net.N + kChunk - 1) / kChunk, 2048);
   NetArgs na = net_args(net);
   void* args[] = {(void*)&na, (void*)&tk, (void*)&tr, (void*)&c0, (void*)&c1, (void*)&out};
+  if constexpr (P == 2) {
+    if (net.N % 512 == 0) {
+      const size_t lds2 = (size_t)2 * net.s * kTab * 8 + (size_t)net.s * 258 * 4;
+      if (int rc = allow_lds((const void*)k_kernel_cols2<SMAX>, lds2)) return rc;
+      const unsigned grid2 = (unsigned)std::min<int64_t>(net.N / 512, 4096);
+      return launch_timed((const void*)k_kernel_cols2<SMAX>, dim3(grid2), dim3(kChunk), args, lds2, st,
+                          FDWT_TC_KCOLS, 8.0 * (double)net.N * (c1 - c0));
+    }
+  }
+  const unsigned grid = (unsigned)std::min<int64_t>((net.N + kChunk - 1) / kChunk, 2048);
   return launch_timed((const void*)k_kernel_cols<P, SMAX>, dim3(grid), dim3(kChunk), args, lds, st, FDWT_TC_KCOLS,
                       8.0 * (double)net.N * (c1 - c0));
 }
