@@ -28,6 +28,7 @@
 #include <cmath>
 #include <cstdlib>
 #include <cstring>
+#include <limits>
 
 namespace fdwt {
 
@@ -332,8 +333,9 @@ __device__ __forceinline__ int ffbh_raw(uint32_t z) {
 //          the high 32 bits of the strings; a lane whose high words agree for
 //          some (point, coordinate) of a group of 4 points (the first 15 or 10
 //          digits equal, rare) redoes that group exactly, taking c from the
-//          low words there.  A running minimum of the high-word XORs detects
-//          it without a branch in the loop.
+//          low words there.  Entry 0 (c = -1: high words equal) is a NaN,
+//          which the group's products keep, so one test per point after the
+//          coordinate loop detects it without work in the loop.
 constexpr int kTabE = 68;  // table entries per coordinate (p odd uses 0..65)
 
 template <int P, int SMAX>
@@ -391,22 +393,23 @@ __global__ void __launch_bounds__(256) k_spline_eval(const void* __restrict__ Xp
       float pr[V];
 #pragma unroll
       for (int u = 0; u < V; ++u) pr[u] = 1.0f;
-      uint32_t zmin = 0xffffffffu;
 #pragma unroll
       for (int j = 0; j < SMAX; ++j) {
         if (j < s) {
           const uint4 xv = *reinterpret_cast<const uint4*>(lxh + j * kNS + k);
           const uint32_t xs[V] = {xv.x, xv.y, xv.z, xv.w};
 #pragma unroll
-          for (int u = 0; u < V; ++u) {
-            const uint32_t zh = qh[j] ^ xs[u];
-            if constexpr (ODD) zmin = min(zmin, zh);
-            pr[u] *= factor(j, ffbh_raw(zh));
-          }
+          for (int u = 0; u < V; ++u) pr[u] *= factor(j, ffbh_raw(qh[j] ^ xs[u]));
         }
       }
       if constexpr (ODD) {
-        if (zmin == 0u) {
+        // Equal high words (leading-zero count -1) pick a NaN table entry,
+        // which the product keeps: one test per point instead of one per
+        // coordinate finds the groups that need the low words.
+        bool rare = false;
+#pragma unroll
+        for (int u = 0; u < V; ++u) rare |= __builtin_isnan(pr[u]);
+        if (rare) {
           // Rare: some high words agree; redo the group from the full strings.
           // The empty asm keeps the query loads on this path.
           int64_t qo = qq;
@@ -827,7 +830,8 @@ int run_spline_eval(Net& net, Scratch& sc, const fdwt_kernel* kern, const void* 
   // Factor 1 + gamma_j K'(t+1) of first differing digit t < D, and 1 + gamma_j
   // when all D digits agree, at entry c + 1 of the leading-zero count c that
   // k_spline_eval computes (p = 2: c = t, or -1 when equal; p odd: c = Bt+1..Bt+B,
-  // or 64 when equal).
+  // or 64 when equal).  For p odd, entry 0 (high words equal, c = -1) is a
+  // NaN: it marks the points whose low words must be read.
   const int B = p == 3 ? kStrBits<3> : kStrBits<5>;  // digit-string field width (coords.h)
   std::vector<float> htl((size_t)s * kTabE, 1.0f);
   for (int j = 0; j < s; ++j) {
@@ -839,6 +843,7 @@ int run_spline_eval(Net& net, Scratch& sc, const fdwt_kernel* kern, const void* 
       else for (int l = B * t + 1; l <= B * t + B; ++l) row[l + 1] = v;
     }
     row[p == 2 ? 0 : 65] = eq;
+    if (p != 2) row[0] = std::numeric_limits<float>::quiet_NaN();
   }
   rc = upload(sc, htl.data(), htl.size() * 4, w.tl, st);
   if (rc) return rc;
