@@ -294,7 +294,13 @@ __global__ void __launch_bounds__(kSumThreads) k_sum_rows(const double* __restri
 }
 
 // --------------------------------------------------------- evaluation
-constexpr int kNS = 64;  // points staged per step
+// Points staged in LDS per step of the evaluation: 256 for up to 16
+// coordinates (fewer barriers and staging rounds per evaluation), 64 above
+// (the staged strings of many coordinates would otherwise limit how many
+// workgroups share a CU).  Point chunks are rounded to kNSMax.
+constexpr int kNSMax = 256;
+template <int SMAX>
+constexpr int eval_ns() { return SMAX <= 16 ? 256 : 64; }
 
 // Query digit strings, p odd: the D digits of q[j][i] (most significant
 // first) in the layout of eval_string_odd.
@@ -345,6 +351,8 @@ __global__ void __launch_bounds__(256) k_spline_eval(const void* __restrict__ Xp
                                                      df* __restrict__ partial) {
   constexpr bool ODD = P != 2;
   constexpr int V = 4;  // points per LDS read
+  constexpr int kNS = eval_ns<SMAX>();
+  constexpr int kSub = 64;  // points per float partial sum (then double-float)
   extern __shared__ __align__(16) unsigned char smem[];
   float* lt = reinterpret_cast<float*>(smem);                              // [s][kTabE]
   uint32_t* lxh = reinterpret_cast<uint32_t*>(lt + (size_t)s * kTabE);     // [s][kNS] (p odd: high words)
@@ -388,55 +396,57 @@ __global__ void __launch_bounds__(256) k_spline_eval(const void* __restrict__ Xp
     }
     for (int k = threadIdx.x; k < kNS; k += blockDim.x) lc[k] = (n0 + k < nend) ? c[n0 + k] : 0.0f;
     __syncthreads();
-    float sub = 0.0f;
-    for (int k = 0; k < kNS; k += V) {
-      float pr[V];
-#pragma unroll
-      for (int u = 0; u < V; ++u) pr[u] = 1.0f;
-#pragma unroll
-      for (int j = 0; j < SMAX; ++j) {
-        if (j < s) {
-          const uint4 xv = *reinterpret_cast<const uint4*>(lxh + j * kNS + k);
-          const uint32_t xs[V] = {xv.x, xv.y, xv.z, xv.w};
-#pragma unroll
-          for (int u = 0; u < V; ++u) pr[u] *= factor(j, ffbh_raw(qh[j] ^ xs[u]));
+    for (int kb = 0; kb < kNS; kb += kSub) {  // float partial sums over kSub points
+      float sub = 0.0f;
+      for (int k = kb; k < kb + kSub; k += V) {
+        float pr[V];
+  #pragma unroll
+        for (int u = 0; u < V; ++u) pr[u] = 1.0f;
+  #pragma unroll
+        for (int j = 0; j < SMAX; ++j) {
+          if (j < s) {
+            const uint4 xv = *reinterpret_cast<const uint4*>(lxh + j * kNS + k);
+            const uint32_t xs[V] = {xv.x, xv.y, xv.z, xv.w};
+  #pragma unroll
+            for (int u = 0; u < V; ++u) pr[u] *= factor(j, ffbh_raw(qh[j] ^ xs[u]));
+          }
         }
-      }
-      if constexpr (ODD) {
-        // Equal high words (leading-zero count -1) pick a NaN table entry,
-        // which the product keeps: one test per point instead of one per
-        // coordinate finds the groups that need the low words.
-        bool rare = false;
-#pragma unroll
-        for (int u = 0; u < V; ++u) rare |= __builtin_isnan(pr[u]);
-        if (rare) {
-          // Rare: some high words agree; redo the group from the full strings.
-          // The empty asm keeps the query loads on this path.
-          int64_t qo = qq;
-          asm volatile("" : "+v"(qo));
-#pragma unroll
-          for (int u = 0; u < V; ++u) pr[u] = 1.0f;
-          for (int j = 0; j < s; ++j) {
-            const uint64_t qs = ((const uint64_t*)qv + (int64_t)j * nq)[qo];
-            const uint32_t qhi = (uint32_t)(qs >> 32), qlo = (uint32_t)qs;
-            for (int u = 0; u < V; ++u) {
-              const uint32_t zh = qhi ^ lxh[j * kNS + k + u];
-              int cl;
-              if (zh) {
-                cl = ffbh_raw(zh);
-              } else {
-                const uint32_t zl = qlo ^ lxl[j * kNS + k + u];
-                cl = zl ? 32 + ffbh_raw(zl) : 64;
+        if constexpr (ODD) {
+          // Equal high words (leading-zero count -1) pick a NaN table entry,
+          // which the product keeps: one test per point instead of one per
+          // coordinate finds the groups that need the low words.
+          bool rare = false;
+  #pragma unroll
+          for (int u = 0; u < V; ++u) rare |= __builtin_isnan(pr[u]);
+          if (rare) {
+            // Rare: some high words agree; redo the group from the full strings.
+            // The empty asm keeps the query loads on this path.
+            int64_t qo = qq;
+            asm volatile("" : "+v"(qo));
+  #pragma unroll
+            for (int u = 0; u < V; ++u) pr[u] = 1.0f;
+            for (int j = 0; j < s; ++j) {
+              const uint64_t qs = ((const uint64_t*)qv + (int64_t)j * nq)[qo];
+              const uint32_t qhi = (uint32_t)(qs >> 32), qlo = (uint32_t)qs;
+              for (int u = 0; u < V; ++u) {
+                const uint32_t zh = qhi ^ lxh[j * kNS + k + u];
+                int cl;
+                if (zh) {
+                  cl = ffbh_raw(zh);
+                } else {
+                  const uint32_t zl = qlo ^ lxl[j * kNS + k + u];
+                  cl = zl ? 32 + ffbh_raw(zl) : 64;
+                }
+                pr[u] *= factor(j, cl);
               }
-              pr[u] *= factor(j, cl);
             }
           }
         }
+  #pragma unroll
+        for (int u = 0; u < V; ++u) sub += lc[k + u] * pr[u];
       }
-#pragma unroll
-      for (int u = 0; u < V; ++u) sub += lc[k + u] * pr[u];
+      acc = add(acc, df{sub, 0.0f});
     }
-    acc = add(acc, df{sub, 0.0f});
   }
   if (qi < nq) partial[(int64_t)blockIdx.y * nq + qi] = acc;
 }
@@ -755,12 +765,16 @@ int run_spline_coef(Net& net, Scratch& sc, const fdwt_kernel* kern, const void* 
 // ----------------------------------------------------------- evaluation
 template <int P>
 static int launch_eval(Net& net, const void* Xp, const float* c, int64_t nq, const void* qv, const float* tl,
-                       df* partial, int gy, int64_t ppc, size_t lds, hipStream_t st) {
+                       df* partial, int gy, int64_t ppc, hipStream_t st) {
   const dim3 grid((unsigned)((nq + 255) / 256), (unsigned)gy);
   const int s = net.s;
+  const size_t xb = P == 2 ? 4 : 8;  // staged bytes per point and coordinate
+  // Tables, then the staged points (p odd: high and low words of the strings).
 #define FDWT_EVAL(SM)                                                                              \
   {                                                                                                \
     auto fn = k_spline_eval<P, SM>;                                                                \
+    constexpr size_t ns_ = eval_ns<SM>();                                                          \
+    const size_t lds = (size_t)s * kTabE * 4 + (size_t)s * ns_ * xb + ns_ * 4;                     \
     if (int rc_ = allow_lds((const void*)fn, lds)) return rc_;                                     \
     hipLaunchKernelGGL(fn, grid, dim3(256), lds, st, Xp, c, net.N, s, qv, nq, tl, ppc, partial);   \
   }
@@ -782,9 +796,9 @@ size_t packed_bytes(const Net& net) { return (size_t)net.s * net.N * (net.p == 2
 // alongside what it runs.
 static void eval_grid(int64_t N, int64_t nq, int* gy_out, int64_t* ppc_out) {
   const int64_t qb = (nq + 255) / 256;
-  int gy = (int)std::max<int64_t>(1, std::min<int64_t>((2048 + qb - 1) / qb, (N + kNS - 1) / kNS));
+  int gy = (int)std::max<int64_t>(1, std::min<int64_t>((2048 + qb - 1) / qb, (N + kNSMax - 1) / kNSMax));
   int64_t ppc = (N + gy - 1) / gy;
-  ppc = (ppc + kNS - 1) / kNS * kNS;
+  ppc = (ppc + kNSMax - 1) / kNSMax * kNSMax;
   gy = (int)((N + ppc - 1) / ppc);
   *gy_out = gy;
   *ppc_out = ppc;
@@ -818,7 +832,6 @@ int run_spline_eval(Net& net, Scratch& sc, const fdwt_kernel* kern, const void* 
   const int p = net.p, s = net.s, m = net.m;
   const int D = query_depth(p);
   const int64_t N = net.N;
-  const size_t xb = (p == 2) ? 4 : 8;
   int gy;
   int64_t ppc;
   eval_grid(N, nq, &gy, &ppc);
@@ -861,11 +874,9 @@ int run_spline_eval(Net& net, Scratch& sc, const fdwt_kernel* kern, const void* 
     FDWT_HIP(hipGetLastError());
     qv = w.qs;
   }
-  // Tables, then the staged points (p odd: high and low words of the strings).
-  const size_t lds = (size_t)s * kTabE * 4 + (size_t)s * kNS * xb + kNS * 4;
   hipEvent_t tb = timed_begin(st);
-  if (p == 2) rc = launch_eval<2>(net, Xp, c, nq, qv, w.tl, w.partial, gy, ppc, lds, st);
-  else rc = launch_eval<3>(net, Xp, c, nq, qv, w.tl, w.partial, gy, ppc, lds, st);  // any odd p: digit strings
+  if (p == 2) rc = launch_eval<2>(net, Xp, c, nq, qv, w.tl, w.partial, gy, ppc, st);
+  else rc = launch_eval<3>(net, Xp, c, nq, qv, w.tl, w.partial, gy, ppc, st);  // any odd p: digit strings
   if (rc) return rc;
   timed_end(tb, st, FDWT_TC_EVAL, (double)nq * (double)N * s);
   hipLaunchKernelGGL(k_eval_finish, dim3(grid1(nq)), dim3(256), 0, st, w.partial, gy, nq, sf);
