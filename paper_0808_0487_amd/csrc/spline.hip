@@ -328,7 +328,9 @@ __device__ __forceinline__ int ffbh_raw(uint32_t z) {
 
 // Sf at queries as partial sums over point chunks (blockIdx.y): each thread
 // takes one query; the points of a chunk are staged in LDS kNS at a time and
-// read as 16-byte broadcasts (4 points).  The factor 1 + gamma_j K'(.) of
+// read as 16-byte broadcasts, 8 points a group (two reads per coordinate:
+// with 4 points a group the table reads' latency was not hidden, 8 reach the
+// VALU issue limit).  The factor 1 + gamma_j K'(.) of
 // coordinate j is entry (c + 1) of a per-coordinate table in LDS (kTabE
 // floats a row, copied from ftab), where c is the leading-zero count of the
 // XOR of the query's and the point's digit strings (one v_add_lshl_u32 makes
@@ -337,7 +339,7 @@ __device__ __forceinline__ int ffbh_raw(uint32_t z) {
 //   p odd: c = Bt + 1..Bt + B for first differing digit t (B = 2 for p = 3,
 //          3 otherwise: coords.h), 64 when all D digits agree.  c comes from
 //          the high 32 bits of the strings; a lane whose high words agree for
-//          some (point, coordinate) of a group of 4 points (the first 15 or 10
+//          some (point, coordinate) of a group of 8 points (the first 15 or 10
 //          digits equal, rare) redoes that group exactly, taking c from the
 //          low words there.  Entry 0 (c = -1: high words equal) is a NaN,
 //          which the group's products keep, so one test per point after the
@@ -350,7 +352,7 @@ __global__ void __launch_bounds__(256) k_spline_eval(const void* __restrict__ Xp
                                                      const float* __restrict__ ftab, int64_t ppc,
                                                      df* __restrict__ partial) {
   constexpr bool ODD = P != 2;
-  constexpr int V = 4;  // points per LDS read
+  constexpr int V = 8;  // points per group (two 16-byte LDS reads per coordinate)
   constexpr int kNS = eval_ns<SMAX>();
   constexpr int kSub = 64;  // points per float partial sum (then double-float)
   extern __shared__ __align__(16) unsigned char smem[];
@@ -406,7 +408,8 @@ __global__ void __launch_bounds__(256) k_spline_eval(const void* __restrict__ Xp
         for (int j = 0; j < SMAX; ++j) {
           if (j < s) {
             const uint4 xv = *reinterpret_cast<const uint4*>(lxh + j * kNS + k);
-            const uint32_t xs[V] = {xv.x, xv.y, xv.z, xv.w};
+            const uint4 xw = *reinterpret_cast<const uint4*>(lxh + j * kNS + k + 4);
+            const uint32_t xs[V] = {xv.x, xv.y, xv.z, xv.w, xw.x, xw.y, xw.z, xw.w};
   #pragma unroll
             for (int u = 0; u < V; ++u) pr[u] *= factor(j, ffbh_raw(qh[j] ^ xs[u]));
           }
