@@ -402,15 +402,15 @@ __global__ void __launch_bounds__(256) k_spline_eval(const void* __restrict__ Xp
       float sub = 0.0f;
       for (int k = kb; k < kb + kSub; k += V) {
         float pr[V];
-  #pragma unroll
+#pragma unroll
         for (int u = 0; u < V; ++u) pr[u] = 1.0f;
-  #pragma unroll
+#pragma unroll
         for (int j = 0; j < SMAX; ++j) {
           if (j < s) {
             const uint4 xv = *reinterpret_cast<const uint4*>(lxh + j * kNS + k);
             const uint4 xw = *reinterpret_cast<const uint4*>(lxh + j * kNS + k + 4);
             const uint32_t xs[V] = {xv.x, xv.y, xv.z, xv.w, xw.x, xw.y, xw.z, xw.w};
-  #pragma unroll
+#pragma unroll
             for (int u = 0; u < V; ++u) pr[u] *= factor(j, ffbh_raw(qh[j] ^ xs[u]));
           }
         }
@@ -419,14 +419,14 @@ __global__ void __launch_bounds__(256) k_spline_eval(const void* __restrict__ Xp
           // which the product keeps: one test per point instead of one per
           // coordinate finds the groups that need the low words.
           bool rare = false;
-  #pragma unroll
+#pragma unroll
           for (int u = 0; u < V; ++u) rare |= __builtin_isnan(pr[u]);
           if (rare) {
             // Rare: some high words agree; redo the group from the full strings.
             // The empty asm keeps the query loads on this path.
             int64_t qo = qq;
             asm volatile("" : "+v"(qo));
-  #pragma unroll
+#pragma unroll
             for (int u = 0; u < V; ++u) pr[u] = 1.0f;
             for (int j = 0; j < s; ++j) {
               const uint64_t qs = ((const uint64_t*)qv + (int64_t)j * nq)[qo];
@@ -445,7 +445,7 @@ __global__ void __launch_bounds__(256) k_spline_eval(const void* __restrict__ Xp
             }
           }
         }
-  #pragma unroll
+#pragma unroll
         for (int u = 0; u < V; ++u) sub += lc[k + u] * pr[u];
       }
       acc = add(acc, df{sub, 0.0f});
