@@ -217,6 +217,14 @@ int o2_fwt(int p, int m, int64_t ncols, double* re, double* im, int inverse) {
   return 0;
 }
 
+/* 1 when every entry of a[0..n) lies in [0, lim). */
+static int in_range(const int64_t* a, int64_t n, int64_t lim) {
+  int ok = 1;
+#pragma omp parallel for schedule(static) reduction(& : ok)
+  for (int64_t i = 0; i < n; ++i) ok &= a[i] >= 0 && a[i] < lim;
+  return ok;
+}
+
 /* --------------------------------------------------------- kernel data */
 /* Position (1-based, most significant first) of the first non-zero base-p
  * digit of the D-digit integer z; 0 for z = 0.  For p = 2 the position of
@@ -273,6 +281,7 @@ static int tables(int p, int m, int s, double alpha, const double* gamma, double
 int o2_kernel_cols(int p, int m, int s, double alpha, const double* gamma, const int64_t* X, int64_t N, double* K,
                    double* U, double* Q) {
   if (!valid_pm(p, m) || s < 1 || s > 256 || N < 0 || !(alpha > 1.0)) return -1;
+  if (!in_range(X, (int64_t)s * N, ipow64(p, m))) return -1;
   double *kt, *rt;
   if (tables(p, m, s, alpha, gamma, &kt, &rt)) return -2;
 #pragma omp parallel for schedule(static)
@@ -308,6 +317,7 @@ int o2_variances(int p, int m, int s, double alpha, const double* gamma, const i
                  const double* ft_im, double* var_trc, double* var_sup) {
   if (!valid_pm(p, m) || s < 1 || s > 256 || !(alpha > 1.0) || (!ft_im && p != 2)) return -1;
   const int64_t N = ipow64(p, m);
+  if (!in_range(X, (int64_t)s * N, N)) return -1;
   const int cplx = p != 2;
   double* K = (double*)calloc((size_t)N, sizeof(double));
   double* Q = (double*)calloc((size_t)N * s, sizeof(double));
@@ -376,6 +386,7 @@ int o2_spline_coef(int p, int m, int s, double alpha, const double* gamma, const
                    const double* ft_im, double* c) {
   if (!valid_pm(p, m) || s < 1 || s > 256 || !(alpha > 1.0) || (!ft_im && p != 2)) return -1;
   const int64_t N = ipow64(p, m);
+  if (!in_range(X, (int64_t)s * N, N)) return -1;
   const int cplx = p != 2;
   double* K = (double*)calloc((size_t)N, sizeof(double));
   double* Ki = cplx ? (double*)calloc((size_t)N, sizeof(double)) : NULL;
@@ -409,6 +420,7 @@ int o2_spline_eval(int p, int m, int s, double alpha, const double* gamma, const
   if (!valid_pm(p, m) || s < 1 || nq < 0 || D < m || !(alpha > 1.0)) return -1;
   if (D * log((double)p) / log(2.0) > 62.0) return -1;
   const int64_t N = ipow64(p, m), lift = ipow64(p, D - m);
+  if (!in_range(X, (int64_t)s * N, N) || !in_range(Q, (int64_t)s * nq, ipow64(p, D))) return -1;
   double *kt, *rt;
   if (tables(p, D, s, alpha, gamma, &kt, &rt)) return -2;
   int64_t pw[64];

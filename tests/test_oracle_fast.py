@@ -151,3 +151,7 @@ def test_invalid_arguments_raise():
         fast.kernel_cols(2, 3, 1.0, [1.0, 1.0], X)  # alpha must exceed 1
     with pytest.raises(ValueError):
         fast.fwt(3, 2, np.zeros(8))  # wrong length
+    with pytest.raises(ValueError):
+        fast.kernel_cols(2, 3, 2.0, [1.0, 1.0], X + 8)  # coordinates beyond p^m
+    with pytest.raises(ValueError):
+        fast.spline_eval(2, 3, 2.0, [1.0, 1.0], X, np.zeros(8), np.full((2, 1), 1 << 10), 10)  # query beyond p^D
