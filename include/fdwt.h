@@ -236,7 +236,8 @@ int fdwt_walsh_interp_depth(const fdwt_net* net, const fdwt_kernel* kern, const 
  *   var_sup[d] = sigma^2_sup(Sf; d) = sum_{j<=d} p^2m sum_h |c~(h)|^2 Q~_j(h),
  *                Q_j = j-th elementary symmetric polynomial of the
  *                gamma_l^2 R'(x_l, 0),
- * for d = 0..s (index 0 holds 0), var_total = var_trc[s] = sigma^2(Sf)
+ * for d = 0..s (index 0 holds 0; var_sup[s] = var_trc[s], the two being
+ * sigma^2(Sf) by definition, so Q_s is never transformed), var_total = var_trc[s] = sigma^2(Sf)
  * (Eq. (varSf), with the h = 0 bin included), var_total_h0 = the h = 0
  * bin's share of it, var_qmc = sum_{h != 0} |ft(h)|^2 (the sample variance
  * of the data), d_trc / d_sup = smallest d with var_*[d] >= 0.99 var_total.

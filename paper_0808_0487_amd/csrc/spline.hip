@@ -918,8 +918,13 @@ struct EffWs {
   double* qmc_partial;
   double* res;
 };
+// Columns transformed for the variances: U_1..U_s and Q_1..Q_{s-1}.  Q_s is
+// not needed: sigma^2_sup(s) = sigma^2_trc(s) = sigma^2(Sf) (Section 4), so
+// its increment is the total minus sigma^2_sup(s - 1).
+static int effdim_cols(int s) { return 2 * s - 1; }
+
 static void eff_layout(const Net& net, bool have_gk, int ch, Carve& cv, EffWs& w) {
-  const int ncols = 2 * net.s;
+  const int ncols = effdim_cols(net.s);
   const size_t wb = (net.p == 2) ? sizeof(double) : sizeof(double2);
   const int64_t parts = fwt_reduce_parts(net.p, net.m, wb);
   w.gk = have_gk ? nullptr : cv.take(spectrum_bytes(net));
@@ -940,16 +945,17 @@ size_t eff_dim_ws_bytes(const Net& net, bool have_spectrum, int chunk) {
 }
 
 // Enqueues the whole variance computation on st; the 2s + 2 result doubles
-// (sigma^2_trc(d) for d = 1..s, the superposition increments for j = 1..s,
-// sigma^2_QMC and the h = 0 share) land in res_host (pinned) when st reaches
-// this point (when res_host is given; *res_dev receives their device copy).
+// (sigma^2_trc(d) for d = 1..s, the superposition increments for j = 1..s-1,
+// an unused slot, sigma^2_QMC and the h = 0 share) land in res_host (pinned)
+// when st reaches this point (when res_host is given; *res_dev receives their
+// device copy).
 // gk_given: a cached spectrum, or nullptr to compute it here.
 int eff_dim_enqueue(Net& net, Scratch& sc, const fdwt_kernel* kern, const void* gk_given, const void* ft, int ch,
                     double* res_host, const double** res_dev, hipStream_t st) {
   const int p = net.p, s = net.s;
   const int64_t N = net.N;
   const size_t wb = (p == 2) ? sizeof(double) : sizeof(double2);
-  const int ncols = 2 * s;  // U_1..U_s, Q_1..Q_s (generator columns 1..2s)
+  const int ncols = effdim_cols(s);  // U_1..U_s, Q_1..Q_{s-1} (generator columns 1..2s-1)
   const int64_t parts = fwt_reduce_parts(p, net.m, wb);  // partial sums per column
   int rc = ensure_ws(sc, eff_dim_ws_bytes(net, gk_given != nullptr, ch), st);
   if (rc) return rc;
@@ -965,7 +971,7 @@ int eff_dim_enqueue(Net& net, Scratch& sc, const fdwt_kernel* kern, const void* 
     if (rc) return rc;
     GK = w.gk;
   }
-  double* h0 = w.res + ncols + 1;  // h = 0 share of the total
+  double* h0 = w.res + 2 * s + 1;  // h = 0 share of the total
   const double pm = (double)N;
   // p = 2 two-pass plans keep the intermediate columns in the blocked layout
   // (the grouped-sum pass then reads contiguous tiles and weights).
@@ -1002,7 +1008,7 @@ int eff_dim_enqueue(Net& net, Scratch& sc, const fdwt_kernel* kern, const void* 
     if (rc) return rc;
   }
   hipLaunchKernelGGL(k_sum_rows, dim3(ncols), dim3(kSumThreads), 0, st, w.partial, (int)parts, w.res);
-  hipLaunchKernelGGL(k_sum_rows, dim3(1), dim3(kSumThreads), 0, st, w.qmc_partial, kRedBlocks, w.res + ncols);
+  hipLaunchKernelGGL(k_sum_rows, dim3(1), dim3(kSumThreads), 0, st, w.qmc_partial, kRedBlocks, w.res + 2 * s);
   FDWT_HIP(hipGetLastError());
   if (res_dev) *res_dev = w.res;
   if (res_host) FDWT_HIP(hipMemcpyAsync(res_host, w.res, eff_dim_res_bytes(net), hipMemcpyDeviceToHost, st));
@@ -1016,7 +1022,7 @@ void eff_dim_finish(int s, const double* r, fdwt_effdim* out) {
   out->var_sup[0] = 0.0;
   for (int d = 1; d <= s; ++d) {
     out->var_trc[d] = r[d - 1];
-    out->var_sup[d] = out->var_sup[d - 1] + r[s + d - 1];
+    out->var_sup[d] = d < s ? out->var_sup[d - 1] + r[s + d - 1] : r[s - 1];  // sup(s) = trc(s)
   }
   out->var_total = out->var_trc[s];
   out->var_qmc = r[2 * s];
