@@ -71,6 +71,47 @@ def test_interpolant_at_queries(p, m, s, seed):
     assert nrel(sf[-len(idx):], fo[idx]) <= 1e-5
 
 
+@pytest.mark.parametrize("m,s,seed", [(16, 1, 43), (16, 2, 44), (17, 3, 45)])
+def test_effdim_few_coordinates_on_the_two_pass_path(m, s, seed):
+    """p = 2 at two-pass sizes with s <= 3 (one, three and five transformed
+    columns) against the fast CPU reference's variances (the dense oracle
+    cannot run at these sizes; the reference is pinned to it in
+    tests/test_oracle_fast.py)."""
+    from oracle import fast
+    p = 2
+    announce("eff_dim few coordinates", p, m, s, seed)
+    C = inputs.upper_triangular_generators(p, m, s, seed)
+    X = fast.net_int(p, m, C)
+    gam = inputs.kernel_weights(s)
+    a = inputs.family_params("product", s, scale=1.0, alpha=2.0)
+    fo = fast.sample("product", p, m, a, X)
+    net = fdwt.Net(p, m, s, C)
+    res = net.eff_dim(fdwt.Kernel(2.0, gam), net.forward(torch.from_numpy(fo).float().cuda()))
+    trc, sup = fast.variances(p, m, 2.0, gam, X, fast.fwt(p, m, fo))
+    assert np.allclose(res["var_trc"], trc, rtol=1e-5, atol=1e-7 * trc[s])
+    assert np.allclose(res["var_sup"], sup, rtol=1e-5, atol=1e-7 * trc[s])
+    assert res["var_sup"][s] == res["var_trc"][s]
+    net.close()
+
+
+@pytest.mark.parametrize("p,m,s,seed", [(2, 9, 3, 51), (3, 5, 3, 52)])
+def test_interpolation_without_queries_and_with_one(p, m, s, seed):
+    """nq = 0: walsh_interp returns the spline coefficients alone (those of
+    spline_coef on the forward transform); nq = 1: the one query's value."""
+    announce("interp nq 0/1", p, m, s, seed)
+    C, X, gam, fo, net, kern, f = setup_case(p, m, s, seed)
+    c0, sf0 = net.walsh_interp(kern, f)
+    ref = net.spline_coef(kern, net.forward(f))
+    assert sf0 is None or sf0.numel() == 0
+    assert nrel(c0.cpu().numpy(), ref.cpu().numpy()) <= 1e-6
+    D = inputs.QUERY_DEPTH[p]
+    Q = inputs.queries(p, s, 1, seed).astype(np.int64)
+    qd = torch.from_numpy(Q.astype(np.uint32).view(np.int32)).cuda()
+    _, sf1 = net.walsh_interp(kern, f, qd)
+    co = kernel.spline_coef_dense(p, m, 2.0, gam, X, fo)
+    assert nrel(sf1.cpu().numpy().astype(np.float64), kernel.spline_eval(p, m, 2.0, gam, X, co, Q, D)) <= 1e-5
+
+
 @pytest.mark.parametrize("p,m,s,qd,seed", [(2, 8, 4, 12, 31), (3, 5, 3, 7, 32), (5, 3, 3, 4, 33),
                                          (2, 7, 3, 5, 34), (3, 4, 2, 20, 35)])
 def test_interpolant_at_queries_of_given_depth(p, m, s, qd, seed):
@@ -97,7 +138,12 @@ def test_interpolant_at_queries_of_given_depth(p, m, s, qd, seed):
         net.walsh_interp(kern, f, qdev, q_depth=D + 1)
 
 
-@pytest.mark.parametrize("p,m,s,seed", CASES + WIDE)
+# one coordinate (the superposition and truncation columns coincide; only U_1
+# is transformed), p = 2 and p = 3 (the two-pass p = 2 path: below)
+DEGENERATE = [(2, 9, 1, 41), (3, 4, 1, 42)]
+
+
+@pytest.mark.parametrize("p,m,s,seed", CASES + WIDE + DEGENERATE)
 def test_effective_dimension_variances(p, m, s, seed):
     """var_trc, var_sup (Section 4) against the direct double sums with the
     oracle's dense-solve coefficients; d_trc, d_sup equal; sample variance."""
